@@ -1,0 +1,168 @@
+/*
+ * jsvd -- block one-sided Jacobi SVD and hyperbolic SVD on AMD Instinct
+ * MI355X (gfx950), FP64.
+ *
+ * The method is the two single-GPU levels of the hierarchically blocked
+ * one-sided Jacobi algorithm (Novakovic, "A hierarchically blocked Jacobi
+ * SVD algorithm for single and multiple graphics processing units"):
+ *   - block level (Section 2, eqs. (2.6)-(2.9); Section 4): the columns of
+ *     G and V are split into block-columns of width w; a parallel pivot
+ *     strategy (Section 3) pairs them; for each pair (p, q) the Gram matrix
+ *     H_pq = [G_p G_q]^T [G_p G_q] is formed and Cholesky-factored, eq.
+ *     (2.7), an inner Jacobi orthogonalises the 2w x 2w factor
+ *     (Section 4.3), and the accumulated transformation V'_pq updates
+ *     [G_p G_q] and [V_p V_q], eq. (2.9);
+ *   - a block sweep repeats until it performs no proper rotation
+ *     (Section 4.5).
+ *
+ * Conventions for every entry point below
+ *   - Matrices are column-major (Section 4), doubles, in device memory
+ *     owned by the caller; leading dimensions are in elements.
+ *   - All work is enqueued on the stream given to jsvd_create /
+ *     jsvd_set_stream.  A call returns after its work has finished (it
+ *     synchronises the stream once per block sweep to read the one
+ *     convergence counter, as the paper's host loop does).
+ *   - The library owns the handle, its strategy tables and a workspace it
+ *     allocates with hipMalloc on first use for a shape and keeps until
+ *     jsvd_destroy.  A handle must not be used by two threads at once.
+ *   - Return codes: JSVD_OK; a negative value -i means argument i is
+ *     invalid (nothing was run); a positive value is a run-time condition,
+ *     after which the outputs are still written.
+ */
+#ifndef JSVD_H
+#define JSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JSVD_OK 0
+#define JSVD_NOT_CONVERGED 1   /* max_sweeps reached with proper rotations left */
+#define JSVD_CHOL_BREAKDOWN 2  /* reserved: zero Cholesky pivots are handled, see jsvd_info */
+#define JSVD_NONFINITE 3       /* a NaN or infinity appeared in the input or the iteration */
+#define JSVD_HIP_ERROR 4       /* a HIP runtime call failed */
+#define JSVD_NO_MEMORY 5       /* workspace allocation failed */
+
+/* Parallel pivot strategies of Section 3, used at both levels. */
+#define JSVD_STRAT_RREV 0 /* reverse of the p-strategy closest to row-cyclic (default) */
+#define JSVD_STRAT_R 1    /* p-strategy closest to row-cyclic, Definition 3.1 */
+#define JSVD_STRAT_CREV 2 /* reverse of the p-strategy closest to column-cyclic */
+#define JSVD_STRAT_C 3    /* p-strategy closest to column-cyclic */
+
+typedef struct jsvd_handle_s *jsvd_handle_t;
+
+typedef struct {
+    int32_t block_w;          /* block-column width w: 0 = choose by size, else 16 or 32 */
+    int32_t strategy;         /* JSVD_STRAT_* (default JSVD_STRAT_RREV) */
+    int32_t max_inner_sweeps; /* M_s of Section 4.3: 1 = block-oriented, default 30 = full block */
+    int32_t max_sweeps;       /* limit on block sweeps (default 30) */
+    int32_t want_v;           /* 1 = accumulate V (default), 0 = do not touch V */
+    int32_t sort;             /* 1 = order the output (default), 0 = column order as computed */
+} jsvd_opts;
+
+typedef struct {
+    int32_t sweeps;            /* block sweeps performed */
+    int32_t converged;         /* 1 if the last sweep had no proper rotation */
+    int64_t rotations;         /* inner rotations performed, all sweeps */
+    int64_t proper_rotations;  /* of which with cos != 1 (Section 4.3, subphase 4) */
+    int64_t inner_sweeps;      /* inner sweeps summed over all pivot block-pairs */
+    int64_t pair_updates;      /* pivot block-pairs whose V'_pq was applied */
+    int32_t chol_breakdowns;   /* non-positive Cholesky pivots met (the block Gram matrix was
+                                  only semidefinite); each makes its row of R zero */
+    int32_t hyp_clamps;        /* |coth 2phi| <= 1 replaced by 5/4 (Section 4.3.1) */
+    int32_t block_w;           /* w actually used */
+    int32_t n_blocks;          /* block-columns in the pivot strategy (with padding) */
+    double seconds;            /* wall time of the call */
+} jsvd_info;
+
+/* Fill *opts with the defaults listed above.  Returns JSVD_OK, or -1 if
+ * opts is NULL. */
+int jsvd_default_opts(jsvd_opts *opts);
+
+/* Create a handle bound to a HIP stream (a hipStream_t; NULL = the null
+ * stream).  The current HIP device at this call is the handle's device.
+ * Returns JSVD_OK, -1 if h is NULL, or JSVD_HIP_ERROR. */
+int jsvd_create(jsvd_handle_t *h, void *hip_stream);
+
+/* Rebind the handle to another stream of the same device. */
+int jsvd_set_stream(jsvd_handle_t h, void *hip_stream);
+
+/* Free the handle and its device workspace. */
+int jsvd_destroy(jsvd_handle_t h);
+
+/*
+ * Ordinary SVD, G = U Sigma V^T (Section 2, eqs. (2.3)-(2.5); Section 4).
+ *   m, n   : rows and columns, m >= n >= 1 (the paper transposes when m < n;
+ *            here m < n is rejected).
+ *   A      : device, m x n, leading dimension lda >= m.  In: G.  Out: U
+ *            (economy, m x n, orthonormal columns; u_i = 0 for sigma_i = 0).
+ *   S      : device, n doubles.  Out: singular values, non-increasing when
+ *            opts->sort, else in computed column order.
+ *   V      : device, n x n, leading dimension ldv >= n; may be NULL when
+ *            opts->want_v == 0.  Out: right singular vectors.
+ *   opts   : host, may be NULL for defaults.
+ *   info   : host, may be NULL.  Statistics of the run.
+ * Returns JSVD_OK, a negative argument index, JSVD_NOT_CONVERGED,
+ * JSVD_NONFINITE, JSVD_HIP_ERROR or JSVD_NO_MEMORY.
+ */
+int jsvd_gesvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda, double *S,
+               double *V, int64_t ldv, const jsvd_opts *opts, jsvd_info *info);
+
+/*
+ * Hyperbolic SVD, G = U Sigma V^{-1} with V^T J V = J (eq. (2.10); Section
+ * 4.3, subphases 4-5).  J = diag(j_1..j_n), j_i = +1 or -1, given on the host.
+ * Pairs of columns with opposite signs are orthogonalised by hyperbolic
+ * rotations (4.2), the others by trigonometric ones (4.1).
+ *   J      : host, n entries, each +1 or -1 (argument 6).
+ *   J_out  : host, n entries, may be NULL.  Out: the sign of each output
+ *            column.  Internally the columns are stably permuted so that J
+ *            is partitioned as diag(I, -I) (the paper keeps J partitioned);
+ *            J_out is that partitioned J.
+ *   V      : device, n x n.  Out: V with rows in the input column order and
+ *            columns in the output order, so that G V = U Sigma and
+ *            V^T J V = diag(J_out).
+ *   Other arguments as for jsvd_gesvd.  With opts->sort the positive part
+ *   is ordered by non-increasing sigma and the negative part by
+ *   non-decreasing sigma, i.e. j_i sigma_i^2 is non-increasing.
+ * The hyperbolic SVD exists when rank(G) = rank(G J G^T) (Section 2).
+ */
+int jsvd_hsvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
+              const int8_t *J, int8_t *J_out, double *S, double *V, int64_t ldv,
+              const jsvd_opts *opts, jsvd_info *info);
+
+/*
+ * The parallel pivot strategy table of Section 3 for an even order
+ * (2 <= order <= 4096; order = 2^k * o with o in {1,3,5,7,9,11}) and kind
+ * JSVD_STRAT_*: (order - 1) p-steps of order/2 pairs.  Orders that are not
+ * powers of two start from Algorithm 3.1 at 2o and are expanded by
+ * Algorithm 3.2; powers of two are expanded from order 2.
+ *   pairs : host, (order - 1) * (order / 2) * 2 int32, written as one-based
+ *           (p, q) with p < q, p-step by p-step.
+ * Returns JSVD_OK, -1 for an unsupported order, -2 for an unknown kind,
+ * -3 for pairs == NULL.
+ */
+int jsvd_strategy_table(int32_t order, int32_t kind, int32_t *pairs);
+
+/* Smallest supported strategy order >= max(nb, 2) (even, 2^k * o, o <= 11). */
+int32_t jsvd_strategy_order(int32_t nb);
+
+/* Static description of a return code. */
+const char *jsvd_error_string(int code);
+
+/*
+ * Diagnostic: run IEEE FP64 division a[i]/b[i] and sqrt(a[i]) for count
+ * values on the device (the paper assumes both correctly rounded, Section 4).
+ * a, b, quot, root: device arrays of count doubles.  Returns JSVD_OK or
+ * JSVD_HIP_ERROR.
+ */
+int jsvd_diag_fp64(jsvd_handle_t h, int64_t count, const double *a, const double *b,
+                   double *quot, double *root);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JSVD_H */

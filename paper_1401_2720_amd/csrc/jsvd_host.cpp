@@ -1,0 +1,421 @@
+// Host driver and C ABI.  The host only controls the iteration, as in
+// Section 4 of the paper: it launches one p-step after another, reads one
+// block of per-sweep counters after each block sweep, and stops when a
+// sweep performed no proper rotation (Section 4.5) or the sweep limit is
+// reached.  Everything else runs in the kernels of jsvd_kernels.hip.
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+
+#include "jsvd_internal.h"
+
+using namespace jsvd;
+
+namespace {
+
+struct DeviceTable {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct jsvd_handle_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    void *ws = nullptr;          // device workspace
+    size_t ws_bytes = 0;
+    unsigned long long *host_counters = nullptr;  // pinned
+    std::map<std::pair<int, int>, DeviceTable> block_tables;  // (order, kind) -> int2[]
+    std::map<std::pair<int, int>, DeviceTable> inner_tables;  // (bw, kind) -> uchar[]
+};
+
+namespace {
+
+#define HIP_TRY(expr)                         \
+    do {                                      \
+        hipError_t e_ = (expr);               \
+        if (e_ != hipSuccess) return JSVD_HIP_ERROR; \
+    } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int ensure_workspace(jsvd_handle_s *h, size_t bytes) {
+    if (bytes <= h->ws_bytes) return JSVD_OK;
+    if (h->ws) {
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return JSVD_HIP_ERROR;
+        (void)hipFree(h->ws);
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+    }
+    if (hipMalloc(&h->ws, bytes) != hipSuccess) {
+        h->ws = nullptr;
+        return JSVD_NO_MEMORY;
+    }
+    h->ws_bytes = bytes;
+    return JSVD_OK;
+}
+
+int get_block_table(jsvd_handle_s *h, int order, int kind, const int2 **out) {
+    auto key = std::make_pair(order, kind);
+    auto it = h->block_tables.find(key);
+    if (it == h->block_tables.end()) {
+        Table t;
+        if (!make_table(order, kind, t)) return JSVD_HIP_ERROR;
+        std::vector<int2> flat;
+        for (const auto &st : t)
+            for (const auto &pr : st) flat.push_back(make_int2(pr.first, pr.second));
+        DeviceTable d;
+        d.bytes = flat.size() * sizeof(int2);
+        HIP_TRY(hipMalloc(&d.ptr, d.bytes));
+        HIP_TRY(hipMemcpy(d.ptr, flat.data(), d.bytes, hipMemcpyHostToDevice));
+        it = h->block_tables.emplace(key, d).first;
+    }
+    *out = static_cast<const int2 *>(it->second.ptr);
+    return JSVD_OK;
+}
+
+int get_inner_table(jsvd_handle_s *h, int bw, int kind, const unsigned char **out) {
+    auto key = std::make_pair(bw, kind);
+    auto it = h->inner_tables.find(key);
+    if (it == h->inner_tables.end()) {
+        Table t;
+        if (!make_table(bw, kind, t)) return JSVD_HIP_ERROR;
+        std::vector<unsigned char> flat;
+        for (const auto &st : t)
+            for (const auto &pr : st) {
+                flat.push_back(static_cast<unsigned char>(pr.first));
+                flat.push_back(static_cast<unsigned char>(pr.second));
+            }
+        DeviceTable d;
+        d.bytes = flat.size();
+        HIP_TRY(hipMalloc(&d.ptr, d.bytes));
+        HIP_TRY(hipMemcpy(d.ptr, flat.data(), d.bytes, hipMemcpyHostToDevice));
+        it = h->inner_tables.emplace(key, d).first;
+    }
+    *out = static_cast<const unsigned char *>(it->second.ptr);
+    return JSVD_OK;
+}
+
+jsvd_opts defaults() {
+    jsvd_opts o;
+    o.block_w = 0;
+    o.strategy = JSVD_STRAT_RREV;
+    o.max_inner_sweeps = 30;
+    o.max_sweeps = 30;
+    o.want_v = 1;
+    o.sort = 1;
+    return o;
+}
+
+int choose_w(int64_t m, int64_t n) {
+    (void)m;
+    return n >= 1024 ? 32 : 16;
+}
+
+// Workspace carve-up for one solve.
+struct Layout {
+    size_t hpart, vprime, pair_rot, counters, perm, s_tmp, tmp, perm_in, total;
+};
+
+Layout plan(int64_t m, int64_t n, int bw, int npairs, int splits, bool hsvd) {
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    L.hpart = take((size_t)npairs * splits * bw * bw * sizeof(double));
+    L.vprime = take((size_t)npairs * bw * bw * sizeof(double));
+    L.pair_rot = take((size_t)npairs * sizeof(int));
+    L.counters = take(C_COUNT * sizeof(unsigned long long));
+    L.perm = take((size_t)n * sizeof(int));
+    L.s_tmp = take((size_t)n * sizeof(double));
+    L.tmp = take((size_t)std::max(m * n, n * n) * sizeof(double));
+    L.perm_in = take(hsvd ? (size_t)n * sizeof(int) : 0);
+    L.total = off;
+    return L;
+}
+
+// The solver shared by the SVD and the hyperbolic SVD.  A holds G with J
+// already partitioned (columns [0, n_plus) positive).
+int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double *S, double *V,
+          int64_t ldv, int64_t n_plus, const jsvd_opts &o, jsvd_info *info, bool hsvd,
+          const int *perm_in_host) {
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = h->stream;
+    const int w = o.block_w ? o.block_w : choose_w(m, n);
+    const int bw = 2 * w;
+    const int nb_real = (int)((n + w - 1) / w);
+    const int order = strategy_order(nb_real);
+    const int npairs = order / 2;
+    const int nsteps = order - 1;
+    const bool want_v = o.want_v != 0;
+
+    // Gram row splits and update row chunks: aim at ~4 workgroups per CU.
+    const int target_wg = 1024;
+    int splits = std::max(1, target_wg / npairs);
+    int64_t rps = align_up((size_t)((m + splits - 1) / splits), 64);
+    splits = (int)((m + rps - 1) / rps);
+    const int64_t upd_total_rows = m + (want_v ? n : 0);
+    const int per_pair = std::max(1, target_wg / npairs);
+    int64_t upd_rows = align_up((size_t)((upd_total_rows + per_pair - 1) / per_pair), 64);
+
+    Layout L = plan(m, n, bw, npairs, splits, hsvd);
+    int rc = ensure_workspace(h, L.total);
+    if (rc) return rc;
+    char *ws = static_cast<char *>(h->ws);
+
+    const int2 *blk = nullptr;
+    const unsigned char *inner = nullptr;
+    if ((rc = get_block_table(h, order, o.strategy, &blk))) return rc;
+    if ((rc = get_inner_table(h, bw, o.strategy, &inner))) return rc;
+
+    StepArgs a;
+    a.G = A;
+    a.ldg = lda;
+    a.m = m;
+    a.V = want_v ? V : nullptr;
+    a.ldv = ldv;
+    a.n = n;
+    a.w = w;
+    a.n_plus = (int)n_plus;
+    a.pairs = nullptr;
+    a.npairs = npairs;
+    a.splits = splits;
+    a.rows_per_split = (int)rps;
+    a.hpart = reinterpret_cast<double *>(ws + L.hpart);
+    a.vprime = reinterpret_cast<double *>(ws + L.vprime);
+    a.pair_rot = reinterpret_cast<int *>(ws + L.pair_rot);
+    a.counters = reinterpret_cast<unsigned long long *>(ws + L.counters);
+    a.inner_tbl = inner;
+    a.max_inner_sweeps = std::max(1, o.max_inner_sweeps);
+    a.upd_rows = (int)upd_rows;
+    a.upd_chunks_g = (int)((m + upd_rows - 1) / upd_rows);
+    a.upd_chunks_v = want_v ? (int)((n + upd_rows - 1) / upd_rows) : 0;
+
+    if (want_v) HIP_TRY(launch_init_identity(V, ldv, n, st));
+
+    jsvd_info inf;
+    std::memset(&inf, 0, sizeof inf);
+    inf.block_w = w;
+    inf.n_blocks = order;
+    int status = JSVD_OK;
+    bool converged = false;
+    for (int sweep = 0; sweep < o.max_sweeps; ++sweep) {
+        HIP_TRY(launch_reset_counters(a.counters, st));
+        for (int s = 0; s < nsteps; ++s) {
+            a.pairs = blk + (size_t)s * npairs;
+            HIP_TRY(launch_gram(bw, a, st));
+            HIP_TRY(launch_inner(bw, a, st));
+            HIP_TRY(launch_update(bw, a, st));
+        }
+        HIP_TRY(hipMemcpyAsync(h->host_counters, a.counters, C_COUNT * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const unsigned long long *c = h->host_counters;
+        inf.sweeps = sweep + 1;
+        inf.rotations += (int64_t)c[C_ROT];
+        inf.proper_rotations += (int64_t)c[C_PROPER];
+        inf.inner_sweeps += (int64_t)c[C_INNER_SW];
+        inf.pair_updates += (int64_t)c[C_UPDATES];
+        inf.chol_breakdowns += (int32_t)c[C_BREAKDOWN];
+        inf.hyp_clamps += (int32_t)c[C_CLAMP];
+        if (c[C_NONFINITE]) {
+            status = JSVD_NONFINITE;
+            break;
+        }
+        if (c[C_PROPER] == 0) {  // Section 4.5: no proper rotation in the sweep
+            converged = true;
+            break;
+        }
+    }
+    inf.converged = converged ? 1 : 0;
+    if (status == JSVD_OK && !converged) status = JSVD_NOT_CONVERGED;
+
+    // ---- singular values, U, and the output order
+    double *s_tmp = reinterpret_cast<double *>(ws + L.s_tmp);
+    int *perm = reinterpret_cast<int *>(ws + L.perm);
+    double *tmp = reinterpret_cast<double *>(ws + L.tmp);
+    HIP_TRY(launch_colnorms(A, lda, m, n, s_tmp, st));
+    if (o.sort) {
+        HIP_TRY(launch_rank(s_tmp, n, n_plus, perm, st));
+        HIP_TRY(hipMemcpy2DAsync(tmp, m * sizeof(double), A, lda * sizeof(double),
+                                 m * sizeof(double), n, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(launch_gather_cols(tmp, m, A, lda, m, n, perm, s_tmp, S, st));
+        if (want_v) {
+            HIP_TRY(hipMemcpy2DAsync(tmp, n * sizeof(double), V, ldv * sizeof(double),
+                                     n * sizeof(double), n, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(launch_gather_cols(tmp, n, V, ldv, n, n, perm, nullptr, nullptr, st));
+        }
+    } else {
+        HIP_TRY(launch_gather_cols(A, lda, A, lda, m, n, nullptr, s_tmp, S, st));
+    }
+    if (want_v && hsvd && perm_in_host) {
+        int *pin = reinterpret_cast<int *>(ws + L.perm_in);
+        HIP_TRY(hipMemcpyAsync(pin, perm_in_host, n * sizeof(int), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpy2DAsync(tmp, n * sizeof(double), V, ldv * sizeof(double),
+                                 n * sizeof(double), n, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(launch_scatter_rows(tmp, n, V, ldv, n, n, pin, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    const auto t1 = std::chrono::steady_clock::now();
+    inf.seconds = std::chrono::duration<double>(t1 - t0).count();
+    if (info) *info = inf;
+    return status;
+}
+
+int check_common(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
+                 const jsvd_opts &o) {
+    if (!h) return -1;
+    if (m < 1 || m < n) return -2;
+    if (n < 1) return -3;
+    if (!A) return -4;
+    if (lda < m) return -5;
+    if (o.block_w != 0 && o.block_w != 16 && o.block_w != 32) return -9;
+    if (o.strategy < JSVD_STRAT_RREV || o.strategy > JSVD_STRAT_C) return -9;
+    if (o.max_sweeps < 1 || o.max_inner_sweeps < 1) return -9;
+    if (m > (int64_t)1 << 31 || n > (int64_t)1 << 20) return -2;
+    return JSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int jsvd_default_opts(jsvd_opts *opts) {
+    if (!opts) return -1;
+    *opts = defaults();
+    return JSVD_OK;
+}
+
+int jsvd_create(jsvd_handle_t *h, void *hip_stream) {
+    if (!h) return -1;
+    auto *p = new (std::nothrow) jsvd_handle_s();
+    if (!p) return JSVD_NO_MEMORY;
+    if (hipGetDevice(&p->device) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&p->host_counters),
+                      C_COUNT * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+        delete p;
+        return JSVD_HIP_ERROR;
+    }
+    p->stream = static_cast<hipStream_t>(hip_stream);
+    *h = p;
+    return JSVD_OK;
+}
+
+int jsvd_set_stream(jsvd_handle_t h, void *hip_stream) {
+    if (!h) return -1;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    return JSVD_OK;
+}
+
+int jsvd_destroy(jsvd_handle_t h) {
+    if (!h) return -1;
+    (void)hipStreamSynchronize(h->stream);
+    if (h->ws) (void)hipFree(h->ws);
+    for (auto &kv : h->block_tables) (void)hipFree(kv.second.ptr);
+    for (auto &kv : h->inner_tables) (void)hipFree(kv.second.ptr);
+    if (h->host_counters) (void)hipHostFree(h->host_counters);
+    delete h;
+    return JSVD_OK;
+}
+
+int jsvd_gesvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda, double *S,
+               double *V, int64_t ldv, const jsvd_opts *opts, jsvd_info *info) {
+    const jsvd_opts o = opts ? *opts : defaults();
+    int rc = check_common(h, m, n, A, lda, o);
+    if (rc) return rc == -9 ? -9 : rc;
+    if (!S) return -6;
+    if (o.want_v && !V) return -7;
+    if (o.want_v && ldv < n) return -8;
+    if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
+    return solve(h, m, n, A, lda, S, V, ldv, n, o, info, false, nullptr);
+}
+
+int jsvd_hsvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda, const int8_t *J,
+              int8_t *J_out, double *S, double *V, int64_t ldv, const jsvd_opts *opts,
+              jsvd_info *info) {
+    const jsvd_opts o = opts ? *opts : defaults();
+    int rc = check_common(h, m, n, A, lda, o);
+    if (rc) return rc == -9 ? -11 : rc;
+    if (!J) return -6;
+    if (!S) return -8;
+    if (o.want_v && !V) return -9;
+    if (o.want_v && ldv < n) return -10;
+    std::vector<int> perm_in;  // stable partition: positives first
+    for (int64_t i = 0; i < n; ++i) {
+        if (J[i] != 1 && J[i] != -1) return -6;
+        if (J[i] == 1) perm_in.push_back((int)i);
+    }
+    const int64_t n_plus = (int64_t)perm_in.size();
+    for (int64_t i = 0; i < n; ++i)
+        if (J[i] == -1) perm_in.push_back((int)i);
+    bool identity = true;
+    for (int64_t i = 0; i < n; ++i) identity = identity && perm_in[i] == i;
+    if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
+    if (!identity) {
+        // permute the columns of G so that J = diag(I, -I)
+        const size_t tmp_bytes = align_up((size_t)m * n * sizeof(double), 256);
+        if ((rc = ensure_workspace(h, tmp_bytes + (size_t)n * sizeof(int)))) return rc;
+        double *tmp = static_cast<double *>(h->ws);
+        int *pd = reinterpret_cast<int *>(static_cast<char *>(h->ws) + tmp_bytes);
+        HIP_TRY(hipMemcpyAsync(pd, perm_in.data(), n * sizeof(int), hipMemcpyHostToDevice,
+                               h->stream));
+        HIP_TRY(hipMemcpy2DAsync(tmp, m * sizeof(double), A, lda * sizeof(double),
+                                 m * sizeof(double), n, hipMemcpyDeviceToDevice, h->stream));
+        HIP_TRY(launch_gather_cols(tmp, m, A, lda, m, n, pd, nullptr, nullptr, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    rc = solve(h, m, n, A, lda, S, V, ldv, n_plus, o, info, true,
+               identity ? nullptr : perm_in.data());
+    if (J_out)
+        for (int64_t i = 0; i < n; ++i) J_out[i] = (int8_t)(i < n_plus ? 1 : -1);
+    return rc;
+}
+
+int jsvd_strategy_table(int32_t order, int32_t kind, int32_t *pairs) {
+    if (kind < JSVD_STRAT_RREV || kind > JSVD_STRAT_C) return -2;
+    if (!pairs) return -3;
+    if (order < 2 || order % 2 || strategy_order(order) != order || order > 4096) return -1;
+    Table t;
+    if (!make_table(order, kind, t)) return -1;
+    size_t k = 0;
+    for (const auto &st : t)
+        for (const auto &pr : st) {
+            pairs[k++] = pr.first + 1;
+            pairs[k++] = pr.second + 1;
+        }
+    return JSVD_OK;
+}
+
+int32_t jsvd_strategy_order(int32_t nb) { return strategy_order(nb); }
+
+const char *jsvd_error_string(int code) {
+    switch (code) {
+    case JSVD_OK: return "success";
+    case JSVD_NOT_CONVERGED: return "not converged within the block sweep limit";
+    case JSVD_CHOL_BREAKDOWN: return "Cholesky breakdown in a pivot block Gram matrix";
+    case JSVD_NONFINITE: return "non-finite value in the input or the iteration";
+    case JSVD_HIP_ERROR: return "HIP runtime error";
+    case JSVD_NO_MEMORY: return "device workspace allocation failed";
+    default: return code < 0 ? "invalid argument" : "unknown status";
+    }
+}
+
+int jsvd_diag_fp64(jsvd_handle_t h, int64_t count, const double *a, const double *b,
+                   double *quot, double *root) {
+    if (!h) return -1;
+    if (count < 0) return -2;
+    if (!a || !b || !quot || !root) return -3;
+    if (count == 0) return JSVD_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
+    HIP_TRY(launch_diag_fp64(count, a, b, quot, root, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return JSVD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// Internal declarations shared by the host driver and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <utility>
+#include <vector>
+
+#include "jsvd.h"
+
+namespace jsvd {
+
+// ---------------------------------------------------------------- strategies
+using Pair = std::pair<int, int>;  // zero-based (p, q), p < q
+using Step = std::vector<Pair>;
+using Table = std::vector<Step>;
+
+int strategy_order(int nb);
+bool make_table(int order, int kind, Table &out);
+
+// ------------------------------------------------------------------ counters
+// Per-sweep device counters (unsigned 64-bit), reset at the start of a sweep.
+enum Counter {
+    C_ROT = 0,       // inner rotations
+    C_PROPER = 1,    // inner rotations with cs != 1
+    C_CLAMP = 2,     // |coth 2phi| substitutions
+    C_BREAKDOWN = 3, // non-positive Cholesky pivots
+    C_INNER_SW = 4,  // inner sweeps
+    C_UPDATES = 5,   // pivot block-pairs with a transformation to apply
+    C_NONFINITE = 6, // NaN met in a pivot Gram matrix
+    C_COUNT = 8
+};
+
+// ------------------------------------------------------- one p-step's launch
+struct StepArgs {
+    double *G;
+    int64_t ldg;
+    int64_t m;          // rows of G
+    double *V;          // may be null (no V accumulation)
+    int64_t ldv;
+    int64_t n;          // real columns (and rows of V)
+    int w;              // block width
+    int n_plus;         // columns [0, n_plus) carry +1 in J
+    const int2 *pairs;  // this p-step's pivot block-pairs, zero-based
+    int npairs;
+    int splits;         // Gram row splits per pair
+    int rows_per_split; // multiple of 64
+    double *hpart;      // [npairs][splits][bw*bw] partial Gram matrices (row-major tiles)
+    double *vprime;     // [npairs][bw*bw] column-major V'_pq
+    int *pair_rot;      // [npairs] rotations done in the pair (0 = skip update)
+    unsigned long long *counters;
+    const unsigned char *inner_tbl;  // [(bw-1)][bw/2][2] zero-based inner pairs
+    int max_inner_sweeps;
+    int upd_rows;       // rows per update workgroup, multiple of 64
+    int upd_chunks_g;   // update workgroups over the rows of G (per pair)
+    int upd_chunks_v;   // update workgroups over the rows of V (per pair)
+};
+
+hipError_t launch_gram(int bw, const StepArgs &a, hipStream_t s);
+hipError_t launch_inner(int bw, const StepArgs &a, hipStream_t s);
+hipError_t launch_update(int bw, const StepArgs &a, hipStream_t s);
+
+hipError_t launch_reset_counters(unsigned long long *c, hipStream_t s);
+hipError_t launch_init_identity(double *V, int64_t ldv, int64_t n, hipStream_t s);
+hipError_t launch_colnorms(const double *G, int64_t ldg, int64_t m, int64_t n, double *s_out,
+                           hipStream_t s);
+hipError_t launch_rank(const double *s, int64_t n, int64_t n_plus, int *perm, hipStream_t st);
+hipError_t launch_gather_cols(const double *src, int64_t lds, double *dst, int64_t ldd,
+                              int64_t rows, int64_t cols, const int *perm, const double *scale,
+                              double *s_out, hipStream_t s);
+hipError_t launch_scatter_rows(const double *src, int64_t lds, double *dst, int64_t ldd,
+                               int64_t rows, int64_t cols, const int *row_of, hipStream_t s);
+hipError_t launch_diag_fp64(int64_t count, const double *a, const double *b, double *q,
+                            double *r, hipStream_t s);
+
+}  // namespace jsvd

@@ -1,0 +1,198 @@
+// Parallel pivot strategies (Section 3).
+//
+// A p-strategy of even order N has N-1 parallel steps (p-steps) of N/2
+// disjoint pivot pairs and visits every pair once per sweep, eq. (3.1).
+// The strategy closest to a sequential order O (Definition 3.1) is the one
+// whose pairs, read step by step, have the lexicographically smallest
+// sequence of positions in O.  Algorithm 3.1 builds it by taking the
+// lexicographically first set of N/2 disjoint unused pairs that still lets
+// the remaining pairs be completed, backtracking otherwise.  It is only
+// affordable for small orders, so (following Section 3) a table of order
+// 2^k * o is built from order 2o by k-1 expansions of Algorithm 3.2, which
+// turns every p-step of order N into two p-steps of order 2N.  The reverse
+// strategies list the pairs in the opposite order.
+#include "jsvd_internal.h"
+
+#include <map>
+#include <mutex>
+
+namespace jsvd {
+
+namespace {
+
+// Sequential cyclic orders as lists of zero-based pairs.
+std::vector<Pair> sequential(int n, bool row_cyclic) {
+    std::vector<Pair> v;
+    v.reserve(static_cast<size_t>(n) * (n - 1) / 2);
+    if (row_cyclic) {
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) v.push_back({i, j});
+    } else {
+        for (int j = 1; j < n; ++j)
+            for (int i = 0; i < j; ++i) v.push_back({i, j});
+    }
+    return v;
+}
+
+// Algorithm 3.1 by depth-first search over positions in the sequential
+// order.  'used' marks pairs already placed in earlier p-steps.
+class ClosestSearch {
+  public:
+    ClosestSearch(int n, bool row) : n_(n), half_(n / 2), seq_(sequential(n, row)), used_(seq_.size(), 0) {}
+
+    bool run(Table &out) {
+        steps_.clear();
+        if (!level(static_cast<int>(seq_.size()))) return false;
+        out.clear();
+        for (const auto &st : steps_) {
+            Step s;
+            for (int pos : st) s.push_back(seq_[pos]);
+            out.push_back(s);
+        }
+        return true;
+    }
+
+  private:
+    // One recursion level of Algorithm 3.1: enumerate candidate p-steps in
+    // lexicographic order of positions and recurse on the rest.
+    bool level(int remaining) {
+        if (remaining == 0) return true;
+        std::vector<int> chosen;
+        std::vector<char> covered(n_, 0);
+        return enumerate(0, chosen, covered, remaining);
+    }
+
+    // Every index not yet covered must still be reachable by an unused pair
+    // at a position >= start whose other index is also uncovered.
+    bool feasible(int start, const std::vector<char> &covered) const {
+        std::vector<char> reach(n_, 0);
+        for (size_t k = start; k < seq_.size(); ++k) {
+            if (used_[k]) continue;
+            const Pair &pr = seq_[k];
+            if (!covered[pr.first] && !covered[pr.second]) reach[pr.first] = reach[pr.second] = 1;
+        }
+        for (int i = 0; i < n_; ++i)
+            if (!covered[i] && !reach[i]) return false;
+        return true;
+    }
+
+    bool enumerate(int start, std::vector<int> &chosen, std::vector<char> &covered, int remaining) {
+        if (static_cast<int>(chosen.size()) == half_) {
+            for (int pos : chosen) used_[pos] = 1;
+            steps_.push_back(chosen);
+            if (level(remaining - half_)) return true;
+            steps_.pop_back();
+            for (int pos : chosen) used_[pos] = 0;
+            return false;  // try the next candidate (backtrack)
+        }
+        if (!feasible(start, covered)) return false;
+        for (size_t k = start; k < seq_.size(); ++k) {
+            if (used_[k]) continue;
+            const Pair &pr = seq_[k];
+            if (covered[pr.first] || covered[pr.second]) continue;
+            covered[pr.first] = covered[pr.second] = 1;
+            chosen.push_back(static_cast<int>(k));
+            if (enumerate(static_cast<int>(k) + 1, chosen, covered, remaining)) return true;
+            chosen.pop_back();
+            covered[pr.first] = covered[pr.second] = 0;
+        }
+        return false;
+    }
+
+    int n_, half_;
+    std::vector<Pair> seq_;
+    std::vector<char> used_;
+    std::vector<std::vector<int>> steps_;
+};
+
+// Algorithm 3.2: order N -> order 2N.  The first p-step pairs (2k, 2k+1)
+// (zero-based); p-step i >= 1 of the result comes from p-step (i+1)/2 - 1
+// of the input: even one-based i gives the NW and SE pairs of each 2x2
+// block, odd i the NE and SW pairs (SW first for the column-cyclic family).
+Table expand(const Table &in, bool row_cyclic) {
+    const int n = static_cast<int>(in.size()) + 1;
+    Table out;
+    Step first;
+    for (int k = 0; k < n; ++k) first.push_back({2 * k, 2 * k + 1});
+    out.push_back(first);
+    for (int i = 2; i <= 2 * n - 1; ++i) {  // one-based step index
+        const Step &src = in[i / 2 - 1];
+        Step s;
+        for (const Pair &pq : src) {
+            const int p = pq.first, q = pq.second;
+            if (i % 2 == 0) {
+                s.push_back({2 * p, 2 * q});
+                s.push_back({2 * p + 1, 2 * q + 1});
+            } else if (row_cyclic) {
+                s.push_back({2 * p, 2 * q + 1});
+                s.push_back({2 * p + 1, 2 * q});
+            } else {
+                s.push_back({2 * p + 1, 2 * q});
+                s.push_back({2 * p, 2 * q + 1});
+            }
+        }
+        out.push_back(s);
+    }
+    return out;
+}
+
+bool split_order(int order, int &k, int &o) {
+    if (order < 2 || order % 2) return false;
+    k = 0;
+    o = order;
+    while (o % 2 == 0) {
+        o /= 2;
+        ++k;
+    }
+    return o == 1 || o == 3 || o == 5 || o == 7 || o == 9 || o == 11;
+}
+
+}  // namespace
+
+int strategy_order(int nb) {
+    int n = nb < 2 ? 2 : nb;
+    if (n % 2) ++n;
+    int k, o;
+    while (!split_order(n, k, o)) n += 2;
+    return n;
+}
+
+bool make_table(int order, int kind, Table &out) {
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, Table> cache;
+    int k, o;
+    if (!split_order(order, k, o) || order > 4096) return false;
+    if (kind < JSVD_STRAT_RREV || kind > JSVD_STRAT_C) return false;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({order, kind});
+    if (it != cache.end()) {
+        out = it->second;
+        return true;
+    }
+    const bool row = (kind == JSVD_STRAT_R || kind == JSVD_STRAT_RREV);
+    const bool rev = (kind == JSVD_STRAT_RREV || kind == JSVD_STRAT_CREV);
+    Table t;
+    int cur;
+    if (o == 1) {
+        t = {Step{{0, 1}}};
+        cur = 2;
+    } else {
+        ClosestSearch s(2 * o, row);
+        if (!s.run(t)) return false;
+        cur = 2 * o;
+    }
+    while (cur < order) {
+        t = expand(t, row);
+        cur *= 2;
+    }
+    if (rev) {
+        Table r(t.rbegin(), t.rend());
+        for (auto &st : r) std::reverse(st.begin(), st.end());
+        t.swap(r);
+    }
+    cache[{order, kind}] = t;
+    out = t;
+    return true;
+}
+
+}  // namespace jsvd
