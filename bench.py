@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark: FP64 one-sided block Jacobi SVD of a 4096 x 4096 N(0,1) matrix
+on one MI355X, through the C ABI.
+
+One step = one complete SVD (strategy tables from the handle's cache, V := I,
+block sweeps of Gram / Cholesky + inner Jacobi / update until no proper
+rotation, singular values, U and the output order).  The input is already
+in HBM; each step first restores it from a device copy (U overwrites it).
+
+Prints one JSON line with the time per SVD, the roofline of the dominant
+kernel (per-kernel times from HIP events recorded by the library on the
+stream it launches on) and the oracle timed on a bounded sample on the
+host cores.
+"""
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 matrix (= FP64 vector)
+RIDGE = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--block-w", type=int, default=0)
+    ap.add_argument("--strategy", default="rrev")
+    ap.add_argument("--max-inner-sweeps", type=int, default=30)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target length of the oracle sample (0 = skip)")
+    return ap.parse_args()
+
+
+def kernel_roofline(name, avg_ms, per_launch, w):
+    """Roofline entry of one p-step kernel from its algorithmic work per launch."""
+    bw = 2 * w
+    sec = avg_ms * 1e-3
+    if name == "inner":
+        achieved = per_launch["inner_flops"] / sec / 1e12
+        return {"kernel": "inner", "bound": "alu", "achieved": achieved,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": None}
+    flops = per_launch[name + "_flops"]
+    bytes_ = per_launch[name + "_bytes"]
+    if flops / max(bytes_, 1) >= RIDGE:
+        achieved = flops / sec / 1e12
+        return {"kernel": name, "bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "intensity_flop_per_byte": flops / bytes_}
+    achieved = bytes_ / sec / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+            "intensity_flop_per_byte": flops / bytes_, "bw": bw}
+
+
+def cpu_baseline(A, sweeps, target_s):
+    """The oracle (round-robin OpenMP ordering) on the first rounds of the
+    first sweep of the same matrix, scaled to seconds per SVD."""
+    import numpy as np
+    import oracle
+    n = A.shape[1]
+    rounds_per_sweep = n - 1 + (n & 1)
+    probe = 32
+    t0 = time.perf_counter()
+    oracle.gesvj(A, order="rr", max_sweeps=1, max_rounds=probe, sort=False)
+    t_probe = time.perf_counter() - t0
+    rounds = int(max(probe, min(rounds_per_sweep, target_s / max(t_probe / probe, 1e-9))))
+    t0 = time.perf_counter()
+    oracle.gesvj(A, order="rr", max_sweeps=1, max_rounds=rounds, sort=False)
+    t = time.perf_counter() - t0
+    per_sweep = t / rounds * rounds_per_sweep
+    del np
+    return {"value": per_sweep * sweeps, "unit": "s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": (f"round-robin oracle, first {rounds} of {rounds_per_sweep} rounds of "
+                       f"sweep 1 on the same {A.shape[0]}x{n} input ({t:.1f} s); per-sweep "
+                       f"time x {sweeps} sweeps (the GPU run's sweep count)")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU level is not part of "
+              "it); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1401_2720_amd as jsvd
+    from paper_1401_2720_amd import _binding as B
+    from paper_1401_2720_amd import inputs
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    m = n = args.n
+    A_host = inputs.square_gaussian(seed=2, n=n)
+    A0 = torch.from_numpy(A_host).to(dev).t().contiguous()  # column-major copy (n x m)
+    work = torch.empty_like(A0)
+    S = torch.empty(n, dtype=torch.float64, device=dev)
+    V = torch.empty((n, n), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    L = jsvd.lib()
+    h = B._handle(0, stream.cuda_stream)
+    opts = B.make_opts(block_w=args.block_w, strategy=args.strategy,
+                       max_inner_sweeps=args.max_inner_sweeps)
+    info = B.Info()
+
+    def step():
+        work.copy_(A0)
+        rc = L.jsvd_gesvd(h, m, n, ctypes.c_void_p(work.data_ptr()), m,
+                          ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(V.data_ptr()), n,
+                          ctypes.byref(opts), ctypes.byref(info))
+        if rc != 0:
+            raise B.JsvdError(rc, "jsvd_gesvd")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    B.kernel_timing(0, True)
+    sweeps, rotations, inner_sweeps, updates = [], [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        sweeps.append(info.sweeps)
+        rotations.append(info.rotations)
+        inner_sweeps.append(info.inner_sweeps)
+        updates.append(info.pair_updates)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = B.kernel_times(0)
+    B.kernel_timing(0, False)
+    ms_per_step = (t1 - t0) / args.steps * 1e3
+    w = info.block_w
+    bw = 2 * w
+    nb = info.n_blocks
+    npairs = nb // 2
+    steps_per_sweep = nb - 1
+
+    # algorithmic work per launch (every pair of a p-step is active here)
+    launches = kt["gram"][1]
+    upd_per_launch = sum(updates) / max(launches, 1)
+    rot_per_launch = sum(rotations) / max(launches, 1)
+    isw_per_launch = sum(inner_sweeps) / max(launches, 1)
+    per_launch = {
+        "gram_flops": npairs * 2.0 * m * bw * bw,
+        "gram_bytes": npairs * m * bw * 8.0,
+        "update_flops": upd_per_launch * 2.0 * (m + n) * bw * bw,
+        "update_bytes": upd_per_launch * (m + n) * bw * 8.0 * 2,
+        "inner_flops": (isw_per_launch * (bw - 1) * (bw // 2) * 6.0 * bw
+                        + rot_per_launch * 12.0 * bw + npairs * bw ** 3 / 3.0),
+    }
+    avg = {k: (kt[k][0] / max(kt[k][1], 1)) for k in kt}
+    dominant = max(kt, key=lambda k: kt[k][0])
+    roof = kernel_roofline(dominant, avg[dominant], per_launch, w)
+    roof["avg_launch_us"] = avg[dominant] * 1e3
+    roof["launches"] = kt[dominant][1]
+
+    # accuracy of the last step against properties that hold at any size
+    Ucm = work.t()
+    s = S
+    fro2 = float((A0 * A0).sum())
+    sum_s2 = float((s * s).sum())
+    Vm = V.t()  # V is stored column-major: its transpose view is the matrix
+    orth_v = float((Vm.t().contiguous() @ Vm - torch.eye(n, dtype=torch.float64, device=dev))
+                   .abs().max())
+    orth_u = float((Ucm.t().contiguous() @ Ucm - torch.eye(n, dtype=torch.float64, device=dev))
+                   .abs().max())
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline(A_host, int(np.median(sweeps)), args.cpu_seconds)
+
+    out = {
+        "metric": "FP64 SVD time (s) at n=4096",
+        "value": ms_per_step / 1e3,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"svd_gaussian_{m}x{n}", "m": m, "n": n, "seed": 2,
+                   "block_w": w, "strategy": args.strategy,
+                   "max_inner_sweeps": args.max_inner_sweeps, "sweeps": sweeps,
+                   "rotations": rotations[-1]},
+        "roofline": roof,
+        "kernels_avg_us": {k: avg[k] * 1e3 for k in avg},
+        "kernels_share": {k: kt[k][0] / max(sum(v[0] for v in kt.values()), 1e-9) for k in kt},
+        "accuracy": {"fro2_rel": abs(sum_s2 - fro2) / fro2, "orth_u": orth_u, "orth_v": orth_v},
+        "cpu_baseline": cpu,
+        "context": {"paper_k20c_s_n4096": 46.357804, "paper_c2070_s_n4096": 84.4665,
+                    "note": "paper: Cholesky factors with spectrum Lambda(2), other hardware"},
+        "steps_per_sweep": steps_per_sweep,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -45,6 +45,7 @@ extern "C" {
 #define JSVD_NONFINITE 3       /* a NaN or infinity appeared in the input or the iteration */
 #define JSVD_HIP_ERROR 4       /* a HIP runtime call failed */
 #define JSVD_NO_MEMORY 5       /* workspace allocation failed */
+#define JSVD_DEGENERATE 6      /* equal singular values: the adjoint of U and V is undefined */
 
 /* Parallel pivot strategies of Section 3, used at both levels. */
 #define JSVD_STRAT_RREV 0 /* reverse of the p-strategy closest to row-cyclic (default) */
@@ -134,6 +135,56 @@ int jsvd_hsvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
               const jsvd_opts *opts, jsvd_info *info);
 
 /*
+ * Many independent ordinary SVDs of uneven sizes (the same one-sided Jacobi
+ * method, Section 2 eqs. (2.3)-(2.5) with the rotations (4.3)-(4.6), applied
+ * pointwise to each problem in the p-steps of the closest parallel strategy
+ * of Section 3), in one persistent launch: workgroups pull problems from a
+ * device queue, largest n first, and each runs its problem to its own
+ * convergence (a sweep with no rotation) or opts->max_sweeps.
+ *   batch        : number of problems (0 is allowed: nothing is done).
+ *   max_m, max_n : host bounds on the sizes, 1 <= max_n <= 256, max_n <= max_m;
+ *                  they size the per-workgroup scratch.
+ *   m, n         : device int32[batch], 1 <= n[i] <= m[i], m[i] <= max_m, n[i] <= max_n.
+ *   a_off        : device int64[batch]: problem i is A + a_off[i], column-major, lda = m[i];
+ *                  in: G_i, out: U_i (m[i] x n[i]).
+ *   s_off        : device int64[batch]: singular values of i at S + s_off[i] (n[i], non-increasing).
+ *   v_off        : device int64[batch] or NULL when opts->want_v == 0: V_i at V + v_off[i],
+ *                  n[i] x n[i], ldv = n[i].
+ *   status       : device int32[batch] or NULL: 0 converged, JSVD_NOT_CONVERGED otherwise.
+ *   sweeps       : device int32[batch] or NULL: sweeps performed.
+ * Only opts->max_sweeps and opts->want_v are used (block_w does not apply:
+ * the problems are not blocked).  The work is enqueued on the handle's
+ * stream and the call returns without waiting, so a caller can capture it
+ * into a HIP graph once the first call (which allocates the workspace and
+ * uploads the strategy tables) has run; the problems must not overlap in A,
+ * S or V.  Returns JSVD_OK, a negative argument index, JSVD_HIP_ERROR or
+ * JSVD_NO_MEMORY.
+ */
+int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t max_n,
+                       const int32_t *m, const int32_t *n, const int64_t *a_off,
+                       const int64_t *s_off, const int64_t *v_off, double *A, double *S,
+                       double *V, const jsvd_opts *opts, int32_t *status, int32_t *sweeps);
+
+/*
+ * Adjoint (reverse-mode derivative) of the SVD for a batch of equally sized
+ * problems (not in the paper; the published SVD adjoint):
+ *   J = U^T dU, K = V^T dV, F_ij = 1/(s_j^2 - s_i^2) (i != j), F_ii = 0,
+ *   dA = U [diag(dS) + (F o (J - J^T)) diag(S) + diag(S) (F o (K - K^T))] V^T
+ *        + (I - U U^T) dU diag(S)^{-1} V^T,
+ * computed as (U (M - J diag(S)^{-1}) + dU diag(S)^{-1}) V^T with FP64 MFMA
+ * products.  All arrays are device memory, batch after batch, column-major
+ * and contiguous: U and dU batch x (m x n), S and dS batch x n, V and dV
+ * batch x (n x n), dA batch x (m x n).  dU, dS and dV may each be NULL (a
+ * zero adjoint).  Requires m >= n >= 1 and distinct, non-zero singular
+ * values.  Synchronises the stream before returning.
+ * Returns JSVD_OK, a negative argument index, JSVD_DEGENERATE,
+ * JSVD_HIP_ERROR or JSVD_NO_MEMORY.
+ */
+int jsvd_svd_backward(jsvd_handle_t h, int64_t batch, int64_t m, int64_t n, const double *U,
+                      const double *S, const double *V, const double *dU, const double *dS,
+                      const double *dV, double *dA);
+
+/*
  * The parallel pivot strategy table of Section 3 for an even order
  * (2 <= order <= 4096; order = 2^k * o with o in {1,3,5,7,9,11}) and kind
  * JSVD_STRAT_*: (order - 1) p-steps of order/2 pairs.  Orders that are not
@@ -148,6 +199,18 @@ int jsvd_strategy_table(int32_t order, int32_t kind, int32_t *pairs);
 
 /* Smallest supported strategy order >= max(nb, 2) (even, 2^k * o, o <= 11). */
 int32_t jsvd_strategy_order(int32_t nb);
+
+/*
+ * Measurement aid: per-kernel GPU time of the block sweeps, taken with HIP
+ * events recorded on the handle's stream around every launch of the three
+ * p-step kernels (index 0 = Gram, 1 = inner Cholesky and Jacobi, 2 =
+ * update).  jsvd_kernel_timing(h, 1) turns it on and zeroes the totals,
+ * (h, 0) turns it off.  jsvd_kernel_times writes the totals since the last
+ * reset: ms[3] (host) in milliseconds and launches[3] (host).
+ * Both return JSVD_OK or -i for a NULL argument i.
+ */
+int jsvd_kernel_timing(jsvd_handle_t h, int enable);
+int jsvd_kernel_times(jsvd_handle_t h, double *ms, int64_t *launches);
 
 /* Static description of a return code. */
 const char *jsvd_error_string(int code);

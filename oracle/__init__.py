@@ -62,6 +62,7 @@ def _load(precision="double"):
     pi32 = ctypes.POINTER(_i32)
     pi64 = ctypes.POINTER(_i64)
     f.argtypes = [_i64, pi32, pi32, pi64, pi64, pi64, preal, preal, preal, _i32, pi32, pi32]
+    getattr(lib, "orc_num_threads" + sfx).restype = ctypes.c_int
     _LIBS[precision] = (lib, sfx, real)
     return _LIBS[precision]
 
@@ -186,3 +187,9 @@ def gesvj_many(mats, max_sweeps=100, want_v=True):
         out.append(dict(U=U[:, perm], S=s[perm], V=Vi, sweeps=int(sweeps[i]),
                         converged=status[i] == 0))
     return out
+
+
+def num_threads():
+    """OpenMP threads used by the parallel oracle entry points."""
+    lib, sfx, _ = _load("double")
+    return int(getattr(lib, "orc_num_threads" + sfx)())

@@ -44,6 +44,7 @@
  * SVD and of the hyperbolic SVD.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -322,3 +323,6 @@ void NAME(orc_gesvj_many)(int64_t count, const int32_t *m, const int32_t *n,
         status[i] = rc;
     }
 }
+
+/* Threads the OpenMP entry points use (for reporting timings). */
+int NAME(orc_num_threads)(void) { return omp_get_max_threads(); }

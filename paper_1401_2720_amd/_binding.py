@@ -19,7 +19,7 @@ _i32, _i64, _dbl, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.
 
 STRATEGIES = {"rrev": 0, "r": 1, "crev": 2, "c": 3}
 STATUS = {0: "ok", 1: "not converged", 2: "Cholesky breakdown", 3: "non-finite value",
-          4: "HIP error", 5: "out of device memory"}
+          4: "HIP error", 5: "out of device memory", 6: "equal singular values"}
 
 
 class Opts(ctypes.Structure):
@@ -46,7 +46,8 @@ class JsvdError(RuntimeError):
 _LIB = None
 EXPORTS = ["jsvd_default_opts", "jsvd_create", "jsvd_set_stream", "jsvd_destroy", "jsvd_gesvd",
            "jsvd_hsvd", "jsvd_strategy_table", "jsvd_strategy_order", "jsvd_error_string",
-           "jsvd_diag_fp64"]
+           "jsvd_diag_fp64", "jsvd_kernel_timing", "jsvd_kernel_times", "jsvd_gesvd_batched",
+           "jsvd_svd_backward"]
 
 
 def lib():
@@ -72,8 +73,15 @@ def lib():
     L.jsvd_error_string.argtypes = [ctypes.c_int]
     L.jsvd_error_string.restype = ctypes.c_char_p
     L.jsvd_diag_fp64.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp]
+    L.jsvd_gesvd_batched.argtypes = [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                     _vp, ctypes.POINTER(Opts), _vp, _vp]
+    L.jsvd_svd_backward.argtypes = [_vp, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.jsvd_kernel_timing.argtypes = [_vp, ctypes.c_int]
+    L.jsvd_kernel_times.argtypes = [_vp, _vp, _vp]
     for f in ("jsvd_default_opts", "jsvd_create", "jsvd_set_stream", "jsvd_destroy",
-              "jsvd_gesvd", "jsvd_hsvd", "jsvd_strategy_table", "jsvd_diag_fp64"):
+              "jsvd_gesvd", "jsvd_hsvd", "jsvd_strategy_table", "jsvd_diag_fp64",
+              "jsvd_kernel_timing", "jsvd_kernel_times", "jsvd_gesvd_batched",
+              "jsvd_svd_backward"):
         getattr(L, f).restype = ctypes.c_int
     _LIB = L
     return L
@@ -218,3 +226,167 @@ def diag_fp64(a, b):
     if rc:
         raise JsvdError(rc, "jsvd_diag_fp64")
     return q, r
+
+
+def kernel_timing(device_index, enable=True):
+    """Turn per-kernel event timing on (and zero it) or off for a device's handle."""
+    import torch
+    h = _handle(device_index, torch.cuda.current_stream(device_index).cuda_stream)
+    rc = lib().jsvd_kernel_timing(h, 1 if enable else 0)
+    if rc:
+        raise JsvdError(rc, "jsvd_kernel_timing")
+
+
+def kernel_times(device_index):
+    """{'gram'|'inner'|'update': (total_ms, launches)} since the last reset."""
+    import numpy as np
+    import torch
+    h = _handle(device_index, torch.cuda.current_stream(device_index).cuda_stream)
+    ms = np.zeros(3, np.float64)
+    cnt = np.zeros(3, np.int64)
+    rc = lib().jsvd_kernel_times(h, _vp(ms.ctypes.data), _vp(cnt.ctypes.data))
+    if rc:
+        raise JsvdError(rc, "jsvd_kernel_times")
+    return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(("gram", "inner", "update"))}
+
+
+class Batch:
+    """Uneven problems packed column-major into one device buffer.
+
+    Built from a list of (m_i x n_i) arrays (numpy or torch); holds the
+    device buffers A (in: G, out: U), S, V, the int32 sizes and the int64
+    offsets that jsvd_gesvd_batched takes.
+    """
+
+    def __init__(self, mats, device="cuda", want_v=True):
+        import numpy as np
+        import torch
+        ms = np.array([a.shape[0] for a in mats], np.int32)
+        ns = np.array([a.shape[1] for a in mats], np.int32)
+        if np.any(ms < ns) or np.any(ns < 1):
+            raise ValueError("every problem needs 1 <= n <= m")
+        count = len(mats)
+        a_off = np.zeros(count, np.int64)
+        s_off = np.zeros(count, np.int64)
+        v_off = np.zeros(count, np.int64)
+        if count:
+            a_off[1:] = np.cumsum(ms.astype(np.int64) * ns)[:-1]
+            s_off[1:] = np.cumsum(ns.astype(np.int64))[:-1]
+            v_off[1:] = np.cumsum(ns.astype(np.int64) ** 2)[:-1]
+        host = np.concatenate([np.asarray(a if not hasattr(a, "cpu") else a.cpu(),
+                                          np.float64).ravel(order="F") for a in mats])
+        self.count = count
+        self.max_m = int(ms.max()) if count else 1
+        self.max_n = int(ns.max()) if count else 1
+        self.m_host, self.n_host = ms, ns
+        self.a_off_host, self.s_off_host, self.v_off_host = a_off, s_off, v_off
+        dev = torch.device(device)
+        self.A0 = torch.from_numpy(host).to(dev)
+        self.A = self.A0.clone()
+        self.S = torch.zeros(int(ns.sum()), dtype=torch.float64, device=dev)
+        self.V = torch.zeros(int((ns.astype(np.int64) ** 2).sum()), dtype=torch.float64,
+                             device=dev) if want_v else None
+        self.m = torch.from_numpy(ms).to(dev)
+        self.n = torch.from_numpy(ns).to(dev)
+        self.a_off = torch.from_numpy(a_off).to(dev)
+        self.s_off = torch.from_numpy(s_off).to(dev)
+        self.v_off = torch.from_numpy(v_off).to(dev)
+        self.status = torch.zeros(count, dtype=torch.int32, device=dev)
+        self.sweeps = torch.zeros(count, dtype=torch.int32, device=dev)
+        self.want_v = want_v
+
+    @classmethod
+    def from_uniform(cls, A, want_v=True):
+        """A batch of equally sized problems from a (b, m, n) float64 CUDA tensor,
+        packed on the device (no host round trip)."""
+        import numpy as np
+        import torch
+        b, m, n = A.shape
+        self = cls.__new__(cls)
+        dev = A.device
+        self.count = b
+        self.max_m, self.max_n = m, n
+        self.m_host = np.full(b, m, np.int32)
+        self.n_host = np.full(b, n, np.int32)
+        self.a_off_host = np.arange(b, dtype=np.int64) * m * n
+        self.s_off_host = np.arange(b, dtype=np.int64) * n
+        self.v_off_host = np.arange(b, dtype=np.int64) * n * n
+        self.A0 = A.transpose(-1, -2).contiguous().view(-1)
+        self.A = self.A0.clone()
+        self.S = torch.zeros(b * n, dtype=torch.float64, device=dev)
+        self.V = torch.zeros(b * n * n, dtype=torch.float64, device=dev) if want_v else None
+        self.m = torch.from_numpy(self.m_host).to(dev)
+        self.n = torch.from_numpy(self.n_host).to(dev)
+        self.a_off = torch.from_numpy(self.a_off_host).to(dev)
+        self.s_off = torch.from_numpy(self.s_off_host).to(dev)
+        self.v_off = torch.from_numpy(self.v_off_host).to(dev)
+        self.status = torch.zeros(b, dtype=torch.int32, device=dev)
+        self.sweeps = torch.zeros(b, dtype=torch.int32, device=dev)
+        self.want_v = want_v
+        return self
+
+    def results(self, i):
+        """(U, S, V) of problem i as numpy arrays (after a synchronised run)."""
+        m, n = int(self.m_host[i]), int(self.n_host[i])
+        a, s, v = int(self.a_off_host[i]), int(self.s_off_host[i]), int(self.v_off_host[i])
+        U = self.A[a:a + m * n].cpu().numpy().reshape((m, n), order="F")
+        S = self.S[s:s + n].cpu().numpy()
+        V = self.V[v:v + n * n].cpu().numpy().reshape((n, n), order="F") if self.want_v else None
+        return U, S, V
+
+
+def gesvd_batched(batch, max_sweeps=30, restore=True):
+    """Run jsvd_gesvd_batched on a Batch on the current stream (asynchronous).
+
+    restore=True first copies the original inputs back into batch.A.
+    """
+    import torch
+    dev = batch.A.device
+    stream = torch.cuda.current_stream(dev)
+    h = _handle(dev.index if dev.index is not None else torch.cuda.current_device(),
+                stream.cuda_stream)
+    if restore:
+        batch.A.copy_(batch.A0)
+    o = make_opts(max_sweeps=max_sweeps, want_v=batch.want_v)
+    rc = lib().jsvd_gesvd_batched(
+        h, batch.count, batch.max_m, batch.max_n, _vp(batch.m.data_ptr()),
+        _vp(batch.n.data_ptr()), _vp(batch.a_off.data_ptr()), _vp(batch.s_off.data_ptr()),
+        _vp(batch.v_off.data_ptr()) if batch.want_v else None, _vp(batch.A.data_ptr()),
+        _vp(batch.S.data_ptr()), _vp(batch.V.data_ptr()) if batch.want_v else None,
+        ctypes.byref(o), _vp(batch.status.data_ptr()), _vp(batch.sweeps.data_ptr()))
+    if rc:
+        raise JsvdError(rc, "jsvd_gesvd_batched")
+
+
+def svd_backward(U, S, V, dU=None, dS=None, dV=None):
+    """dA from the SVD adjoint for (b, m, n) / (m, n) float64 CUDA tensors.
+
+    U (.., m, n), S (.., n), V (.., n, n) as matrices (any strides); dU, dS,
+    dV of the same shapes or None.  Returns dA (.., m, n).
+    """
+    import torch
+    batched = U.dim() == 3
+    if not batched:
+        U, S, V = U[None], S[None], V[None]
+        dU = None if dU is None else dU[None]
+        dS = None if dS is None else dS[None]
+        dV = None if dV is None else dV[None]
+    b, m, n = U.shape
+
+    def cm(X):  # contiguous batch of column-major matrices
+        return None if X is None else X.transpose(-1, -2).contiguous()
+
+    Uc, Vc, dUc, dVc = cm(U), cm(V), cm(dU), cm(dV)
+    Sc = S.contiguous()
+    dSc = None if dS is None else dS.contiguous()
+    dA = torch.empty((b, n, m), dtype=torch.float64, device=U.device)
+    dev = U.device
+    h = _handle(dev.index if dev.index is not None else torch.cuda.current_device(),
+                torch.cuda.current_stream(dev).cuda_stream)
+    p = lambda X: None if X is None else _vp(X.data_ptr())  # noqa: E731
+    rc = lib().jsvd_svd_backward(h, b, m, n, p(Uc), p(Sc), p(Vc), p(dUc), p(dSc), p(dVc),
+                                 p(dA))
+    if rc:
+        raise JsvdError(rc, "jsvd_svd_backward")
+    dA = dA.transpose(-1, -2)
+    return dA if batched else dA[0]

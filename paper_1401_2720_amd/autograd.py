@@ -1,0 +1,58 @@
+"""Differentiable Jacobi SVD: a torch.autograd.Function over the C ABI.
+
+Forward: jsvd_gesvd for one matrix, jsvd_gesvd_batched for a batch of equally
+sized matrices with n <= 256 (else one jsvd_gesvd per matrix).  Backward:
+jsvd_svd_backward (the SVD adjoint on FP64 MFMA products).  With
+recompute=True only A is kept for the backward and the forward is run again
+there (less memory, one more forward).
+"""
+import torch
+
+from . import _binding as B
+
+
+def _forward(A):
+    """(U, S, V) of A (m, n) or (b, m, n), float64 CUDA."""
+    if A.dim() == 2:
+        U, S, V, _ = B.gesvd(A)
+        return U, S, V
+    b, m, n = A.shape
+    if n <= 256:
+        batch = B.Batch.from_uniform(A)
+        B.gesvd_batched(batch, restore=False)
+        Ub = batch.A.view(b, n, m).transpose(-1, -2)
+        Sb = batch.S.view(b, n)
+        Vb = batch.V.view(b, n, n).transpose(-1, -2)
+        if int(batch.status.abs().sum()) != 0:
+            raise B.JsvdError(1, "jsvd_gesvd_batched")
+        return Ub, Sb, Vb
+    outs = [B.gesvd(A[i])[:3] for i in range(b)]
+    return tuple(torch.stack([o[k] for o in outs]) for k in range(3))
+
+
+class JacobiSVD(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, A, recompute=False):
+        U, S, V = _forward(A)
+        ctx.recompute = recompute
+        if recompute:
+            ctx.save_for_backward(A)
+        else:
+            ctx.save_for_backward(U, S, V)
+        ctx.set_materialize_grads(False)
+        return U, S, V
+
+    @staticmethod
+    def backward(ctx, gU, gS, gV):
+        if ctx.recompute:
+            (A,) = ctx.saved_tensors
+            U, S, V = _forward(A.detach())
+        else:
+            U, S, V = ctx.saved_tensors
+        dA = B.svd_backward(U, S, V, gU, gS, gV)
+        return dA, None
+
+
+def svd(A, recompute=False):
+    """U, S, V with A = U diag(S) V^T (economy), differentiable."""
+    return JacobiSVD.apply(A, recompute)

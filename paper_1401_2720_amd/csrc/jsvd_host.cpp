@@ -30,6 +30,15 @@ struct jsvd_handle_s {
     unsigned long long *host_counters = nullptr;  // pinned
     std::map<std::pair<int, int>, DeviceTable> block_tables;  // (order, kind) -> int2[]
     std::map<std::pair<int, int>, DeviceTable> inner_tables;  // (bw, kind) -> uchar[]
+    // batched path: strategy tables of every order up to kBatchMaxN
+    void *batch_tables = nullptr;   // uchar pairs
+    void *batch_meta = nullptr;     // int tbl_order[kBatchMaxN+1], int64 tbl_off[kBatchMaxN/2+1]
+    int cu_count = 0;
+    // per-kernel timing (measurement aid): 4 events per p-step
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    double kernel_ms[3] = {0, 0, 0};
+    int64_t launches[3] = {0, 0, 0};
 };
 
 namespace {
@@ -155,9 +164,10 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     const int nsteps = order - 1;
     const bool want_v = o.want_v != 0;
 
-    // Gram row splits and update row chunks: aim at ~4 workgroups per CU.
+    // Gram row splits (at most 16, the inner kernel's limit) and update row
+    // chunks: aim at a few workgroups per CU.
     const int target_wg = 1024;
-    int splits = std::max(1, target_wg / npairs);
+    int splits = std::min(16, std::max(1, 512 / npairs));
     int64_t rps = align_up((size_t)((m + splits - 1) / splits), 64);
     splits = (int)((m + rps - 1) / rps);
     const int64_t upd_total_rows = m + (want_v ? n : 0);
@@ -205,17 +215,40 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     inf.n_blocks = order;
     int status = JSVD_OK;
     bool converged = false;
+    if (h->timing) {
+        while (h->events.size() < (size_t)4 * nsteps) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            h->events.push_back(e);
+        }
+    }
     for (int sweep = 0; sweep < o.max_sweeps; ++sweep) {
         HIP_TRY(launch_reset_counters(a.counters, st));
         for (int s = 0; s < nsteps; ++s) {
             a.pairs = blk + (size_t)s * npairs;
+            hipEvent_t *ev = h->timing ? &h->events[(size_t)4 * s] : nullptr;
+            if (ev) HIP_TRY(hipEventRecord(ev[0], st));
             HIP_TRY(launch_gram(bw, a, st));
+            if (ev) HIP_TRY(hipEventRecord(ev[1], st));
             HIP_TRY(launch_inner(bw, a, st));
+            if (ev) HIP_TRY(hipEventRecord(ev[2], st));
             HIP_TRY(launch_update(bw, a, st));
+            if (ev) HIP_TRY(hipEventRecord(ev[3], st));
         }
         HIP_TRY(hipMemcpyAsync(h->host_counters, a.counters, C_COUNT * sizeof(unsigned long long),
                                hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
+        if (h->timing) {
+            for (int s = 0; s < nsteps; ++s) {
+                hipEvent_t *ev = &h->events[(size_t)4 * s];
+                for (int k = 0; k < 3; ++k) {
+                    float ms = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+                    h->kernel_ms[k] += ms;
+                    h->launches[k] += 1;
+                }
+            }
+        }
         const unsigned long long *c = h->host_counters;
         inf.sweeps = sweep + 1;
         inf.rotations += (int64_t)c[C_ROT];
@@ -319,7 +352,10 @@ int jsvd_destroy(jsvd_handle_t h) {
     if (h->ws) (void)hipFree(h->ws);
     for (auto &kv : h->block_tables) (void)hipFree(kv.second.ptr);
     for (auto &kv : h->inner_tables) (void)hipFree(kv.second.ptr);
+    if (h->batch_tables) (void)hipFree(h->batch_tables);
+    if (h->batch_meta) (void)hipFree(h->batch_meta);
     if (h->host_counters) (void)hipHostFree(h->host_counters);
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     delete h;
     return JSVD_OK;
 }
@@ -394,6 +430,192 @@ int jsvd_strategy_table(int32_t order, int32_t kind, int32_t *pairs) {
 
 int32_t jsvd_strategy_order(int32_t nb) { return strategy_order(nb); }
 
+int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t max_n,
+                       const int32_t *m, const int32_t *n, const int64_t *a_off,
+                       const int64_t *s_off, const int64_t *v_off, double *A, double *S,
+                       double *V, const jsvd_opts *opts, int32_t *status, int32_t *sweeps) {
+    const jsvd_opts o = opts ? *opts : defaults();
+    if (!h) return -1;
+    if (batch < 0) return -2;
+    if (max_m < 1 || max_m > (1 << 20)) return -3;
+    if (max_n < 1 || max_n > kBatchMaxN || max_n > max_m) return -4;
+    if (!m) return -5;
+    if (!n) return -6;
+    if (!a_off) return -7;
+    if (!s_off) return -8;
+    if (o.want_v && !v_off) return -9;
+    if (!A) return -10;
+    if (!S) return -11;
+    if (o.want_v && !V) return -12;
+    if (o.max_sweeps < 1) return -13;
+    if (batch == 0) return JSVD_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
+    hipStream_t st = h->stream;
+
+    if (!h->batch_tables) {
+        // tables of every supported order <= strategy_order(kBatchMaxN), R-reverse
+        std::vector<unsigned char> flat;
+        std::vector<int> tbl_order(kBatchMaxN + 1, 2);
+        const int top = strategy_order(kBatchMaxN);
+        std::vector<int64_t> tbl_off(top / 2 + 1, 0);
+        for (int N = 2; N <= top; N += 2) {
+            if (strategy_order(N) != N) continue;
+            Table t;
+            if (!make_table(N, JSVD_STRAT_RREV, t)) return JSVD_HIP_ERROR;
+            tbl_off[N / 2] = (int64_t)flat.size();
+            for (const auto &stp : t)
+                for (const auto &pr : stp) {
+                    flat.push_back((unsigned char)pr.first);
+                    flat.push_back((unsigned char)pr.second);
+                }
+        }
+        for (int k = 1; k <= kBatchMaxN; ++k) tbl_order[k] = strategy_order(k);
+        HIP_TRY(hipMalloc(&h->batch_tables, flat.size()));
+        HIP_TRY(hipMemcpy(h->batch_tables, flat.data(), flat.size(), hipMemcpyHostToDevice));
+        const size_t meta = align_up(tbl_order.size() * sizeof(int), 256) +
+                            tbl_off.size() * sizeof(int64_t);
+        HIP_TRY(hipMalloc(&h->batch_meta, meta));
+        HIP_TRY(hipMemcpy(h->batch_meta, tbl_order.data(), tbl_order.size() * sizeof(int),
+                          hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(static_cast<char *>(h->batch_meta) +
+                              align_up(tbl_order.size() * sizeof(int), 256),
+                          tbl_off.data(), tbl_off.size() * sizeof(int64_t),
+                          hipMemcpyHostToDevice));
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, h->device));
+        h->cu_count = prop.multiProcessorCount;
+    }
+    const int grid = (int)std::min<int64_t>(batch, 2 * (int64_t)std::max(1, h->cu_count));
+    const int64_t scratch_per_wg = (int64_t)max_m * max_n + (int64_t)max_n * max_n;
+    const size_t off_hist = 0;
+    const size_t off_order = align_up((size_t)(kBatchMaxN + 1) * sizeof(int), 256);
+    const size_t off_queue = off_order + align_up((size_t)batch * sizeof(int32_t), 256);
+    const size_t off_scratch = off_queue + 256;
+    const size_t total = off_scratch + (size_t)grid * scratch_per_wg * sizeof(double);
+    int rc = ensure_workspace(h, total);
+    if (rc) return rc;
+    char *ws = static_cast<char *>(h->ws);
+
+    BatchArgs b;
+    b.count = batch;
+    b.m = m;
+    b.n = n;
+    b.a_off = a_off;
+    b.s_off = s_off;
+    b.v_off = o.want_v ? v_off : nullptr;
+    b.A = A;
+    b.S = S;
+    b.V = o.want_v ? V : nullptr;
+    b.order = reinterpret_cast<int32_t *>(ws + off_order);
+    b.queue = reinterpret_cast<int *>(ws + off_queue);
+    b.tbl_order = static_cast<const int *>(h->batch_meta);
+    b.tbl_off = reinterpret_cast<const int64_t *>(
+        static_cast<char *>(h->batch_meta) + align_up((kBatchMaxN + 1) * sizeof(int), 256));
+    b.tbls = static_cast<const unsigned char *>(h->batch_tables);
+    b.scratch = reinterpret_cast<double *>(ws + off_scratch);
+    b.scratch_per_wg = scratch_per_wg;
+    b.max_sweeps = o.max_sweeps;
+    b.status = status;
+    b.sweeps = sweeps;
+    HIP_TRY(launch_batched(b, grid, max_n, reinterpret_cast<int *>(ws + off_hist),
+                           reinterpret_cast<int32_t *>(ws + off_order), st));
+    return JSVD_OK;
+}
+
+int jsvd_svd_backward(jsvd_handle_t h, int64_t batch, int64_t m, int64_t n, const double *U,
+                      const double *S, const double *V, const double *dU, const double *dS,
+                      const double *dV, double *dA) {
+    if (!h) return -1;
+    if (batch < 1) return -2;
+    if (m < 1 || m < n || m > (1 << 24)) return -3;
+    if (n < 1 || n > 32768) return -4;
+    if (!U) return -5;
+    if (!S) return -6;
+    if (!V) return -7;
+    if (!dA) return -11;
+    if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
+    hipStream_t st = h->stream;
+    const size_t nn = (size_t)n * n;
+    const size_t off_J = 0;
+    const size_t off_K = off_J + align_up((size_t)batch * nn * sizeof(double), 256);
+    const size_t off_M = off_K + align_up((size_t)batch * nn * sizeof(double), 256);
+    const size_t off_T = off_M + align_up((size_t)batch * nn * sizeof(double), 256);
+    const size_t off_inv = off_T + align_up((size_t)batch * m * n * sizeof(double), 256);
+    const size_t off_flag = off_inv + align_up((size_t)batch * n * sizeof(double), 256);
+    int rc = ensure_workspace(h, off_flag + 256);
+    if (rc) return rc;
+    char *ws = static_cast<char *>(h->ws);
+    double *J = dU ? reinterpret_cast<double *>(ws + off_J) : nullptr;
+    double *K = dV ? reinterpret_cast<double *>(ws + off_K) : nullptr;
+    double *Mp = reinterpret_cast<double *>(ws + off_M);
+    double *T = reinterpret_cast<double *>(ws + off_T);
+    double *inv_s = reinterpret_cast<double *>(ws + off_inv);
+    int *flag = reinterpret_cast<int *>(ws + off_flag);
+
+    GemmArgs g;
+    g.batch = batch;
+    g.E = nullptr;
+    g.d = nullptr;
+    g.lde = g.se = g.sd = 0;
+    if (dU) {  // J = U^T dU  (n x n)
+        g.M = (int)n; g.N = (int)n; g.K = (int)m; g.ta = true; g.tb = false;
+        g.A = U; g.lda = m; g.sa = m * n;
+        g.B = dU; g.ldb = m; g.sb = m * n;
+        g.C = J; g.ldc = n; g.sc = (int64_t)nn;
+        HIP_TRY(launch_gemm(g, st));
+    }
+    if (dV) {  // K = V^T dV  (n x n)
+        g.M = (int)n; g.N = (int)n; g.K = (int)n; g.ta = true; g.tb = false;
+        g.A = V; g.lda = n; g.sa = (int64_t)nn;
+        g.B = dV; g.ldb = n; g.sb = (int64_t)nn;
+        g.C = K; g.ldc = n; g.sc = (int64_t)nn;
+        HIP_TRY(launch_gemm(g, st));
+    }
+    HIP_TRY(launch_adjoint_middle(batch, (int)n, S, n, dS, J, K, Mp, inv_s, flag, st));
+    // T = U M' + dU diag(1/s)  (m x n)
+    g.M = (int)m; g.N = (int)n; g.K = (int)n; g.ta = false; g.tb = false;
+    g.A = U; g.lda = m; g.sa = m * n;
+    g.B = Mp; g.ldb = n; g.sb = (int64_t)nn;
+    g.C = T; g.ldc = m; g.sc = m * n;
+    if (dU) {
+        g.E = dU; g.lde = m; g.se = m * n;
+        g.d = inv_s; g.sd = n;
+    }
+    HIP_TRY(launch_gemm(g, st));
+    // dA = T V^T
+    g.E = nullptr; g.d = nullptr;
+    g.M = (int)m; g.N = (int)n; g.K = (int)n; g.ta = false; g.tb = true;
+    g.A = T; g.lda = m; g.sa = m * n;
+    g.B = V; g.ldb = n; g.sb = (int64_t)nn;
+    g.C = dA; g.ldc = m; g.sc = m * n;
+    HIP_TRY(launch_gemm(g, st));
+    int hflag = 0;
+    HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return hflag ? JSVD_DEGENERATE : JSVD_OK;
+}
+
+int jsvd_kernel_timing(jsvd_handle_t h, int enable) {
+    if (!h) return -1;
+    h->timing = enable != 0;
+    for (int k = 0; k < 3; ++k) {
+        h->kernel_ms[k] = 0.0;
+        h->launches[k] = 0;
+    }
+    return JSVD_OK;
+}
+
+int jsvd_kernel_times(jsvd_handle_t h, double *ms, int64_t *launches) {
+    if (!h) return -1;
+    if (!ms) return -2;
+    if (!launches) return -3;
+    for (int k = 0; k < 3; ++k) {
+        ms[k] = h->kernel_ms[k];
+        launches[k] = h->launches[k];
+    }
+    return JSVD_OK;
+}
+
 const char *jsvd_error_string(int code) {
     switch (code) {
     case JSVD_OK: return "success";
@@ -402,6 +624,7 @@ const char *jsvd_error_string(int code) {
     case JSVD_NONFINITE: return "non-finite value in the input or the iteration";
     case JSVD_HIP_ERROR: return "HIP runtime error";
     case JSVD_NO_MEMORY: return "device workspace allocation failed";
+    case JSVD_DEGENERATE: return "equal singular values: the adjoint is undefined";
     default: return code < 0 ? "invalid argument" : "unknown status";
     }
 }

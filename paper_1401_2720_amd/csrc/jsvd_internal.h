@@ -62,6 +62,46 @@ hipError_t launch_gram(int bw, const StepArgs &a, hipStream_t s);
 hipError_t launch_inner(int bw, const StepArgs &a, hipStream_t s);
 hipError_t launch_update(int bw, const StepArgs &a, hipStream_t s);
 
+// ------------------------------------------------------ batched small SVDs
+constexpr int kBatchMaxN = 256;  // largest n of a problem in the batched path
+
+struct BatchArgs {
+    int64_t count;
+    const int32_t *m, *n;                       // device, per problem
+    const int64_t *a_off, *s_off, *v_off;       // device, element offsets
+    double *A, *S, *V;                          // V may be null
+    const int32_t *order;                       // device, work order (by non-increasing n)
+    int *queue;                                 // device work counter
+    const int *tbl_order;                       // device [kBatchMaxN + 1]: strategy order for n
+    const int64_t *tbl_off;                     // device: offset of the order-N table at [N/2]
+    const unsigned char *tbls;                  // device: concatenated zero-based pair tables
+    double *scratch;                            // device, per workgroup
+    int64_t scratch_per_wg;                     // doubles
+    int max_sweeps;
+    int32_t *status, *sweeps;                   // device, per problem (may be null)
+};
+
+hipError_t launch_batched(const BatchArgs &b, int grid, int max_n, int *hist, int32_t *order,
+                          hipStream_t s);
+
+// ------------------------------------------------------------ SVD adjoint
+struct GemmArgs {
+    int64_t batch;
+    int M, N, K;                 // C (M x N) = op(A) (M x K) op(B) (K x N)
+    bool ta, tb;                 // op = transpose
+    const double *A, *B;
+    int64_t lda, ldb, sa, sb;    // leading dimensions and batch strides (elements)
+    double *C;
+    int64_t ldc, sc;
+    const double *E, *d;         // optional: C += E diag(d)
+    int64_t lde, se, sd;
+};
+
+hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
+hipError_t launch_adjoint_middle(int64_t batch, int n, const double *s, int64_t ss,
+                                 const double *ds, const double *J, const double *K, double *Mp,
+                                 double *inv_s, int *degenerate, hipStream_t st);
+
 hipError_t launch_reset_counters(unsigned long long *c, hipStream_t s);
 hipError_t launch_init_identity(double *V, int64_t ldv, int64_t n, hipStream_t s);
 hipError_t launch_colnorms(const double *G, int64_t ldg, int64_t m, int64_t n, double *s_out,

@@ -151,42 +151,46 @@ __device__ __forceinline__ void rotation(double hpp, double hqq, double hpq, int
     cs = (act >= kSqrt2OverEps) ? 1.0 : act / sqrt(fma(act, act, tt));
 }
 
-template <int WIDTH>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-    for (int mask = 1; mask < WIDTH; mask <<= 1) v += __shfl_xor(v, mask, 64);
-    return v;
+// Sum over the 32 lanes of a half wave, identical in every lane: each level
+// adds the value of a partner lane whose own partial sum is the mirror image
+// (lane l <-> l^1, l^2, 7-l, 15-l within a row, l^16), so both lanes add the
+// same two numbers.  Needs all 64 lanes active.
+__device__ __forceinline__ double half_wave_sum(double v) {
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+    const long long x = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_ds_swizzle((int)x, 0x401F);         // lane ^ 16
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(x >> 32), 0x401F);
+    return v + __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
 // ---------------------------------------------------------------- inner
 // One workgroup per pivot block-pair.  BW = 2w.  R and V' live in LDS,
 // column-major with a padded leading dimension.  A p-step of the inner
-// strategy has BW/2 pivot pairs; every pair is handled by a group of BW
-// lanes (a half wave for BW = 32, a whole wave for BW = 64), lane x owning
-// row x of the pair's two columns of R and of V'.  The three dot products
-// of subphase 1 are butterfly sums over the group, identical in every lane.
+// strategy has BW/2 pivot pairs; every pair is handled by one half wave,
+// lane x owning rows x, x + 32, ... (BW/32 rows) of the pair's two columns of
+// R and of V'.  The three dot products of subphase 1 are half-wave sums.
 template <int BW>
-struct InnerCfg;
-template <>
-struct InnerCfg<32> {
-    static constexpr int kThreads = 512;  // 8 waves x 2 half-wave groups
-    static constexpr int kPairsPerLane = 1;
-};
-template <>
-struct InnerCfg<64> {
-    static constexpr int kThreads = 1024;  // 16 waves x 2 pairs each
-    static constexpr int kPairsPerLane = 2;
+struct InnerCfg {
+    static constexpr int kThreads = BW / 2 * 32;  // one half wave per pivot pair
+    static constexpr int kRows = BW / 32;         // rows per lane in the Jacobi steps
+    static constexpr int kOwn = BW / 16;          // Cholesky rows owned per thread
+    static constexpr int kMaxSplits = 16;         // Gram partial sums per pair, at most
 };
 
 template <int BW>
 __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs a) {
+    using Cfg = InnerCfg<BW>;
     constexpr int LD = BW + 1;
-    constexpr int NTHR = InnerCfg<BW>::kThreads;
-    constexpr int PPL = InnerCfg<BW>::kPairsPerLane;
-    constexpr int NWAVES = NTHR / 64;
+    constexpr int NTHR = Cfg::kThreads;
+    constexpr int ROWS = Cfg::kRows;
+    constexpr int OWN = Cfg::kOwn;
     __shared__ double R[BW * LD];
     __shared__ double Vp[BW * LD];
-    __shared__ int cnt[NWAVES][4];
+    __shared__ double hdiag[BW];
+    __shared__ int flags[2];  // [0] NaN met, [1] zero pivots
 
     const int pair = blockIdx.x;
     const int2 pq = a.pairs[pair];
@@ -196,156 +200,211 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
         return;
     }
 
-    // ---- sum of the partial Gram matrices, in split order
+    // ---- H_pq.  Thread t owns the upper-triangle entries (i, j), i <= j,
+    // with i = 16 o + t / BW and j = t % BW for o = 0 .. BW/16 - 1, so that
+    // each row of the Cholesky factor is produced by one (half) wave.  The
+    // partial Gram values of an entry are summed in split order.
+    const int jcol = tid % BW, ibase = tid / BW;
+    double h[OWN], di[OWN];
     const double *hp = a.hpart + (size_t)pair * a.splits * BW * BW;
-    for (int e = tid; e < BW * BW; e += NTHR) {
-        const int i = e / BW, j = e % BW;
-        if ((i >> 4) <= (j >> 4)) {
-            double s = 0.0;
-            for (int sp = 0; sp < a.splits; ++sp) s += hp[(size_t)sp * BW * BW + e];
+#pragma unroll
+    for (int o = 0; o < OWN; ++o) {
+        const int i = 16 * o + ibase;
+        double s = 0.0;
+        if (i <= jcol) {
+            double part[Cfg::kMaxSplits];
+            const double *src = hp + i * BW + jcol;
+#pragma unroll
+            for (int sp = 0; sp < Cfg::kMaxSplits; ++sp)
+                part[sp] = sp < a.splits ? src[(size_t)sp * BW * BW] : 0.0;
+#pragma unroll
+            for (int sp = 0; sp < Cfg::kMaxSplits; ++sp)
+                if (sp < a.splits) s += part[sp];
             // padding columns become unit vectors orthogonal to everything
-            if (pair_col(i, a.w, pq) >= a.n || pair_col(j, a.w, pq) >= a.n) s = (i == j) ? 1.0 : 0.0;
-            R[j * LD + i] = s;
+            if (pair_col(i, a.w, pq) >= a.n || pair_col(jcol, a.w, pq) >= a.n)
+                s = (i == jcol) ? 1.0 : 0.0;
+            if (i == jcol) hdiag[i] = s;
         }
+        h[o] = s;
     }
+    for (int e = tid; e < BW * BW; e += NTHR) {
+        const int i = e % BW, j = e / BW;
+        if (i > j) R[j * LD + i] = 0.0;
+        Vp[j * LD + i] = (i == j) ? 1.0 : 0.0;
+    }
+    if (tid < 2) flags[tid] = 0;
     __syncthreads();
+#pragma unroll
+    for (int o = 0; o < OWN; ++o) di[o] = hdiag[16 * o + ibase];
 
-    // ---- Cholesky H = R^T R on the upper triangle (Section 4.1, by rows of
-    // R).  A pivot that is not positive (H only semidefinite: a block with
-    // dependent columns) makes row k of R zero, which keeps R^T R = H for
-    // the positive semidefinite case; NaN aborts the pair.
+    // ---- Cholesky H = R^T R, row k of R at step k (Section 4.1).  Every
+    // owner of an entry of row i keeps its own copy of the current H(i,i)
+    // (updated by the same fma as the owner of that diagonal entry), so one
+    // barrier per step suffices.  A pivot that is not positive (H only
+    // semidefinite: dependent columns) makes row k of R zero.
     int zero_pivots = 0;
-    bool nonfinite = false;
     for (int k = 0; k < BW; ++k) {
-        const double hkk = R[k * LD + k];  // uniform: every thread reads the same value
-        if (hkk != hkk) {
-            nonfinite = true;
-            break;
-        }
-        if (hkk > 0.0) {
-            const double d = sqrt(hkk);
-            for (int j = k + tid; j < BW; j += NTHR) R[j * LD + k] = (j == k) ? d : R[j * LD + k] / d;
-        } else {
-            ++zero_pivots;
-            for (int j = k + tid; j < BW; j += NTHR) R[j * LD + k] = 0.0;
+        const int ok = k >> 4;
+        if ((k & 15) == ibase && jcol >= k) {
+#pragma unroll
+            for (int o = 0; o < OWN; ++o) {
+                if (o == ok) {
+                    const double hkk = di[o];
+                    double r = 0.0;
+                    if (hkk > 0.0) {
+                        const double d = sqrt(hkk);
+                        r = (jcol == k) ? d : h[o] / d;
+                    } else if (hkk != hkk) {
+                        flags[0] = 1;
+                    } else if (jcol == k) {
+                        ++zero_pivots;
+                    }
+                    R[jcol * LD + k] = r;
+                }
+            }
         }
         __syncthreads();
-        for (int e = tid; e < BW * BW; e += NTHR) {
-            const int i = e % BW, j = e / BW;
-            if (i > k && i <= j) R[j * LD + i] = fma(-R[i * LD + k], R[j * LD + k], R[j * LD + i]);
+        const double rkj = R[jcol * LD + k];
+#pragma unroll
+        for (int o = 0; o < OWN; ++o) {
+            const int i = 16 * o + ibase;
+            if (i > k && i <= jcol) {
+                const double rki = R[i * LD + k];
+                h[o] = fma(-rki, rkj, h[o]);
+                di[o] = fma(-rki, rki, di[o]);
+            }
         }
-        __syncthreads();
     }
-    if (nonfinite) {
+    if (zero_pivots) atomicAdd(&flags[1], zero_pivots);
+    __syncthreads();
+    if (flags[0]) {
         if (tid == 0) {
             a.pair_rot[pair] = 0;
             atomicAdd(&a.counters[C_NONFINITE], 1ull);
         }
         return;
     }
-    if (tid == 0 && zero_pivots) atomicAdd(&a.counters[C_BREAKDOWN], (unsigned long long)zero_pivots);
-    for (int e = tid; e < BW * BW; e += NTHR) {
-        const int i = e % BW, j = e / BW;
-        if (i > j) R[j * LD + i] = 0.0;
-        Vp[j * LD + i] = (i == j) ? 1.0 : 0.0;
-    }
-    __syncthreads();
+    if (tid == 0 && flags[1]) atomicAdd(&a.counters[C_BREAKDOWN], (unsigned long long)flags[1]);
 
-    // ---- inner Jacobi (Section 4.3)
+    // ---- inner Jacobi (Section 4.3).  A p-step runs in three phases:
+    //   A  every half wave loads its pair's columns of R (and V') and forms
+    //      the three dot products of subphase 1;
+    //   B  one wave, one lane per pivot pair, decides and computes the
+    //      rotations (subphases 2-5), so the long FP64 division and square
+    //      root chains run once per pair instead of once per half wave;
+    //   C  every half wave applies its pair's rotation (subphase 6).
     const int lane = tid & 63, wave = tid >> 6;
-    const int x = (BW == 32) ? (lane & 31) : lane;  // row owned by this lane
-    const double tol = kEps * sqrt((double)BW);     // c(eps) = eps sqrt(nhat), nhat = 2w
-    int rot_total = 0, proper_total = 0, clamp_total = 0, sweeps = 0;
+    const int x = lane & 31;                          // first row owned by this lane
+    const int slot = wave * 2 + (lane >> 5);          // pivot pair of this half wave
+    const double tol = kEps * sqrt((double)BW);       // c(eps) = eps sqrt(nhat), nhat = 2w
+    __shared__ double dots[BW / 2][3];
+    __shared__ double rot_mtn[BW / 2], rot_tn[BW / 2], rot_cs[BW / 2];
+    __shared__ int rot_code[BW / 2];                  // bit 0 rotate, 1 swap, 2 cs != 1
+    __shared__ int sweep_rot;
+    int rot_total = 0, proper_total = 0, clamp_total = 0, sweeps = 0;  // lanes of wave 0
 
     for (int sw = 0; sw < a.max_inner_sweeps; ++sw) {
-        int rot_sweep = 0;
+        int rot_sweep = 0;  // lanes of wave 0
         for (int st = 0; st < BW - 1; ++st) {
             const unsigned char *tbl = a.inner_tbl + (size_t)st * BW;  // BW/2 pairs x 2
-            int p[PPL], q[PPL];
-            double rp[PPL], rq[PPL], vp[PPL], vq[PPL];
-            double hpp[PPL], hqq[PPL], hpq[PPL];
+            const int p = tbl[2 * slot], q = tbl[2 * slot + 1];
+            double rp[ROWS], rq[ROWS], vp[ROWS], vq[ROWS];
+            double hpp = 0.0, hqq = 0.0, hpq = 0.0;
 #pragma unroll
-            for (int k = 0; k < PPL; ++k) {
-                const int slot = (BW == 32) ? wave * 2 + (lane >> 5) : wave * 2 + k;
-                p[k] = tbl[2 * slot];
-                q[k] = tbl[2 * slot + 1];
-                rp[k] = R[p[k] * LD + x];
-                rq[k] = R[q[k] * LD + x];
-                vp[k] = Vp[p[k] * LD + x];
-                vq[k] = Vp[q[k] * LD + x];
-                hpp[k] = rp[k] * rp[k];
-                hqq[k] = rq[k] * rq[k];
-                hpq[k] = rp[k] * rq[k];
+            for (int r = 0; r < ROWS; ++r) {
+                rp[r] = R[p * LD + x + 32 * r];
+                rq[r] = R[q * LD + x + 32 * r];
+                vp[r] = Vp[p * LD + x + 32 * r];
+                vq[r] = Vp[q * LD + x + 32 * r];
+                hpp = fma(rp[r], rp[r], hpp);
+                hqq = fma(rq[r], rq[r], hqq);
+                hpq = fma(rp[r], rq[r], hpq);
             }
-#pragma unroll
-            for (int k = 0; k < PPL; ++k) {
-                hpp[k] = group_sum<BW == 32 ? 32 : 64>(hpp[k]);
-                hqq[k] = group_sum<BW == 32 ? 32 : 64>(hqq[k]);
-                hpq[k] = group_sum<BW == 32 ? 32 : 64>(hpq[k]);
+            hpp = half_wave_sum(hpp);
+            hqq = half_wave_sum(hqq);
+            hpq = half_wave_sum(hpq);
+            if (x == 0) {
+                dots[slot][0] = hpp;
+                dots[slot][1] = hqq;
+                dots[slot][2] = hpq;
             }
-#pragma unroll
-            for (int k = 0; k < PPL; ++k) {
-                const int64_t kp = pair_col(p[k], a.w, pq), kq = pair_col(q[k], a.w, pq);
+            __syncthreads();
+
+            if (wave == 0 && lane < BW / 2) {
+                const int pp = tbl[2 * lane], qq = tbl[2 * lane + 1];
+                const double dpp = dots[lane][0], dqq = dots[lane][1], dpq = dots[lane][2];
+                const int64_t kp = pair_col(pp, a.w, pq), kq = pair_col(qq, a.w, pq);
                 const bool pad = kq >= a.n || kp >= a.n;
                 // subphase 2: relative orthogonality (reading: <= skips)
-                const bool rotate = !(fabs(hpq[k]) <= tol * sqrt(hpp[k]) * sqrt(hqq[k]));
+                const bool rotate = !(fabs(dpq) <= tol * sqrt(dpp) * sqrt(dqq));
                 // subphase 4: hyperbolic iff kp < n+ <= kq
                 const int t = (kp < a.n_plus && kq >= a.n_plus) ? -1 : 1;
-                double np = rp[k], nq = rq[k], nvp = vp[k], nvq = vq[k];
                 double tn = 0.0, cs = 1.0;
                 bool clamped = false;
-                if (rotate) {
-                    rotation(hpp[k], hqq[k], hpq[k], t, tn, cs, clamped);
-                    const double mtn = (t > 0) ? -tn : tn;  // (4.1) / (4.2)
-                    if (cs == 1.0) {
-                        np = fma(mtn, rq[k], rp[k]);
-                        nq = fma(tn, rp[k], rq[k]);
-                        nvp = fma(mtn, vq[k], vp[k]);
-                        nvq = fma(tn, vp[k], vq[k]);
-                    } else {
-                        np = cs * fma(mtn, rq[k], rp[k]);
-                        nq = cs * fma(tn, rp[k], rq[k]);
-                        nvp = cs * fma(mtn, vq[k], vp[k]);
-                        nvq = cs * fma(tn, vp[k], vq[k]);
-                    }
-                }
+                if (rotate) rotation(dpp, dqq, dpq, t, tn, cs, clamped);
                 // subphase 5: keep j*sigma^2 non-increasing for trigonometric
                 // pairs (h_pp' = h_pp - tn h_pq, h_qq' = h_qq + tn h_pq)
                 bool swap = false;
                 if (t > 0 && !pad) {
-                    const double npp = rotate ? fma(-tn, hpq[k], hpp[k]) : hpp[k];
-                    const double nqq = rotate ? fma(tn, hpq[k], hqq[k]) : hqq[k];
+                    const double npp = rotate ? fma(-tn, dpq, dpp) : dpp;
+                    const double nqq = rotate ? fma(tn, dpq, dqq) : dqq;
                     if (kq < a.n_plus)
                         swap = npp < nqq;
                     else if (kp >= a.n_plus)
                         swap = npp > nqq;
                 }
-                R[(swap ? q[k] : p[k]) * LD + x] = np;
-                R[(swap ? p[k] : q[k]) * LD + x] = nq;
-                Vp[(swap ? q[k] : p[k]) * LD + x] = nvp;
-                Vp[(swap ? p[k] : q[k]) * LD + x] = nvq;
-                // counts: one per pair (the lanes of a group agree)
-                int r = rotate ? 1 : 0, pr = (rotate && cs != 1.0) ? 1 : 0, cl = clamped ? 1 : 0;
-                if (BW == 32) {
-                    r = __builtin_amdgcn_readlane(r, 0) + __builtin_amdgcn_readlane(r, 32);
-                    pr = __builtin_amdgcn_readlane(pr, 0) + __builtin_amdgcn_readlane(pr, 32);
-                    cl = __builtin_amdgcn_readlane(cl, 0) + __builtin_amdgcn_readlane(cl, 32);
+                rot_mtn[lane] = (t > 0) ? -tn : tn;  // coefficient of column q in the new p
+                rot_tn[lane] = tn;
+                rot_cs[lane] = cs;
+                rot_code[lane] = (rotate ? 1 : 0) | (swap ? 2 : 0) | (cs != 1.0 ? 4 : 0);
+                rot_sweep += rotate ? 1 : 0;
+                proper_total += (rotate && cs != 1.0) ? 1 : 0;
+                clamp_total += clamped ? 1 : 0;
+            }
+            __syncthreads();
+
+            const int code = rot_code[slot];
+            if (code & 1) {
+                const double mtn = rot_mtn[slot], tn = rot_tn[slot], cs = rot_cs[slot];
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) {
+                    const double a0 = rp[r], b0 = rq[r], c0 = vp[r], d0 = vq[r];
+                    if (code & 4) {
+                        rp[r] = cs * fma(mtn, b0, a0);
+                        rq[r] = cs * fma(tn, a0, b0);
+                        vp[r] = cs * fma(mtn, d0, c0);
+                        vq[r] = cs * fma(tn, c0, d0);
+                    } else {  // cs == 1: the multiplication is omitted
+                        rp[r] = fma(mtn, b0, a0);
+                        rq[r] = fma(tn, a0, b0);
+                        vp[r] = fma(mtn, d0, c0);
+                        vq[r] = fma(tn, c0, d0);
+                    }
                 }
-                rot_sweep += r;
-                proper_total += pr;
-                clamp_total += cl;
+            }
+            if (code & 3) {
+                const int cp = (code & 2) ? q : p, cq = (code & 2) ? p : q;
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) {
+                    R[cp * LD + x + 32 * r] = rp[r];
+                    R[cq * LD + x + 32 * r] = rq[r];
+                    Vp[cp * LD + x + 32 * r] = vp[r];
+                    Vp[cq * LD + x + 32 * r] = vq[r];
+                }
             }
             __syncthreads();
         }
         ++sweeps;
-        rot_total += rot_sweep;
-        if (lane == 0) cnt[wave][0] = rot_sweep;
-        __syncthreads();
-        int all = 0;
+        if (wave == 0) {
+            int all = rot_sweep;  // sum over the lanes of wave 0
 #pragma unroll
-        for (int wv = 0; wv < NWAVES; ++wv) all += cnt[wv][0];
+            for (int off = 1; off < 64; off <<= 1) all += __shfl_xor(all, off, 64);
+            rot_total += rot_sweep;
+            if (lane == 0) sweep_rot = all;
+        }
         __syncthreads();
-        if (all == 0) break;  // no rotation in the inner sweep
+        if (sweep_rot == 0) break;  // no rotation in the inner sweep
+        __syncthreads();
     }
 
     // ---- write V'_pq and the counts
@@ -354,25 +413,22 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
         const int i = e % BW, j = e / BW;
         vout[j * BW + i] = Vp[j * LD + i];
     }
-    if (lane == 0) {
-        cnt[wave][0] = rot_total;
-        cnt[wave][1] = proper_total;
-        cnt[wave][2] = clamp_total;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        long long r = 0, pr = 0, cl = 0;
-        for (int wv = 0; wv < NWAVES; ++wv) {
-            r += cnt[wv][0];
-            pr += cnt[wv][1];
-            cl += cnt[wv][2];
+    if (wave == 0) {
+        int r = rot_total, pr = proper_total, cl = clamp_total;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            r += __shfl_xor(r, off, 64);
+            pr += __shfl_xor(pr, off, 64);
+            cl += __shfl_xor(cl, off, 64);
         }
-        a.pair_rot[pair] = (int)r;
-        atomicAdd(&a.counters[C_ROT], (unsigned long long)r);
-        atomicAdd(&a.counters[C_PROPER], (unsigned long long)pr);
-        atomicAdd(&a.counters[C_CLAMP], (unsigned long long)cl);
-        atomicAdd(&a.counters[C_INNER_SW], (unsigned long long)sweeps);
-        if (r) atomicAdd(&a.counters[C_UPDATES], 1ull);
+        if (lane == 0) {
+            a.pair_rot[pair] = r;
+            atomicAdd(&a.counters[C_ROT], (unsigned long long)r);
+            atomicAdd(&a.counters[C_PROPER], (unsigned long long)pr);
+            atomicAdd(&a.counters[C_CLAMP], (unsigned long long)cl);
+            atomicAdd(&a.counters[C_INNER_SW], (unsigned long long)sweeps);
+            if (r) atomicAdd(&a.counters[C_UPDATES], 1ull);
+        }
     }
 }
 
