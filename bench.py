@@ -35,9 +35,11 @@ def parse():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--block-w", type=int, default=0)
     ap.add_argument("--strategy", default="rrev")
-    ap.add_argument("--max-inner-sweeps", type=int, default=30)
+    ap.add_argument("--max-inner-sweeps", type=int, default=0, help="0 = library's choice")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the oracle sample (0 = skip)")
+    ap.add_argument("--workload", default="svd4096", choices=["svd4096", "batched", "backward"],
+                    help="svd4096: the benchmark line; batched / backward: the other forms")
     return ap.parse_args()
 
 
@@ -61,6 +63,25 @@ def kernel_roofline(name, avg_ms, per_launch, w):
     return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
             "intensity_flop_per_byte": flops / bytes_, "bw": bw}
+
+
+def measured_traffic(kernel_name, w):
+    """HBM bytes per launch of a p-step kernel from the committed rocprofv3
+    counter summary, or None when there is none for this kernel or the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_1401_2720_amd", "csrc", "jsvd_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    entry = rec.get("kernels", {}).get(f"{kernel_name}_kernel<{2 * w}>")
+    if entry is None or rec.get("source_sha256") != sha:
+        return None
+    return entry["hbm_bytes_per_launch"]
 
 
 def cpu_baseline(A, sweeps, target_s):
@@ -87,12 +108,131 @@ def cpu_baseline(A, sweeps, target_s):
                        f"time x {sweeps} sweeps (the GPU run's sweep count)")}
 
 
+def bench_batched(args):
+    """10,000 uneven problems (n ~ U{8..128}, m = n + U{0..64}, 20 % graded),
+    one persistent launch captured in a HIP graph and replayed."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1401_2720_amd as jsvd
+    from paper_1401_2720_amd import inputs
+    data = inputs.ragged_batch()
+    b = jsvd.Batch(data["mats"])
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(max(1, args.warmup)):
+            jsvd.gesvd_batched(b)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        jsvd.gesvd_batched(b)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(args.steps):
+        graph.replay()
+    stop.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) / args.steps * 1e3
+    sw = b.sweeps.cpu().numpy().astype(np.float64)
+    m = b.m_host.astype(np.float64)
+    n = b.n_host.astype(np.float64)
+    # algorithmic flops: per sweep n(n-1)/2 pairs x (dots 6m + rotation of G and V 6(m+n))
+    flops = float(np.sum(sw * n * (n - 1) / 2 * (6 * m + 6 * (m + n))))
+    achieved = flops / (ms * 1e-3) / 1e12
+    status = int(b.status.abs().sum())
+    cpu = None
+    if args.cpu_seconds > 0:
+        # oracle on the problems in index order (one per OpenMP thread) until
+        # the sample reaches the target time, scaled to problems per second
+        mats = data["mats"]
+        done, t_cpu, k = 0, 0.0, 64
+        while t_cpu < args.cpu_seconds and done < len(mats):
+            chunk = mats[done:done + k]
+            c0 = time.perf_counter()
+            oracle.gesvj_many(chunk)
+            t_cpu += time.perf_counter() - c0
+            done += len(chunk)
+            k *= 2
+        cpu = {"value": done / t_cpu, "unit": "SVDs/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": f"first {done} of the 10000 problems ({t_cpu:.1f} s)"}
+    out = {"metric": "batched small SVDs/s", "value": 10000 / (ms * 1e-3), "unit": "SVDs/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "batched_10000_ragged_n8-128", "seed": 5, "graph": True,
+                      "sweeps_mean": float(sw.mean()), "sweeps_max": int(sw.max()),
+                      "not_converged": status},
+           "roofline": {"kernel": "batched", "bound": "alu", "achieved": achieved,
+                        "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                        "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                        "algorithmic_flops_per_launch": flops},
+           "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+def bench_backward(args):
+    """Forward + backward of the differentiable SVD: 256 x (64 x 64) and one
+    1024 x 1024, loss sum w_i s_i + ||U_k V_k^T o W||_F^2, k = 8."""
+    import torch
+
+    import paper_1401_2720_amd as jsvd
+    from paper_1401_2720_amd import inputs
+    d = inputs.differentiable_set()
+    res = {}
+    for name, A, w, W in [("256x64x64", d["small"], d["w_small"], d["W_small"]),
+                          ("1024x1024", d["large"], d["w_large"], d["W_large"])]:
+        A = torch.from_numpy(A).cuda()
+        w = torch.from_numpy(w).cuda()
+        W = torch.from_numpy(W).cuda()
+        fwd, bwd = [], []
+        for it in range(args.warmup + args.steps):
+            X = A.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            U, S, V = jsvd.svd(X)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            P = U[..., :, :8] @ V[..., :, :8].transpose(-1, -2)
+            L = (w * S).sum() + ((P * W) ** 2).sum()
+            L.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if it >= args.warmup:
+                fwd.append(t1 - t0)
+                bwd.append(t2 - t1)
+        b = A.shape[0] if A.dim() == 3 else 1
+        n = A.shape[-1]
+        res[name] = {"forward_ms": 1e3 * sum(fwd) / len(fwd),
+                     "loss_backward_ms": 1e3 * sum(bwd) / len(bwd),
+                     "backward_gemm_flops": b * 8.0 * n ** 3}
+    total_ms = sum(v["forward_ms"] + v["loss_backward_ms"] for v in res.values())
+    out = {"metric": "differentiable SVD forward+backward time", "value": total_ms / 1e3,
+           "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": total_ms, "higher_is_better": False, "scaling": "strong",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "svd_backward_256x64x64_and_1024x1024", "seed": 6, "k": 8,
+                      "parts": res},
+           "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU level is not part of "
               "it); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "backward":
+        return bench_backward(args)
     import numpy as np
     import torch
 
@@ -165,6 +305,9 @@ def main():
     roof = kernel_roofline(dominant, avg[dominant], per_launch, w)
     roof["avg_launch_us"] = avg[dominant] * 1e3
     roof["launches"] = kt[dominant][1]
+    roof["traffic"] = measured_traffic(dominant, w)
+    roof["algorithmic_per_launch"] = {k: v for k, v in per_launch.items()
+                                      if k.startswith(dominant)}
 
     # accuracy of the last step against properties that hold at any size
     Ucm = work.t()

@@ -58,7 +58,8 @@ typedef struct jsvd_handle_s *jsvd_handle_t;
 typedef struct {
     int32_t block_w;          /* block-column width w: 0 = choose by size, else 16 or 32 */
     int32_t strategy;         /* JSVD_STRAT_* (default JSVD_STRAT_RREV) */
-    int32_t max_inner_sweeps; /* M_s of Section 4.3: 1 = block-oriented, default 30 = full block */
+    int32_t max_inner_sweeps; /* M_s of Section 4.3: 0 = choose (default: 1), 1 = block-oriented,
+                                 > 1 = full block (the paper's setting is 30) */
     int32_t max_sweeps;       /* limit on block sweeps (default 30) */
     int32_t want_v;           /* 1 = accumulate V (default), 0 = do not touch V */
     int32_t sort;             /* 1 = order the output (default), 0 = column order as computed */
@@ -140,7 +141,7 @@ int jsvd_hsvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
  * pointwise to each problem in the p-steps of the closest parallel strategy
  * of Section 3), in one persistent launch: workgroups pull problems from a
  * device queue, largest n first, and each runs its problem to its own
- * convergence (a sweep with no rotation) or opts->max_sweeps.
+ * convergence (a sweep with no proper rotation, Section 4.5) or opts->max_sweeps.
  *   batch        : number of problems (0 is allowed: nothing is done).
  *   max_m, max_n : host bounds on the sizes, 1 <= max_n <= 256, max_n <= max_m;
  *                  they size the per-workgroup scratch.

@@ -109,7 +109,7 @@ def _handle(device_index, stream_ptr):
     return h
 
 
-def make_opts(block_w=0, strategy="rrev", max_inner_sweeps=30, max_sweeps=30, want_v=True,
+def make_opts(block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,
               sort=True):
     o = Opts()
     lib().jsvd_default_opts(ctypes.byref(o))
@@ -135,7 +135,7 @@ def _raise_on(rc, what, allow):
         raise JsvdError(rc, what)
 
 
-def gesvd(A, block_w=0, strategy="rrev", max_inner_sweeps=30, max_sweeps=30, want_v=True,
+def gesvd(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,
           sort=True, allow=(1,)):
     """SVD A = U diag(S) V^T of a float64 CUDA tensor (m >= n).
 
@@ -163,7 +163,7 @@ def gesvd(A, block_w=0, strategy="rrev", max_inner_sweeps=30, max_sweeps=30, wan
     return work.t(), S, (Vb.t() if want_v else None), d
 
 
-def hsvd(G, J, block_w=0, strategy="rrev", max_inner_sweeps=30, max_sweeps=30, want_v=True,
+def hsvd(G, J, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,
          sort=True, allow=(1,)):
     """Hyperbolic SVD G V = U diag(S), V^T J V = diag(J_out).
 

@@ -34,6 +34,7 @@ struct jsvd_handle_s {
     void *batch_tables = nullptr;   // uchar pairs
     void *batch_meta = nullptr;     // int tbl_order[kBatchMaxN+1], int64 tbl_off[kBatchMaxN/2+1]
     int cu_count = 0;
+    int batch_lds = 0;              // dynamic LDS bytes of the batched kernel
     // per-kernel timing (measurement aid): 4 events per p-step
     bool timing = false;
     std::vector<hipEvent_t> events;
@@ -112,16 +113,26 @@ jsvd_opts defaults() {
     jsvd_opts o;
     o.block_w = 0;
     o.strategy = JSVD_STRAT_RREV;
-    o.max_inner_sweeps = 30;
+    o.max_inner_sweeps = 0;
     o.max_sweeps = 30;
     o.want_v = 1;
     o.sort = 1;
     return o;
 }
 
+// Block width and inner sweep limit when the caller leaves them to the
+// library (measured on MI355X: 2w = 64 pays off once the p-steps' HBM
+// traffic dominates, from n of about 3000; the block-oriented variant,
+// M_s = 1, was faster than the full block one at every size measured).
 int choose_w(int64_t m, int64_t n) {
     (void)m;
-    return n >= 1024 ? 32 : 16;
+    return n >= 3072 ? 32 : 16;
+}
+
+int choose_inner_sweeps(int64_t m, int64_t n) {
+    (void)m;
+    (void)n;
+    return 1;
 }
 
 // Workspace carve-up for one solve.
@@ -202,7 +213,7 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     a.pair_rot = reinterpret_cast<int *>(ws + L.pair_rot);
     a.counters = reinterpret_cast<unsigned long long *>(ws + L.counters);
     a.inner_tbl = inner;
-    a.max_inner_sweeps = std::max(1, o.max_inner_sweeps);
+    a.max_inner_sweeps = o.max_inner_sweeps > 0 ? o.max_inner_sweeps : choose_inner_sweeps(m, n);
     a.upd_rows = (int)upd_rows;
     a.upd_chunks_g = (int)((m + upd_rows - 1) / upd_rows);
     a.upd_chunks_v = want_v ? (int)((n + upd_rows - 1) / upd_rows) : 0;
@@ -310,7 +321,7 @@ int check_common(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
     if (lda < m) return -5;
     if (o.block_w != 0 && o.block_w != 16 && o.block_w != 32) return -9;
     if (o.strategy < JSVD_STRAT_RREV || o.strategy > JSVD_STRAT_C) return -9;
-    if (o.max_sweeps < 1 || o.max_inner_sweeps < 1) return -9;
+    if (o.max_sweeps < 1 || o.max_inner_sweeps < 0) return -9;
     if (m > (int64_t)1 << 31 || n > (int64_t)1 << 20) return -2;
     return JSVD_OK;
 }
@@ -484,8 +495,13 @@ int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t ma
         hipDeviceProp_t prop;
         HIP_TRY(hipGetDeviceProperties(&prop, h->device));
         h->cu_count = prop.multiProcessorCount;
+        // LDS for the working copy of G: what the CU has, less the static part
+        const size_t lds_total = prop.sharedMemPerMultiprocessor ? prop.sharedMemPerMultiprocessor
+                                                                 : prop.sharedMemPerBlock;
+        h->batch_lds = (int)std::min<size_t>(lds_total, 160 * 1024) - 8 * 1024;
+        if (h->batch_lds < 0 || batched_set_lds(h->batch_lds) != hipSuccess) h->batch_lds = 0;
     }
-    const int grid = (int)std::min<int64_t>(batch, 2 * (int64_t)std::max(1, h->cu_count));
+    const int grid = (int)std::min<int64_t>(batch, std::max(1, h->cu_count));
     const int64_t scratch_per_wg = (int64_t)max_m * max_n + (int64_t)max_n * max_n;
     const size_t off_hist = 0;
     const size_t off_order = align_up((size_t)(kBatchMaxN + 1) * sizeof(int), 256);
@@ -517,6 +533,7 @@ int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t ma
     b.max_sweeps = o.max_sweeps;
     b.status = status;
     b.sweeps = sweeps;
+    b.lds_doubles = h->batch_lds / (int64_t)sizeof(double);
     HIP_TRY(launch_batched(b, grid, max_n, reinterpret_cast<int *>(ws + off_hist),
                            reinterpret_cast<int32_t *>(ws + off_order), st));
     return JSVD_OK;

@@ -79,7 +79,10 @@ struct BatchArgs {
     int64_t scratch_per_wg;                     // doubles
     int max_sweeps;
     int32_t *status, *sweeps;                   // device, per problem (may be null)
+    int64_t lds_doubles;                        // problems with m n <= this work in LDS
 };
+
+hipError_t batched_set_lds(int bytes);
 
 hipError_t launch_batched(const BatchArgs &b, int grid, int max_n, int *hist, int32_t *order,
                           hipStream_t s);

@@ -41,17 +41,20 @@ __device__ __forceinline__ int64_t pair_col(int c, int w, int2 pq) {
 }
 
 // ----------------------------------------------------------------- Gram
-// Grid (splits, npairs), 256 threads.  Each wave takes 16-row slices; lane
-// l holds rows 4*(l/16) .. +3 of local column 16*t + l%16 for every column
-// tile t.  The contraction index of the MFMA runs over those rows, which
-// is free to choose because both operands are the same slice, so every
-// lane loads 4 consecutive doubles of one column.  Only the tiles on and
-// above the diagonal of the symmetric H are formed.
+// Grid (splits, npairs), 256 threads.  Each wave takes 32-row slices; lane
+// l holds rows 8*(l/16) .. +7 of local column 16*t + l%16 for every column
+// tile t, loaded as 16-byte vectors.  The contraction index of the MFMA
+// runs over those rows, which is free to choose because both operands are
+// the same slice.  Only the tiles on and above the diagonal of the
+// symmetric H are formed.
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+
 template <int BW>
 __global__ __launch_bounds__(256) void gram_kernel(StepArgs a) {
     constexpr int T = BW / 16;
     constexpr int NT = T * (T + 1) / 2;
-    constexpr int S = 4;
+    constexpr int S = 8;
+    constexpr int SLICE = 4 * S;  // rows per wave and iteration
     __shared__ d4 red[NT * 64];
 
     const int pair = blockIdx.y, split = blockIdx.x;
@@ -75,14 +78,19 @@ __global__ __launch_bounds__(256) void gram_kernel(StepArgs a) {
 
     const int64_t r0 = (int64_t)split * a.rows_per_split;
     const int64_t r1 = min(a.m, r0 + (int64_t)a.rows_per_split);
-    for (int64_t base = r0 + wave * 16; base < r1; base += 64) {
+    for (int64_t base = r0 + wave * SLICE; base < r1; base += 4 * SLICE) {
         double x[T][S];
         const int64_t rb = base + grp * S;
-        if (base + 16 <= r1) {
+        if (base + SLICE <= r1) {
 #pragma unroll
             for (int t = 0; t < T; ++t)
 #pragma unroll
-                for (int s = 0; s < S; ++s) x[t][s] = valid[t] ? col[t][rb + s] : 0.0;
+                for (int s2 = 0; s2 < S / 2; ++s2) {
+                    const d2u v = valid[t] ? *reinterpret_cast<const d2u *>(col[t] + rb + 2 * s2)
+                                           : d2u{0.0, 0.0};
+                    x[t][2 * s2] = v.x;
+                    x[t][2 * s2 + 1] = v.y;
+                }
         } else {
 #pragma unroll
             for (int t = 0; t < T; ++t)
@@ -151,32 +159,34 @@ __device__ __forceinline__ void rotation(double hpp, double hqq, double hpq, int
     cs = (act >= kSqrt2OverEps) ? 1.0 : act / sqrt(fma(act, act, tt));
 }
 
-// Sum over the 32 lanes of a half wave, identical in every lane: each level
+// Sum over the 16 lanes of a DPP row, identical in every lane: each level
 // adds the value of a partner lane whose own partial sum is the mirror image
-// (lane l <-> l^1, l^2, 7-l, 15-l within a row, l^16), so both lanes add the
-// same two numbers.  Needs all 64 lanes active.
-__device__ __forceinline__ double half_wave_sum(double v) {
+// (lane l <-> l^1, l^2, 7-l, 15-l within the row), so both lanes add the
+// same two numbers.  The 16 lanes of the row must be active.
+__device__ __forceinline__ double row_sum(double v) {
     v += __builtin_amdgcn_update_dpp(0.0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
     v += __builtin_amdgcn_update_dpp(0.0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
     v += __builtin_amdgcn_update_dpp(0.0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
     v += __builtin_amdgcn_update_dpp(0.0, v, 0x140, 0xF, 0xF, false);  // row_mirror
-    const long long x = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_ds_swizzle((int)x, 0x401F);         // lane ^ 16
-    const int hi = __builtin_amdgcn_ds_swizzle((int)(x >> 32), 0x401F);
-    return v + __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+    return v;
 }
 
 // ---------------------------------------------------------------- inner
 // One workgroup per pivot block-pair.  BW = 2w.  R and V' live in LDS,
 // column-major with a padded leading dimension.  A p-step of the inner
-// strategy has BW/2 pivot pairs; every pair is handled by one half wave,
-// lane x owning rows x, x + 32, ... (BW/32 rows) of the pair's two columns of
-// R and of V'.  The three dot products of subphase 1 are half-wave sums.
+// strategy has BW/2 pivot pairs; every pair is handled by one DPP row of 16
+// lanes, lane x owning rows x, x + 16, ... (BW/16 rows) of the pair's two
+// columns of R and of V'.  The three dot products of subphase 1 are row
+// sums; every row then decides and computes its rotation (subphases 2-5)
+// and applies it (subphase 6); one barrier separates the p-steps.  With
+// four pairs per wave the FP64 division and square-root chains of four
+// rotations share one instruction stream.
 template <int BW>
 struct InnerCfg {
-    static constexpr int kThreads = BW / 2 * 32;  // one half wave per pivot pair
-    static constexpr int kRows = BW / 32;         // rows per lane in the Jacobi steps
-    static constexpr int kOwn = BW / 16;          // Cholesky rows owned per thread
+    static constexpr int kThreads = BW / 2 * 16;  // one 16-lane row per pivot pair
+    static constexpr int kRows = BW / 16;         // rows per lane in the Jacobi steps
+    static constexpr int kRowsPerSlot = kThreads / BW;   // Cholesky rows per slot
+    static constexpr int kOwn = BW / kRowsPerSlot;       // Cholesky entries per thread
     static constexpr int kMaxSplits = 16;         // Gram partial sums per pair, at most
 };
 
@@ -187,10 +197,13 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
     constexpr int NTHR = Cfg::kThreads;
     constexpr int ROWS = Cfg::kRows;
     constexpr int OWN = Cfg::kOwn;
+    constexpr int RPS = Cfg::kRowsPerSlot;
+    constexpr int NWAVES = NTHR / 64;
     __shared__ double R[BW * LD];
     __shared__ double Vp[BW * LD];
     __shared__ double hdiag[BW];
     __shared__ int flags[2];  // [0] NaN met, [1] zero pivots
+    __shared__ int cnt[NWAVES][4];
 
     const int pair = blockIdx.x;
     const int2 pq = a.pairs[pair];
@@ -201,15 +214,15 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
     }
 
     // ---- H_pq.  Thread t owns the upper-triangle entries (i, j), i <= j,
-    // with i = 16 o + t / BW and j = t % BW for o = 0 .. BW/16 - 1, so that
-    // each row of the Cholesky factor is produced by one (half) wave.  The
-    // partial Gram values of an entry are summed in split order.
+    // with j = t % BW and i = RPS o + t / BW for o = 0 .. OWN - 1, so that
+    // each row of the Cholesky factor is produced by one group of BW lanes.
+    // The partial Gram values of an entry are summed in split order.
     const int jcol = tid % BW, ibase = tid / BW;
     double h[OWN], di[OWN];
     const double *hp = a.hpart + (size_t)pair * a.splits * BW * BW;
 #pragma unroll
     for (int o = 0; o < OWN; ++o) {
-        const int i = 16 * o + ibase;
+        const int i = RPS * o + ibase;
         double s = 0.0;
         if (i <= jcol) {
             double part[Cfg::kMaxSplits];
@@ -235,7 +248,7 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
     if (tid < 2) flags[tid] = 0;
     __syncthreads();
 #pragma unroll
-    for (int o = 0; o < OWN; ++o) di[o] = hdiag[16 * o + ibase];
+    for (int o = 0; o < OWN; ++o) di[o] = hdiag[RPS * o + ibase];
 
     // ---- Cholesky H = R^T R, row k of R at step k (Section 4.1).  Every
     // owner of an entry of row i keeps its own copy of the current H(i,i)
@@ -244,8 +257,8 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
     // semidefinite: dependent columns) makes row k of R zero.
     int zero_pivots = 0;
     for (int k = 0; k < BW; ++k) {
-        const int ok = k >> 4;
-        if ((k & 15) == ibase && jcol >= k) {
+        const int ok = k / RPS;
+        if ((k % RPS) == ibase && jcol >= k) {
 #pragma unroll
             for (int o = 0; o < OWN; ++o) {
                 if (o == ok) {
@@ -267,7 +280,7 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
         const double rkj = R[jcol * LD + k];
 #pragma unroll
         for (int o = 0; o < OWN; ++o) {
-            const int i = 16 * o + ibase;
+            const int i = RPS * o + ibase;
             if (i > k && i <= jcol) {
                 const double rki = R[i * LD + k];
                 h[o] = fma(-rki, rkj, h[o]);
@@ -286,25 +299,15 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
     }
     if (tid == 0 && flags[1]) atomicAdd(&a.counters[C_BREAKDOWN], (unsigned long long)flags[1]);
 
-    // ---- inner Jacobi (Section 4.3).  A p-step runs in three phases:
-    //   A  every half wave loads its pair's columns of R (and V') and forms
-    //      the three dot products of subphase 1;
-    //   B  one wave, one lane per pivot pair, decides and computes the
-    //      rotations (subphases 2-5), so the long FP64 division and square
-    //      root chains run once per pair instead of once per half wave;
-    //   C  every half wave applies its pair's rotation (subphase 6).
+    // ---- inner Jacobi (Section 4.3)
     const int lane = tid & 63, wave = tid >> 6;
-    const int x = lane & 31;                          // first row owned by this lane
-    const int slot = wave * 2 + (lane >> 5);          // pivot pair of this half wave
-    const double tol = kEps * sqrt((double)BW);       // c(eps) = eps sqrt(nhat), nhat = 2w
-    __shared__ double dots[BW / 2][3];
-    __shared__ double rot_mtn[BW / 2], rot_tn[BW / 2], rot_cs[BW / 2];
-    __shared__ int rot_code[BW / 2];                  // bit 0 rotate, 1 swap, 2 cs != 1
-    __shared__ int sweep_rot;
-    int rot_total = 0, proper_total = 0, clamp_total = 0, sweeps = 0;  // lanes of wave 0
+    const int x = lane & 15;      // first row owned by this lane
+    const int slot = tid >> 4;    // pivot pair of this 16-lane row
+    const double tol = kEps * sqrt((double)BW);  // c(eps) = eps sqrt(nhat), nhat = 2w
+    int rot_total = 0, proper_total = 0, clamp_total = 0, sweeps = 0;
 
     for (int sw = 0; sw < a.max_inner_sweeps; ++sw) {
-        int rot_sweep = 0;  // lanes of wave 0
+        int rot_sweep = 0;
         for (int st = 0; st < BW - 1; ++st) {
             const unsigned char *tbl = a.inner_tbl + (size_t)st * BW;  // BW/2 pairs x 2
             const int p = tbl[2 * slot], q = tbl[2 * slot + 1];
@@ -312,99 +315,90 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
             double hpp = 0.0, hqq = 0.0, hpq = 0.0;
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) {
-                rp[r] = R[p * LD + x + 32 * r];
-                rq[r] = R[q * LD + x + 32 * r];
-                vp[r] = Vp[p * LD + x + 32 * r];
-                vq[r] = Vp[q * LD + x + 32 * r];
+                rp[r] = R[p * LD + x + 16 * r];
+                rq[r] = R[q * LD + x + 16 * r];
+                vp[r] = Vp[p * LD + x + 16 * r];
+                vq[r] = Vp[q * LD + x + 16 * r];
                 hpp = fma(rp[r], rp[r], hpp);
                 hqq = fma(rq[r], rq[r], hqq);
                 hpq = fma(rp[r], rq[r], hpq);
             }
-            hpp = half_wave_sum(hpp);
-            hqq = half_wave_sum(hqq);
-            hpq = half_wave_sum(hpq);
-            if (x == 0) {
-                dots[slot][0] = hpp;
-                dots[slot][1] = hqq;
-                dots[slot][2] = hpq;
-            }
-            __syncthreads();
+            hpp = row_sum(hpp);
+            hqq = row_sum(hqq);
+            hpq = row_sum(hpq);
 
-            if (wave == 0 && lane < BW / 2) {
-                const int pp = tbl[2 * lane], qq = tbl[2 * lane + 1];
-                const double dpp = dots[lane][0], dqq = dots[lane][1], dpq = dots[lane][2];
-                const int64_t kp = pair_col(pp, a.w, pq), kq = pair_col(qq, a.w, pq);
-                const bool pad = kq >= a.n || kp >= a.n;
-                // subphase 2: relative orthogonality (reading: <= skips)
-                const bool rotate = !(fabs(dpq) <= tol * sqrt(dpp) * sqrt(dqq));
-                // subphase 4: hyperbolic iff kp < n+ <= kq
-                const int t = (kp < a.n_plus && kq >= a.n_plus) ? -1 : 1;
-                double tn = 0.0, cs = 1.0;
-                bool clamped = false;
-                if (rotate) rotation(dpp, dqq, dpq, t, tn, cs, clamped);
-                // subphase 5: keep j*sigma^2 non-increasing for trigonometric
-                // pairs (h_pp' = h_pp - tn h_pq, h_qq' = h_qq + tn h_pq)
-                bool swap = false;
-                if (t > 0 && !pad) {
-                    const double npp = rotate ? fma(-tn, dpq, dpp) : dpp;
-                    const double nqq = rotate ? fma(tn, dpq, dqq) : dqq;
-                    if (kq < a.n_plus)
-                        swap = npp < nqq;
-                    else if (kp >= a.n_plus)
-                        swap = npp > nqq;
-                }
-                rot_mtn[lane] = (t > 0) ? -tn : tn;  // coefficient of column q in the new p
-                rot_tn[lane] = tn;
-                rot_cs[lane] = cs;
-                rot_code[lane] = (rotate ? 1 : 0) | (swap ? 2 : 0) | (cs != 1.0 ? 4 : 0);
-                rot_sweep += rotate ? 1 : 0;
-                proper_total += (rotate && cs != 1.0) ? 1 : 0;
-                clamp_total += clamped ? 1 : 0;
+            const int64_t kp = pair_col(p, a.w, pq), kq = pair_col(q, a.w, pq);
+            const bool pad = kq >= a.n || kp >= a.n;
+            // subphase 2: relative orthogonality (reading: <= skips)
+            const bool rotate = !(fabs(hpq) <= tol * sqrt(hpp) * sqrt(hqq));
+            // subphase 4: hyperbolic iff kp < n+ <= kq.  The parameters are
+            // computed whether or not the pair rotates (with a harmless
+            // denominator when h_pq = 0), so that the test and the rotation
+            // chains overlap; the test then selects.
+            const int t = (kp < a.n_plus && kq >= a.n_plus) ? -1 : 1;
+            double tn, cs;
+            bool clamped;
+            rotation(hpp, hqq, hpq == 0.0 ? 1.0 : hpq, t, tn, cs, clamped);
+            if (!rotate) {
+                tn = 0.0;
+                cs = 1.0;
+                clamped = false;
             }
-            __syncthreads();
-
-            const int code = rot_code[slot];
-            if (code & 1) {
-                const double mtn = rot_mtn[slot], tn = rot_tn[slot], cs = rot_cs[slot];
+            // subphase 5: keep j*sigma^2 non-increasing for trigonometric
+            // pairs (h_pp' = h_pp - tn h_pq, h_qq' = h_qq + tn h_pq)
+            bool swap = false;
+            if (t > 0 && !pad) {
+                const double npp = fma(-tn, hpq, hpp);
+                const double nqq = fma(tn, hpq, hqq);
+                if (kq < a.n_plus)
+                    swap = npp < nqq;
+                else if (kp >= a.n_plus)
+                    swap = npp > nqq;
+            }
+            if (rotate || swap) {
+                const double mtn = (t > 0) ? -tn : tn;  // (4.1) / (4.2)
+                const int cp = swap ? q : p, cq = swap ? p : q;
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r) {
-                    const double a0 = rp[r], b0 = rq[r], c0 = vp[r], d0 = vq[r];
-                    if (code & 4) {
-                        rp[r] = cs * fma(mtn, b0, a0);
-                        rq[r] = cs * fma(tn, a0, b0);
-                        vp[r] = cs * fma(mtn, d0, c0);
-                        vq[r] = cs * fma(tn, c0, d0);
-                    } else {  // cs == 1: the multiplication is omitted
-                        rp[r] = fma(mtn, b0, a0);
-                        rq[r] = fma(tn, a0, b0);
-                        vp[r] = fma(mtn, d0, c0);
-                        vq[r] = fma(tn, c0, d0);
+                    double np = rp[r], nq = rq[r], nvp = vp[r], nvq = vq[r];
+                    if (rotate) {
+                        if (cs == 1.0) {  // the multiplication is omitted
+                            np = fma(mtn, rq[r], rp[r]);
+                            nq = fma(tn, rp[r], rq[r]);
+                            nvp = fma(mtn, vq[r], vp[r]);
+                            nvq = fma(tn, vp[r], vq[r]);
+                        } else {
+                            np = cs * fma(mtn, rq[r], rp[r]);
+                            nq = cs * fma(tn, rp[r], rq[r]);
+                            nvp = cs * fma(mtn, vq[r], vp[r]);
+                            nvq = cs * fma(tn, vp[r], vq[r]);
+                        }
                     }
+                    R[cp * LD + x + 16 * r] = np;
+                    R[cq * LD + x + 16 * r] = nq;
+                    Vp[cp * LD + x + 16 * r] = nvp;
+                    Vp[cq * LD + x + 16 * r] = nvq;
                 }
             }
-            if (code & 3) {
-                const int cp = (code & 2) ? q : p, cq = (code & 2) ? p : q;
+            // counts: one per pair (the 16 lanes of a row agree)
+            const int r1 = rotate ? 1 : 0, p1 = (rotate && cs != 1.0) ? 1 : 0, c1 = clamped ? 1 : 0;
 #pragma unroll
-                for (int r = 0; r < ROWS; ++r) {
-                    R[cp * LD + x + 32 * r] = rp[r];
-                    R[cq * LD + x + 32 * r] = rq[r];
-                    Vp[cp * LD + x + 32 * r] = vp[r];
-                    Vp[cq * LD + x + 32 * r] = vq[r];
-                }
+            for (int g = 0; g < 4; ++g) {
+                rot_sweep += __builtin_amdgcn_readlane(r1, 16 * g);
+                proper_total += __builtin_amdgcn_readlane(p1, 16 * g);
+                clamp_total += __builtin_amdgcn_readlane(c1, 16 * g);
             }
             __syncthreads();
         }
         ++sweeps;
-        if (wave == 0) {
-            int all = rot_sweep;  // sum over the lanes of wave 0
+        rot_total += rot_sweep;
+        if (lane == 0) cnt[wave][0] = rot_sweep;
+        __syncthreads();
+        int all = 0;
 #pragma unroll
-            for (int off = 1; off < 64; off <<= 1) all += __shfl_xor(all, off, 64);
-            rot_total += rot_sweep;
-            if (lane == 0) sweep_rot = all;
-        }
+        for (int wv = 0; wv < NWAVES; ++wv) all += cnt[wv][0];
         __syncthreads();
-        if (sweep_rot == 0) break;  // no rotation in the inner sweep
-        __syncthreads();
+        if (all == 0) break;  // no rotation in the inner sweep
     }
 
     // ---- write V'_pq and the counts
@@ -413,35 +407,39 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
         const int i = e % BW, j = e / BW;
         vout[j * BW + i] = Vp[j * LD + i];
     }
-    if (wave == 0) {
-        int r = rot_total, pr = proper_total, cl = clamp_total;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            r += __shfl_xor(r, off, 64);
-            pr += __shfl_xor(pr, off, 64);
-            cl += __shfl_xor(cl, off, 64);
+    if (lane == 0) {
+        cnt[wave][0] = rot_total;
+        cnt[wave][1] = proper_total;
+        cnt[wave][2] = clamp_total;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        long long r = 0, pr = 0, cl = 0;
+        for (int wv = 0; wv < NWAVES; ++wv) {
+            r += cnt[wv][0];
+            pr += cnt[wv][1];
+            cl += cnt[wv][2];
         }
-        if (lane == 0) {
-            a.pair_rot[pair] = r;
-            atomicAdd(&a.counters[C_ROT], (unsigned long long)r);
-            atomicAdd(&a.counters[C_PROPER], (unsigned long long)pr);
-            atomicAdd(&a.counters[C_CLAMP], (unsigned long long)cl);
-            atomicAdd(&a.counters[C_INNER_SW], (unsigned long long)sweeps);
-            if (r) atomicAdd(&a.counters[C_UPDATES], 1ull);
-        }
+        a.pair_rot[pair] = (int)r;
+        atomicAdd(&a.counters[C_ROT], (unsigned long long)r);
+        atomicAdd(&a.counters[C_PROPER], (unsigned long long)pr);
+        atomicAdd(&a.counters[C_CLAMP], (unsigned long long)cl);
+        atomicAdd(&a.counters[C_INNER_SW], (unsigned long long)sweeps);
+        if (r) atomicAdd(&a.counters[C_UPDATES], 1ull);
     }
 }
 
 // --------------------------------------------------------------- update
 // Grid (chunks of G rows + chunks of V rows, npairs), 256 threads.  Each
 // wave takes 16-row slices and computes (X V')^T = V'^T X^T tile by tile:
-// V' supplies the A operand from registers, a slice of X the B operand
+// V' (staged in LDS) supplies the A operand, a slice of X the B operand
 // (lane l reads row l%16 of local column 4*ks + l/16), and each result
 // column is written back as 16 consecutive rows.  All loads of a slice
 // precede its stores, so the update is in place.
 template <int BW>
 __global__ __launch_bounds__(256) void update_kernel(StepArgs a) {
     constexpr int KS = BW / 4, JT = BW / 16;
+    __shared__ double vs[BW * BW];  // V'_pq transposed: vs[k * BW + j] = V'(k, j)
     const int pair = blockIdx.y;
     if (a.pair_rot[pair] == 0) return;
     const int2 pq = a.pairs[pair];
@@ -455,11 +453,7 @@ __global__ __launch_bounds__(256) void update_kernel(StepArgs a) {
     const int i16 = lane & 15, grp = lane >> 4;
 
     const double *vpr = a.vprime + (size_t)pair * BW * BW;
-    double va[JT][KS];
-#pragma unroll
-    for (int jt = 0; jt < JT; ++jt)
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) va[jt][ks] = vpr[(jt * 16 + i16) * BW + 4 * ks + grp];
+    for (int e = threadIdx.x; e < BW * BW; e += 256) vs[(e % BW) * BW + e / BW] = vpr[e];
 
     int64_t ldoff[KS];  // column offsets of the B loads (-1: padding)
 #pragma unroll
@@ -467,18 +461,14 @@ __global__ __launch_bounds__(256) void update_kernel(StepArgs a) {
         const int64_t gc = pair_col(4 * ks + grp, a.w, pq);
         ldoff[ks] = gc < a.n ? gc * ldx : -1;
     }
-    int64_t stoff[JT][4];
-#pragma unroll
-    for (int jt = 0; jt < JT; ++jt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t gc = pair_col(jt * 16 + grp + 4 * v, a.w, pq);
-            stoff[jt][v] = gc < a.n ? gc * ldx : -1;
-        }
+    __syncthreads();
 
     const int64_t r0 = (int64_t)chunk * a.upd_rows;
     const int64_t r1 = min(rows, r0 + (int64_t)a.upd_rows);
     for (int64_t base = r0 + wave * 16; base < r1; base += 64) {
+        // re-read V' from LDS in every slice instead of pinning it in 2w^2/64
+        // registers per lane (keeps the occupancy of this streaming kernel up)
+        asm volatile("" ::: "memory");
         const int64_t row = base + i16;
         const bool rv = row < r1;
         double b[KS];
@@ -490,12 +480,15 @@ __global__ __launch_bounds__(256) void update_kernel(StepArgs a) {
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-            for (int jt = 0; jt < JT; ++jt) acc[jt] = mfma16(va[jt][ks], b[ks], acc[jt]);
+            for (int jt = 0; jt < JT; ++jt)
+                acc[jt] = mfma16(vs[(4 * ks + grp) * BW + jt * 16 + i16], b[ks], acc[jt]);
 #pragma unroll
         for (int jt = 0; jt < JT; ++jt)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                if (rv && stoff[jt][v] >= 0) X[stoff[jt][v] + row] = acc[jt][v];
+            for (int v = 0; v < 4; ++v) {
+                const int64_t gc = pair_col(jt * 16 + grp + 4 * v, a.w, pq);
+                if (rv && gc < a.n) X[gc * ldx + row] = acc[jt][v];
+            }
     }
 }
 

@@ -1,0 +1,96 @@
+"""Full-size workloads, checked by properties that hold at any size (the oracle
+is too slow there) and by singular triplets sampled one by one:
+
+  * 4096 x 4096 N(0,1), the benchmark configuration: sum sigma^2 = ||A||_F^2,
+    U^T U = I, V^T V = I, A V = U Sigma, and for sampled i the residuals
+    ||A v_i - s_i u_i||, ||A^T u_i - s_i v_i|| (each triplet is a singular
+    triplet of A to the method's accuracy);
+  * 8192 x 2048 with prescribed sigma log-spaced 1 .. 1e-10: sigma against the
+    prescribed values within the representation error of A;
+  * hyperbolic 2048 x 2048, J = diag(+1 x 1280, -1 x 768): j_i sigma_i^2
+    against the eigenvalues of G J G^T (LAPACK, normwise), V^T J V = J and
+    G V = U Sigma.
+Bars as in test_gpu_parity.py.
+"""
+import numpy as np
+import pytest
+
+from paper_1401_2720_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return torch
+
+
+def _orth(X):
+    torch = _torch()
+    n = X.shape[1]
+    return float((X.t().contiguous() @ X - torch.eye(n, dtype=X.dtype, device=X.device)).abs().max())
+
+
+def test_square_gaussian_4096():
+    torch = _torch()
+    import paper_1401_2720_amd as jsvd
+    print("4096 x 4096 N(0,1)", flush=True)
+    A = torch.from_numpy(inputs.square_gaussian()).cuda()
+    U, S, V, info = jsvd.gesvd(A)
+    torch.cuda.synchronize()
+    n = 4096
+    assert info["status"] == 0 and info["converged"] == 1
+    fro2 = float((A * A).sum())
+    assert abs(float((S * S).sum()) - fro2) <= 1e-13 * n * fro2
+    assert _orth(U) <= 1e-13 * n and _orth(V) <= 1e-13 * n
+    res = float(torch.linalg.norm(A @ V - U * S) / torch.linalg.norm(A))
+    assert res <= 1e-13 * n
+    assert bool((S[1:] <= S[:-1]).all())
+    s1 = float(S[0])
+    for i in [0, 1, 100, 2047, 4000, 4095]:
+        r1 = float(torch.linalg.norm(A @ V[:, i] - S[i] * U[:, i]))
+        r2 = float(torch.linalg.norm(A.t() @ U[:, i] - S[i] * V[:, i]))
+        assert r1 <= 1e-13 * n * s1 and r2 <= 1e-13 * n * s1, i
+
+
+def test_tall_graded_8192x2048():
+    torch = _torch()
+    import paper_1401_2720_amd as jsvd
+    print("8192 x 2048, sigma 1 .. 1e-10", flush=True)
+    A = torch.from_numpy(inputs.tall_graded()).cuda()
+    U, S, V, info = jsvd.gesvd(A)
+    torch.cuda.synchronize()
+    assert info["status"] == 0
+    sig = inputs.logspaced(2048, -10.0)
+    s = S.cpu().numpy()
+    eps = 2.0 ** -53
+    # A = Q1 diag(sig) Q2^T in fp64 carries an error of order eps ||A|| sqrt(n)
+    assert np.max(np.abs(s - sig)) <= 100 * eps * np.sqrt(2048)
+    assert np.max(np.abs(s - sig)[sig >= 1e-3] / sig[sig >= 1e-3]) <= 1e-12
+    assert _orth(V) <= 1e-13 * 2048
+    res = float(torch.linalg.norm(A @ V - U * S) / torch.linalg.norm(A))
+    assert res <= 1e-13 * 2048
+
+
+def test_hyperbolic_2048():
+    torch = _torch()
+    import paper_1401_2720_amd as jsvd
+    print("hyperbolic 2048 x 2048, n+ = 1280", flush=True)
+    G, J = inputs.hyperbolic_gaussian()
+    Gt = torch.from_numpy(G).cuda()
+    U, S, V, Jout, info = jsvd.hsvd(Gt, J)
+    torch.cuda.synchronize()
+    assert info["status"] == 0
+    n = 2048
+    j = torch.from_numpy(J.astype(np.float64)).cuda()
+    vmax = max(1.0, float(V.abs().max()) ** 2)
+    jo = torch.from_numpy(Jout.astype(np.float64)).cuda()
+    vjv = V.t().contiguous() @ (j[:, None] * V)
+    assert float((vjv - torch.diag(jo)).abs().max()) <= 1e-13 * n * vmax
+    vn = float(torch.linalg.matrix_norm(V, ord=2))
+    res = float(torch.linalg.norm(Gt @ V - U * S) / (torch.linalg.norm(Gt) * vn))
+    assert res <= 1e-13 * n
+    lam = np.linalg.eigvalsh((G * J) @ G.T)
+    got = np.sort(Jout * S.cpu().numpy() ** 2)
+    assert np.max(np.abs(got - np.sort(lam))) <= 1e-12 * np.max(np.abs(lam)) * vmax
