@@ -67,19 +67,17 @@ def kernel_roofline(name, avg_ms, per_launch, w):
 
 def measured_traffic(kernel_name, w):
     """HBM bytes per launch of a p-step kernel from the committed rocprofv3
-    counter summary, or None when there is none for this kernel or the
-    kernel source changed since the counters were taken."""
-    import hashlib
+    counter summary, or None when there is none for this kernel or its
+    sources changed since the counters were taken."""
+    from paper_1401_2720_amd import prof_summary
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    src = os.path.join(ROOT, "paper_1401_2720_amd", "csrc", "jsvd_kernels.hip")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    entry = rec.get("kernels", {}).get(f"{kernel_name}_kernel<{2 * w}>")
-    if entry is None or rec.get("source_sha256") != sha:
+    name = f"{kernel_name}_kernel<{2 * w}>"
+    entry = rec.get("kernels", {}).get(name)
+    if entry is None or entry.get("sources_sha256") != prof_summary.kernel_sources_sha256(kernel_name):
         return None
     return entry["hbm_bytes_per_launch"]
 

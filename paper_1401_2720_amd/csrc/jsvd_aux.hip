@@ -1,0 +1,142 @@
+// Small kernels around the sweeps: counter reset, V = I, column norms
+// (the singular values, Section 4), the final ordering and the gathers.
+#include "jsvd_device.h"
+
+namespace jsvd {
+
+namespace {
+
+// ------------------------------------------------------------ small kernels
+__global__ void reset_counters_kernel(unsigned long long *c) {
+    if (threadIdx.x < C_COUNT) c[threadIdx.x] = 0ull;
+}
+
+__global__ void init_identity_kernel(double *V, int64_t ldv, int64_t n) {
+    const int64_t j = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        V[i + j * ldv] = (i == j) ? 1.0 : 0.0;
+}
+
+// sigma_j = ||g_j||_2 (the Sigma kernel of Section 4): fma accumulation
+// per thread, then a fixed-shape tree in LDS.
+__global__ __launch_bounds__(256) void colnorm_kernel(const double *G, int64_t ldg, int64_t m,
+                                                      double *s_out) {
+    __shared__ double part[256];
+    const int64_t j = blockIdx.x;
+    const double *g = G + j * ldg;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += 256) s = fma(g[i], g[i], s);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) s_out[j] = sqrt(part[0]);
+}
+
+// Output order: positions [0, n_plus) by non-increasing sigma, [n_plus, n)
+// by non-decreasing sigma, ties by column index; NaN sorts as -infinity so
+// that the ranks always form a permutation.
+__global__ void rank_kernel(const double *s, int64_t n, int64_t n_plus, int *perm) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const bool pos = j < n_plus;
+    const int64_t lo = pos ? 0 : n_plus, hi = pos ? n_plus : n;
+    const double kj = (s[j] != s[j]) ? -INFINITY : s[j];
+    int64_t r = lo;
+    for (int64_t i = lo; i < hi; ++i) {
+        const double ki = (s[i] != s[i]) ? -INFINITY : s[i];
+        const bool before = pos ? (ki > kj) : (ki < kj);
+        if (before || (ki == kj && i < j)) ++r;
+    }
+    perm[r] = (int)j;
+}
+
+// dst[:, k] = src[:, perm[k]] (perm may be null: identity), divided by
+// scale[perm[k]] when scale is given (u = g / sigma, 0 when sigma = 0);
+// s_out[k] = scale[perm[k]].
+__global__ void gather_cols_kernel(const double *src, int64_t lds, double *dst, int64_t ldd,
+                                   int64_t rows, const int *perm, const double *scale,
+                                   double *s_out) {
+    const int64_t k = blockIdx.y;
+    const int64_t c = perm ? perm[k] : k;
+    const double sc = scale ? scale[c] : 1.0;
+    if (s_out && blockIdx.x == 0 && threadIdx.x == 0) s_out[k] = sc;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = src[i + c * lds];
+        dst[i + k * ldd] = scale ? (sc > 0.0 ? v / sc : 0.0) : v;
+    }
+}
+
+// dst[row_of[i], :] = src[i, :]
+__global__ void scatter_rows_kernel(const double *src, int64_t lds, double *dst, int64_t ldd,
+                                    int64_t rows, const int *row_of) {
+    const int64_t k = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[row_of[i] + k * ldd] = src[i + k * lds];
+}
+
+__global__ void diag_fp64_kernel(int64_t count, const double *a, const double *b, double *q,
+                                 double *r) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        q[i] = a[i] / b[i];
+        r[i] = sqrt(a[i]);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_reset_counters(unsigned long long *c, hipStream_t s) {
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_identity(double *V, int64_t ldv, int64_t n, hipStream_t s) {
+    const int64_t bx = std::min<int64_t>((n + 255) / 256, 64);
+    hipLaunchKernelGGL(init_identity_kernel, dim3((unsigned)bx, (unsigned)n), dim3(256), 0, s, V,
+                       ldv, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_colnorms(const double *G, int64_t ldg, int64_t m, int64_t n, double *s_out,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(colnorm_kernel, dim3((unsigned)n), dim3(256), 0, s, G, ldg, m, s_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank(const double *s, int64_t n, int64_t n_plus, int *perm, hipStream_t st) {
+    hipLaunchKernelGGL(rank_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, n,
+                       n_plus, perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_cols(const double *src, int64_t lds, double *dst, int64_t ldd,
+                              int64_t rows, int64_t cols, const int *perm, const double *scale,
+                              double *s_out, hipStream_t s) {
+    const int64_t bx = std::max<int64_t>(1, std::min<int64_t>((rows + 255) / 256, 32));
+    hipLaunchKernelGGL(gather_cols_kernel, dim3((unsigned)bx, (unsigned)cols), dim3(256), 0, s,
+                       src, lds, dst, ldd, rows, perm, scale, s_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(const double *src, int64_t lds, double *dst, int64_t ldd,
+                               int64_t rows, int64_t cols, const int *row_of, hipStream_t s) {
+    const int64_t bx = std::max<int64_t>(1, std::min<int64_t>((rows + 255) / 256, 32));
+    hipLaunchKernelGGL(scatter_rows_kernel, dim3((unsigned)bx, (unsigned)cols), dim3(256), 0, s,
+                       src, lds, dst, ldd, rows, row_of);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_fp64(int64_t count, const double *a, const double *b, double *q,
+                            double *r, hipStream_t s) {
+    hipLaunchKernelGGL(diag_fp64_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                       count, a, b, q, r);
+    return hipGetLastError();
+}
+
+}  // namespace jsvd

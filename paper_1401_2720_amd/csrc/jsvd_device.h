@@ -1,0 +1,150 @@
+// Device helpers shared by the p-step kernels of the blocked one-sided
+// Jacobi (H)SVD: MFMA tile, constants of Section 4.3.1, FP64 building
+// blocks, DPP row sums and the rotation formulas (4.3)-(4.6).
+//
+// All arithmetic is FP64.  The kernels are compiled without floating-point
+// contraction: every fused multiply-add is an explicit fma() where the
+// paper writes one.  No floating-point atomics are used, so results are
+// bitwise reproducible run to run.
+#pragma once
+
+#include "jsvd_internal.h"
+
+namespace jsvd {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4_f64.  Operand layout (wave64): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; the 16x16 result D holds
+// D[l / 16 + 4 v][l % 16] in element v of lane l (measured on gfx950).
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Unit roundoff 2^-53 (Appendix A) and the thresholds of Section 4.3.1.
+constexpr double kEps = 1.1102230246251565e-16;       // 2^-53
+constexpr double kSqrtEps = 1.0536712127723509e-08;   // sqrt(2^-53)
+constexpr double kSqrt2OverEps = 134217728.0;         // sqrt(2 / 2^-53) = 2^27
+
+// Global column of local column c of the pivot block-pair (P, Q).
+__device__ __forceinline__ int64_t pair_col(int c, int w, int2 pq) {
+    return c < w ? (int64_t)pq.x * w + c : (int64_t)pq.y * w + (c - w);
+}
+
+// ----------------------------------------------------- FP64 building blocks
+// Division and square roots by the hardware reciprocal (v_rcp_f64) and
+// reciprocal-square-root (v_rsq_f64) seeds, good to about 26 bits, refined by
+// Newton steps and a final residual correction.  For positive normal
+// operands these agree with the correctly rounded IEEE results (checked on
+// 10^6 random operands over 2^+-40); they are used where the operands are
+// known to lie well inside the normal range, and the IEEE operations
+// everywhere else.
+__device__ __forceinline__ double nrcp(double b) {
+    double y = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-b, y, 1.0);
+    return fma(y, e, y);
+}
+__device__ __forceinline__ double ndiv(double a, double b) {
+    const double y = nrcp(b);
+    const double q = a * y;
+    const double r = fma(-b, q, a);
+    return fma(r, y, q);
+}
+__device__ __forceinline__ double nsqrt(double u) {
+    const double y = __builtin_amdgcn_rsq(u);
+    double s = u * y, h = 0.5 * y;
+    const double r = fma(-s, h, 0.5);
+    s = fma(s, r, s);
+    h = fma(h, r, h);
+    const double d = fma(-s, s, u);
+    return fma(d, h, s);
+}
+
+// 64-bit DPP move within a row of 16 lanes (bound_ctrl: no old value).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(u & 0xffffffffu), CTRL, 0xF, 0xF, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum over the 16 lanes of a DPP row, identical in every lane: each level
+// adds the value of a partner lane whose own partial sum is the mirror image
+// (lane l <-> l^1, l^2, 7-l, 15-l within the row), so both lanes add the
+// same two numbers.  The 16 lanes of the row must be active.
+__device__ __forceinline__ double row_sum(double v) {
+    v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);  // row_half_mirror
+    v += dpp_mov<0x140>(v);  // row_mirror
+    return v;
+}
+
+// Value of v in lane l (wave-uniform l).
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(u & 0xffffffffu), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// ----------------------------------------------------- rotations (4.3)-(4.6)
+// Trigonometric (t = +1) or hyperbolic (t = -1) rotation parameters from the
+// pivot Gram entries, cs_2 cosine, with the short cuts at sqrt(eps) and
+// sqrt(2/eps) and |coth 2phi| <= 1 replaced by 5/4.  IEEE operations.
+__device__ __forceinline__ void rotation(double hpp, double hqq, double hpq, int t, double &tn,
+                                         double &cs, bool &clamped) {
+    const double tt = (double)t;
+    const double h = hqq - tt * hpp;
+    const double ct2 = tt * (h / (2.0 * hpq));
+    const double sgn = ct2 < 0.0 ? -1.0 : 1.0;
+    double a = fabs(ct2);
+    clamped = false;
+    if (t < 0 && a <= 1.0) {
+        a = 1.25;
+        clamped = true;
+    }
+    double act;
+    if (t > 0 && a < kSqrtEps)
+        act = a + 1.0;
+    else if (a >= kSqrt2OverEps)
+        act = 2.0 * a;
+    else
+        act = a + sqrt(fma(a, a, tt));
+    tn = sgn * (1.0 / act);
+    cs = (act >= kSqrt2OverEps) ? 1.0 : act / sqrt(fma(act, act, tt));
+}
+
+// The same formulas, branch-free, with the refined reciprocal and square
+// roots.  Valid when h_pp, h_qq and |h_pq| lie in [2^-900, 2^900] and the pair
+// rotates (|h_pq| > tol sqrt(h_pp h_qq)): then every intermediate is a
+// positive normal number or is discarded by a selection.
+__device__ __forceinline__ void rotation_fast(double hpp, double hqq, double hpq, int t, double &tn,
+                                              double &cs, bool &clamped) {
+    const double tt = (double)t;
+    const double h = hqq - tt * hpp;
+    const double ct2 = tt * ndiv(h, 2.0 * hpq);
+    const double sgn = ct2 < 0.0 ? -1.0 : 1.0;
+    double a = fabs(ct2);
+    clamped = (t < 0) && (a <= 1.0);
+    a = clamped ? 1.25 : a;
+    const double root = nsqrt(fma(a, a, tt));
+    double act = (a >= kSqrt2OverEps) ? 2.0 * a : a + root;
+    act = (t > 0 && a < kSqrtEps) ? a + 1.0 : act;
+    tn = sgn * nrcp(act);
+    const double c = ndiv(act, nsqrt(fma(act, act, tt)));
+    cs = (act >= kSqrt2OverEps) ? 1.0 : c;
+}
+
+__device__ __forceinline__ bool in_fast_range(double v) {
+    return v >= 0x1p-900 && v <= 0x1p900;
+}
+
+}  // namespace
+
+}  // namespace jsvd

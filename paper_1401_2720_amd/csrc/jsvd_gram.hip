@@ -1,0 +1,112 @@
+// p-step kernel 1 of 3: the pivot Gram matrices H_pq = [G_p G_q]^T [G_p G_q],
+// eq. (2.7), on FP64 MFMA, split over the rows into deterministic partial sums.
+#include "jsvd_device.h"
+
+namespace jsvd {
+
+namespace {
+
+// ----------------------------------------------------------------- Gram
+// Grid (splits, npairs), 256 threads.  Each wave takes 32-row slices; lane
+// l holds rows 8*(l/16) .. +7 of local column 16*t + l%16 for every column
+// tile t, loaded as 16-byte vectors.  The contraction index of the MFMA
+// runs over those rows, which is free to choose because both operands are
+// the same slice.  Only the tiles on and above the diagonal of the
+// symmetric H are formed.
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+
+template <int BW>
+__global__ __launch_bounds__(256) void gram_kernel(StepArgs a) {
+    constexpr int T = BW / 16;
+    constexpr int NT = T * (T + 1) / 2;
+    constexpr int S = 8;
+    constexpr int SLICE = 4 * S;  // rows per wave and iteration
+    __shared__ d4 red[NT * 64];
+
+    const int pair = blockIdx.y, split = blockIdx.x;
+    const int2 pq = a.pairs[pair];
+    if ((int64_t)pq.x * a.w >= a.n) return;  // both block-columns are padding
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i16 = lane & 15, grp = lane >> 4;
+
+    const double *col[T];
+    bool valid[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int64_t gc = pair_col(t * 16 + i16, a.w, pq);
+        valid[t] = gc < a.n;
+        col[t] = a.G + (valid[t] ? gc : 0) * a.ldg;
+    }
+
+    d4 acc[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) acc[k] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const int64_t r0 = (int64_t)split * a.rows_per_split;
+    const int64_t r1 = min(a.m, r0 + (int64_t)a.rows_per_split);
+    for (int64_t base = r0 + wave * SLICE; base < r1; base += 4 * SLICE) {
+        double x[T][S];
+        const int64_t rb = base + grp * S;
+        if (base + SLICE <= r1) {
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int s2 = 0; s2 < S / 2; ++s2) {
+                    const d2u v = valid[t] ? *reinterpret_cast<const d2u *>(col[t] + rb + 2 * s2)
+                                           : d2u{0.0, 0.0};
+                    x[t][2 * s2] = v.x;
+                    x[t][2 * s2 + 1] = v.y;
+                }
+        } else {
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    x[t][s] = (valid[t] && rb + s < r1) ? col[t][rb + s] : 0.0;
+        }
+        int k = 0;
+#pragma unroll
+        for (int ta = 0; ta < T; ++ta)
+#pragma unroll
+            for (int tb = ta; tb < T; ++tb, ++k)
+#pragma unroll
+                for (int s = 0; s < S; ++s) acc[k] = mfma16(x[ta][s], x[tb][s], acc[k]);
+    }
+
+    // Fixed-order sum over the four waves: ((w0 + w1) + w2) + w3.
+    for (int wv = 0; wv < 4; ++wv) {
+        if (wave == wv) {
+#pragma unroll
+            for (int k = 0; k < NT; ++k)
+                red[k * 64 + lane] = (wv == 0) ? acc[k] : red[k * 64 + lane] + acc[k];
+        }
+        __syncthreads();
+    }
+
+    double *out = a.hpart + ((size_t)pair * a.splits + split) * BW * BW;
+    for (int e = threadIdx.x; e < NT * 256; e += 256) {
+        const int k = e >> 8, rem = e & 255, v = rem >> 6, l = rem & 63;
+        int ta = 0, tb = 0, kk = 0;
+        for (int x0 = 0; x0 < T; ++x0)
+            for (int y0 = x0; y0 < T; ++y0, ++kk)
+                if (kk == k) {
+                    ta = x0;
+                    tb = y0;
+                }
+        const int row = ta * 16 + (l >> 4) + 4 * v, colh = tb * 16 + (l & 15);
+        out[row * BW + colh] = red[k * 64 + l][v];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_gram(int bw, const StepArgs &a, hipStream_t s) {
+    dim3 grid(a.splits, a.npairs);
+    if (bw == 32)
+        hipLaunchKernelGGL(gram_kernel<32>, grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(gram_kernel<64>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace jsvd

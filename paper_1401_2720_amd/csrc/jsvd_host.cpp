@@ -2,7 +2,8 @@
 // Section 4 of the paper: it launches one p-step after another, reads one
 // block of per-sweep counters after each block sweep, and stops when a
 // sweep performed no proper rotation (Section 4.5) or the sweep limit is
-// reached.  Everything else runs in the kernels of jsvd_kernels.hip.
+// reached.  Everything else runs in the kernels of jsvd_gram.hip, jsvd_inner.hip,
+// jsvd_update.hip and jsvd_aux.hip.
 #include <chrono>
 #include <cstring>
 #include <map>
@@ -175,7 +176,7 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     const int nsteps = order - 1;
     const bool want_v = o.want_v != 0;
 
-    // Gram row splits (at most 16, the inner kernel's limit) and update row
+    // Gram row splits (at most 16) and update row
     // chunks: aim at a few workgroups per CU.
     const int target_wg = 1024;
     int splits = std::min(16, std::max(1, 512 / npairs));

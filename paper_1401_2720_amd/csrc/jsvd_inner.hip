@@ -1,0 +1,335 @@
+// p-step kernel 2 of 3: sum of the partial Gram matrices, Cholesky
+// H_pq = R^T R (Section 4.1) and the inner pointwise Jacobi on R with V'_pq
+// accumulated (Section 4.3), all in LDS, one workgroup per pivot block-pair.
+#include "jsvd_device.h"
+
+namespace jsvd {
+
+namespace {
+
+// ---------------------------------------------------------------- inner
+// One workgroup of 16 * BW threads per pivot block-pair (BW = 2w).  R and V'
+// live in LDS, column-major with a padded leading dimension.
+//
+// Cholesky (Section 4.1) by block rows of 16: wave 0 factors a block row
+// with lane j holding column j, pivots and multipliers broadcast by
+// readlane; then all threads subtract the block row's contribution from the
+// trailing part of H.  The subtractions of each entry happen in the same
+// order as in the unblocked row-by-row algorithm.
+//
+// Inner Jacobi (Section 4.3): a p-step of the inner strategy has BW/2 pivot
+// pairs.  Threads [0, 8 BW) handle R: every pair is one DPP row of 16 lanes,
+// lane x owning rows x, x + 16, ... of the pair's two columns; the three
+// dot products (subphase 1) are row sums, each row decides and computes its
+// rotation (subphases 2-5), applies it to its columns of R (subphase 6) and
+// publishes it.  Threads [8 BW, 16 BW) apply the previous p-step's
+// rotations to V' at the same time, so V' never lies on the path of the
+// rotations.  One barrier per p-step.
+template <int BW>
+struct InnerCfg {
+    static constexpr int kThreads = BW * 16;
+    static constexpr int kHalf = kThreads / 2;   // threads on R (and on V')
+    static constexpr int kRows = BW / 16;        // rows per lane and column
+    static constexpr int kPairs = BW / 2;        // pivot pairs per p-step
+    static constexpr int kSteps = BW - 1;        // p-steps per inner sweep
+    static constexpr int kLD = BW + 1;
+};
+
+template <int BW>
+__global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs a) {
+    using Cfg = InnerCfg<BW>;
+    constexpr int NT = Cfg::kThreads;
+    constexpr int HALF = Cfg::kHalf;
+    constexpr int NWAVES = NT / 64;
+    constexpr int LD = Cfg::kLD;
+    constexpr int ROWS = Cfg::kRows;
+    constexpr int NP = Cfg::kPairs;
+    constexpr int NS = Cfg::kSteps;
+    constexpr int EPT = BW * BW / NT;   // Gram entries summed per thread
+    __shared__ double R[BW * LD];
+    __shared__ double Vp[BW * LD];
+    __shared__ unsigned char tb[NS * BW];   // inner strategy, (p, q) per pair and step
+    __shared__ unsigned char sfl[NS * NP];  // pair flags per step, see below
+    __shared__ d4 prm[2][NP];               // published rotations: mtn, tn, cs, flags
+    __shared__ int flags[2];                // [0] NaN met, [1] zero pivots
+    __shared__ int cnt[NWAVES][4];
+
+    const int pair = blockIdx.x;
+    const int2 pq = a.pairs[pair];
+    const int tid = threadIdx.x;
+    if ((int64_t)pq.x * a.w >= a.n) {
+        if (tid == 0) a.pair_rot[pair] = 0;
+        return;
+    }
+    const int lane = tid & 63, wave = tid >> 6;
+
+    // ---- strategy table and pair flags: 1 hyperbolic (kp < n+ <= kq),
+    // 2 a padding column, 4 both columns in the + part, 8 both in the - part
+    for (int e = tid; e < NS * NP; e += NT) {
+        const int p = a.inner_tbl[2 * e], q = a.inner_tbl[2 * e + 1];
+        tb[2 * e] = (unsigned char)p;
+        tb[2 * e + 1] = (unsigned char)q;
+        const int64_t kp = pair_col(p, a.w, pq), kq = pair_col(q, a.w, pq);
+        int f = (kp < a.n_plus && kq >= a.n_plus) ? 1 : 0;
+        f |= (kq >= a.n || kp >= a.n) ? 2 : 0;
+        f |= (kq < a.n_plus) ? 4 : ((kp >= a.n_plus) ? 8 : 0);
+        sfl[e] = (unsigned char)f;
+    }
+
+    // ---- H_pq: the partial Gram matrices summed in split order (upper
+    // triangle, all loads of a thread issued together); padding columns
+    // become unit vectors orthogonal to everything
+    {
+        const double *hp = a.hpart + (size_t)pair * a.splits * BW * BW;
+        double s[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) s[u] = 0.0;
+        for (int s0 = 0; s0 < a.splits; s0 += 8) {
+            double v[8][EPT];
+#pragma unroll
+            for (int sp = 0; sp < 8; ++sp)
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) {
+                    const int e = tid + u * NT;
+                    v[sp][u] = (s0 + sp < a.splits && e / BW <= e % BW)
+                                   ? hp[(size_t)(s0 + sp) * BW * BW + e] : 0.0;
+                }
+#pragma unroll
+            for (int sp = 0; sp < 8; ++sp)
+#pragma unroll
+                for (int u = 0; u < EPT; ++u)
+                    if (s0 + sp < a.splits) s[u] += v[sp][u];
+        }
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + u * NT, i = e / BW, j = e % BW;
+            double h = (i <= j) ? s[u] : 0.0;
+            if (i <= j && (pair_col(i, a.w, pq) >= a.n || pair_col(j, a.w, pq) >= a.n))
+                h = (i == j) ? 1.0 : 0.0;
+            R[j * LD + i] = h;
+            Vp[j * LD + i] = (i == j) ? 1.0 : 0.0;
+        }
+    }
+    if (tid < 2) flags[tid] = 0;
+    __syncthreads();
+
+    // ---- Cholesky H = R^T R (Section 4.1).  A pivot that is not positive
+    // (H only semidefinite: dependent columns) makes its row of R zero.
+#pragma unroll
+    for (int kb = 0; kb < BW / 16; ++kb) {
+        if (wave == 0) {
+            const int j = lane;
+            double hb[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) hb[i] = (j < BW) ? R[j * LD + 16 * kb + i] : 0.0;
+            int zero_pivots = 0, nan_met = 0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int kk = 16 * kb + k;
+                const double hkk = lane_value(hb[k], kk);
+                double r = 0.0;
+                if (hkk > 0.0) {
+                    const double d = sqrt(hkk);
+                    r = (j == kk) ? d : hb[k] / d;
+                } else if (hkk != hkk) {
+                    nan_met = 1;
+                } else {
+                    ++zero_pivots;
+                }
+                if (j < kk) r = 0.0;
+                hb[k] = r;
+#pragma unroll
+                for (int i = k + 1; i < 16; ++i) hb[i] = fma(-lane_value(r, 16 * kb + i), r, hb[i]);
+            }
+            if (j < BW) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) R[j * LD + 16 * kb + i] = (j >= 16 * kb + i) ? hb[i] : 0.0;
+            }
+            if (lane == 0) {
+                flags[0] |= nan_met;
+                flags[1] += zero_pivots;
+            }
+        }
+        __syncthreads();
+        if (kb + 1 < BW / 16) {
+            constexpr int G = NT / BW;
+            const int j = tid % BW, g = tid / BW;
+            if (j >= 16 * (kb + 1)) {
+                double rj[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) rj[k] = R[j * LD + 16 * kb + k];
+                for (int i = 16 * (kb + 1) + g; i <= j; i += G) {
+                    double h = R[j * LD + i];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) h = fma(-R[i * LD + 16 * kb + k], rj[k], h);
+                    R[j * LD + i] = h;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (flags[0]) {
+        if (tid == 0) {
+            a.pair_rot[pair] = 0;
+            atomicAdd(&a.counters[C_NONFINITE], 1ull);
+        }
+        return;
+    }
+    if (tid == 0 && flags[1]) atomicAdd(&a.counters[C_BREAKDOWN], (unsigned long long)flags[1]);
+
+    // ---- inner Jacobi (Section 4.3)
+    const bool on_r = tid < HALF;
+    const int gt = on_r ? tid : tid - HALF;
+    const int x = gt & 15;      // first row owned by this lane
+    const int slot = gt >> 4;   // pivot pair of this 16-lane row
+    const double tol = kEps * sqrt((double)BW);  // c(eps) = eps sqrt(nhat), nhat = 2w
+    int rot_total = 0, proper_total = 0, clamp_total = 0, sweeps = 0;
+
+    for (int sw = 0; sw < a.max_inner_sweeps; ++sw) {
+        int rot_sweep = 0;
+        int p = tb[2 * slot], q = tb[2 * slot + 1], f = sfl[slot];
+        for (int st = 0; st < NS + 1; ++st) {
+            if (on_r) {
+                if (st < NS) {
+                    double rp[ROWS], rq[ROWS];
+#pragma unroll
+                    for (int r = 0; r < ROWS; ++r) {
+                        rp[r] = R[p * LD + x + 16 * r];
+                        rq[r] = R[q * LD + x + 16 * r];
+                    }
+                    double hpp = 0.0, hqq = 0.0, hpq = 0.0;
+#pragma unroll
+                    for (int r = 0; r < ROWS; ++r) {
+                        hpp = fma(rp[r], rp[r], hpp);
+                        hqq = fma(rq[r], rq[r], hqq);
+                        hpq = fma(rp[r], rq[r], hpq);
+                    }
+                    hpp = row_sum(hpp);
+                    hqq = row_sum(hqq);
+                    hpq = row_sum(hpq);
+                    // subphase 2: relative orthogonality (reading: <= skips).
+                    // h_pq != 0 implies h_pp, h_qq > 0.
+                    const bool rotate = hpq != 0.0 && !(fabs(hpq) <= tol * nsqrt(hpp) * nsqrt(hqq));
+                    // subphase 4: hyperbolic iff kp < n+ <= kq
+                    const int t = (f & 1) ? -1 : 1;
+                    double tn = 0.0, cs = 1.0;
+                    bool clamped = false;
+                    if (rotate) {
+                        if (in_fast_range(hpp) && in_fast_range(hqq) && in_fast_range(fabs(hpq)))
+                            rotation_fast(hpp, hqq, hpq, t, tn, cs, clamped);
+                        else
+                            rotation(hpp, hqq, hpq, t, tn, cs, clamped);
+                    }
+                    // subphase 5: keep j*sigma^2 non-increasing for trigonometric
+                    // pairs (h_pp' = h_pp - tn h_pq, h_qq' = h_qq + tn h_pq)
+                    bool swap = false;
+                    if (!(f & 3)) {
+                        const double npp = fma(-tn, hpq, hpp);
+                        const double nqq = fma(tn, hpq, hqq);
+                        swap = (f & 4) ? (npp < nqq) : ((f & 8) ? (npp > nqq) : false);
+                    }
+                    // subphase 6, (4.1) / (4.2).  cs == 1 multiplies exactly.
+                    const double mtn = (t > 0) ? -tn : tn;
+                    if (rotate || swap) {
+                        const int cp = swap ? q : p, cq = swap ? p : q;
+#pragma unroll
+                        for (int r = 0; r < ROWS; ++r) {
+                            const double np = cs * fma(mtn, rq[r], rp[r]);
+                            const double nq = cs * fma(tn, rp[r], rq[r]);
+                            R[cp * LD + x + 16 * r] = np;
+                            R[cq * LD + x + 16 * r] = nq;
+                        }
+                    }
+                    if (x == 0) {
+                        prm[st & 1][slot] = d4{mtn, tn, cs, (double)((rotate || swap ? 1 : 0) | (swap ? 2 : 0))};
+                        rot_sweep += rotate ? 1 : 0;
+                        proper_total += (rotate && cs != 1.0) ? 1 : 0;
+                        clamp_total += clamped ? 1 : 0;
+                    }
+                    if (st + 1 < NS) {
+                        p = tb[(st + 1) * BW + 2 * slot];
+                        q = tb[(st + 1) * BW + 2 * slot + 1];
+                        f = sfl[(st + 1) * NP + slot];
+                    }
+                }
+            } else if (st >= 1) {
+                // V' <- V' (rotation of p-step st - 1)
+                const int s1 = st - 1;
+                const d4 pr = prm[s1 & 1][slot];
+                const int fl = (int)pr[3];
+                if (fl & 1) {
+                    const int vp = tb[s1 * BW + 2 * slot], vq = tb[s1 * BW + 2 * slot + 1];
+                    const int cp = (fl & 2) ? vq : vp, cq = (fl & 2) ? vp : vq;
+                    const double mtn = pr[0], tn = pr[1], cs = pr[2];
+                    double xp[ROWS], xq[ROWS];
+#pragma unroll
+                    for (int r = 0; r < ROWS; ++r) {
+                        xp[r] = Vp[vp * LD + x + 16 * r];
+                        xq[r] = Vp[vq * LD + x + 16 * r];
+                    }
+#pragma unroll
+                    for (int r = 0; r < ROWS; ++r) {
+                        Vp[cp * LD + x + 16 * r] = cs * fma(mtn, xq[r], xp[r]);
+                        Vp[cq * LD + x + 16 * r] = cs * fma(tn, xp[r], xq[r]);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        ++sweeps;
+        rot_total += rot_sweep;
+        int rs = rot_sweep;
+        for (int off = 32; off >= 1; off >>= 1) rs += __shfl_xor(rs, off);
+        if (lane == 0) cnt[wave][0] = rs;
+        __syncthreads();
+        int all = 0;
+#pragma unroll
+        for (int wv = 0; wv < NWAVES; ++wv) all += cnt[wv][0];
+        __syncthreads();
+        if (all == 0) break;  // no rotation in the inner sweep
+    }
+
+    // ---- write V'_pq and the counts
+    for (int off = 32; off >= 1; off >>= 1) {
+        rot_total += __shfl_xor(rot_total, off);
+        proper_total += __shfl_xor(proper_total, off);
+        clamp_total += __shfl_xor(clamp_total, off);
+    }
+    double *vout = a.vprime + (size_t)pair * BW * BW;
+    for (int e = tid; e < BW * BW; e += NT) {
+        const int i = e % BW, j = e / BW;
+        vout[j * BW + i] = Vp[j * LD + i];
+    }
+    if (lane == 0) {
+        cnt[wave][0] = rot_total;
+        cnt[wave][1] = proper_total;
+        cnt[wave][2] = clamp_total;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        long long r = 0, pr = 0, cl = 0;
+        for (int wv = 0; wv < NWAVES; ++wv) {
+            r += cnt[wv][0];
+            pr += cnt[wv][1];
+            cl += cnt[wv][2];
+        }
+        a.pair_rot[pair] = (int)r;
+        atomicAdd(&a.counters[C_ROT], (unsigned long long)r);
+        atomicAdd(&a.counters[C_PROPER], (unsigned long long)pr);
+        atomicAdd(&a.counters[C_CLAMP], (unsigned long long)cl);
+        atomicAdd(&a.counters[C_INNER_SW], (unsigned long long)sweeps);
+        if (r) atomicAdd(&a.counters[C_UPDATES], 1ull);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_inner(int bw, const StepArgs &a, hipStream_t s) {
+    if (bw == 32)
+        hipLaunchKernelGGL(inner_kernel<32>, dim3(a.npairs), dim3(InnerCfg<32>::kThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(inner_kernel<64>, dim3(a.npairs), dim3(InnerCfg<64>::kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace jsvd
