@@ -32,14 +32,14 @@ __global__ __launch_bounds__(256) void update_kernel(StepArgs a) {
     const double *vpr = a.vprime + (size_t)pair * BW * BW;
     for (int e = threadIdx.x; e < BW * BW; e += 256) vs[(e % BW) * BW + e / BW] = vpr[e];
 
-    int64_t ldoff[KS];  // column offsets of the B loads (-1: padding)
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        const int64_t gc = pair_col(4 * ks + grp, a.w, pq);
-        ldoff[ks] = gc < a.n ? gc * ldx : -1;
-    }
     __syncthreads();
 
+    // The pair's columns are w consecutive columns of block P, then w of
+    // block Q; local columns past n (padding) are neither loaded nor stored.
+    // Column addresses are recomputed per slice rather than kept in
+    // registers, which keeps four waves per SIMD resident.
+    double *XP = X + (int64_t)pq.x * a.w * ldx, *XQ = X + (int64_t)pq.y * a.w * ldx;
+    const int64_t np = a.n - (int64_t)pq.x * a.w, nq = a.n - (int64_t)pq.y * a.w;
     const int64_t r0 = (int64_t)chunk * a.upd_rows;
     const int64_t r1 = min(rows, r0 + (int64_t)a.upd_rows);
     for (int64_t base = r0 + wave * 16; base < r1; base += 64) {
@@ -50,7 +50,12 @@ __global__ __launch_bounds__(256) void update_kernel(StepArgs a) {
         const bool rv = row < r1;
         double b[KS];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) b[ks] = (rv && ldoff[ks] >= 0) ? X[ldoff[ks] + row] : 0.0;
+        for (int ks = 0; ks < KS; ++ks) {
+            const int c = 4 * ks + grp;
+            const bool in_p = c < a.w;
+            const int lc = in_p ? c : c - a.w;
+            b[ks] = (rv && lc < (in_p ? np : nq)) ? (in_p ? XP : XQ)[(int64_t)lc * ldx + row] : 0.0;
+        }
         d4 acc[JT];
 #pragma unroll
         for (int jt = 0; jt < JT; ++jt) acc[jt] = d4{0.0, 0.0, 0.0, 0.0};
@@ -63,8 +68,10 @@ __global__ __launch_bounds__(256) void update_kernel(StepArgs a) {
         for (int jt = 0; jt < JT; ++jt)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t gc = pair_col(jt * 16 + grp + 4 * v, a.w, pq);
-                if (rv && gc < a.n) X[gc * ldx + row] = acc[jt][v];
+                const int c = jt * 16 + grp + 4 * v;
+                const bool in_p = c < a.w;
+                const int lc = in_p ? c : c - a.w;
+                if (rv && lc < (in_p ? np : nq)) (in_p ? XP : XQ)[(int64_t)lc * ldx + row] = acc[jt][v];
             }
     }
 }
