@@ -12,144 +12,216 @@
 //
 // Work distribution: a persistent grid of workgroups pulls problem indices
 // from a device queue, largest n first (the order comes from a counting
-// sort on the device).  A workgroup (16 waves) owns its problem: every half
-// wave takes one pivot pair of the current p-step, lane x owning rows x,
-// x + 32, ... of the pair's columns (kept in registers between the dot
-// products and the update); the three dot products are half-wave sums.  G
-// is worked on in LDS when it fits (one workgroup per CU, up to ~150 kB),
-// else in its global buffer; V is updated in global memory.  A workgroup
-// barrier separates p-steps.  At the end of a problem the column
-// norms give sigma, the workgroup ranks them (non-increasing, ties by
-// index) and gathers U = G Sigma^{-1} and V in that order through a
-// per-workgroup scratch area.
-#include "jsvd_internal.h"
+// sort on the device).  A workgroup (16 waves) owns its problem.  With V
+// wanted, half waves 0-15 rotate G and half waves 16-31 apply the previous
+// p-step's rotations to V (published in LDS), so V is off the path of the
+// rotations; without V all 32 half waves rotate G.  A half wave takes one
+// pivot pair at a time, lane x owning rows x, x + 32, ... of the pair's
+// columns (kept in registers between the dot products and the update); the
+// three dot products are half-wave sums.  G is worked on in LDS when it fits
+// (one workgroup per CU, ~148 kB), V too when there is room left, else in
+// their global buffers.  A workgroup barrier separates p-steps.  At the end
+// of a problem the column norms give sigma, the workgroup ranks them
+// (non-increasing, ties by index) and gathers U = G Sigma^{-1} and V in that
+// order (through a per-workgroup scratch area for what is in global memory).
+#include "jsvd_device.h"
 
 namespace jsvd {
 
 namespace {
 
-constexpr double kEpsB = 1.1102230246251565e-16;      // 2^-53
-constexpr double kSqrtEpsB = 1.0536712127723509e-08;  // sqrt(2^-53)
-constexpr double kSqrt2OverEpsB = 134217728.0;        // 2^27
-
 __device__ __forceinline__ double hw_sum(double v) {
-    v += __builtin_amdgcn_update_dpp(0.0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-    v += __builtin_amdgcn_update_dpp(0.0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-    v += __builtin_amdgcn_update_dpp(0.0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
-    v += __builtin_amdgcn_update_dpp(0.0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+    v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);  // row_half_mirror
+    v += dpp_mov<0x140>(v);  // row_mirror
     const long long x = __builtin_bit_cast(long long, v);
     const int lo = __builtin_amdgcn_ds_swizzle((int)x, 0x401F);         // lane ^ 16
     const int hi = __builtin_amdgcn_ds_swizzle((int)(x >> 32), 0x401F);
     return v + __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
-// Trigonometric rotation parameters, eqs. (4.3)-(4.6) with t = +1, cs_2.
-__device__ __forceinline__ void trig_rotation(double hpp, double hqq, double hpq, double &tn,
-                                              double &cs) {
-    const double ct2 = (hqq - hpp) / (2.0 * hpq);
-    const double sgn = ct2 < 0.0 ? -1.0 : 1.0;
-    const double a = fabs(ct2);
-    double act;
-    if (a < kSqrtEpsB)
-        act = a + 1.0;
-    else if (a >= kSqrt2OverEpsB)
-        act = 2.0 * a;
-    else
-        act = a + sqrt(fma(a, a, 1.0));
-    tn = sgn * (1.0 / act);
-    cs = (act >= kSqrt2OverEpsB) ? 1.0 : act / sqrt(fma(act, act, 1.0));
+// Relative orthogonality test (subphase 2, reading: <= skips) and the
+// trigonometric rotation, eqs. (4.3)-(4.6) with t = +1 and cs_2: refined
+// reciprocal and square roots inside [2^-900, 2^900], IEEE outside.
+__device__ __forceinline__ bool trig_pair(double hpp, double hqq, double hpq, double tol,
+                                          double &tn, double &cs) {
+    bool clamped;
+    if (in_fast_range(hpp) && in_fast_range(hqq) && in_fast_range(fabs(hpq))) {
+        if (fabs(hpq) <= tol * nsqrt(hpp) * nsqrt(hqq)) return false;
+        rotation_fast(hpp, hqq, hpq, 1, tn, cs, clamped);
+    } else {
+        if (!(hpq != 0.0) || fabs(hpq) <= tol * sqrt(hpp) * sqrt(hqq)) return false;
+        rotation(hpp, hqq, hpq, 1, tn, cs, clamped);
+    }
+    return true;
 }
 
 constexpr int kBatchThreads = 1024;  // 16 waves, 32 half-wave pair groups
 constexpr int kGroups = kBatchThreads / 32;
 
 // One sweep-loop of the pointwise method on a problem whose working copy of
-// G is Gw (LDS or global; column-major, ld = m) and whose V is in global
-// memory.  R > 0: every lane keeps its R rows of the pair's columns in
-// registers between the dot products and the update (m <= 32 R); R = 0:
-// any m, two passes over the columns.  Returns the sweeps performed; sets
-// *converged when a sweep performed no proper rotation.
-template <int R>
-__device__ int pointwise_sweeps(double *Gw, double *V, int m, int n, int N,
+// G is Gw and of V is Vw (each in LDS or global memory, column-major, ld = m
+// and n; Vw may be null).  R > 0: every lane keeps its R rows of the pair's
+// columns in registers between the dot products and the update (m <= 32 R),
+// and a half wave takes K of its pivot pairs at once, so that their
+// dependent chains (sums, square roots, divisions) overlap; R = 0: any m,
+// one pair at a time, two passes over the columns.  Rotations go from the G
+// half waves to the V half waves through (tn, cs) slots in LDS,
+// double-buffered by p-step; cs = 0 marks a pair that did not rotate.
+// Returns the sweeps performed; sets *converged when a sweep performed no
+// proper rotation.
+template <int R, int K>
+__device__ int pointwise_sweeps(double *Gw, double *Vw, int m, int n, int N,
                                 const unsigned char *tbl, int max_sweeps, double tol,
-                                int *s_rot, bool *converged) {
+                                int *s_rot, double (*s_tn)[kBatchMaxN / 2],
+                                double (*s_cs)[kBatchMaxN / 2], bool *converged) {
     const int tid = threadIdx.x, x = tid & 31, group = tid >> 5;
     const int half = N >> 1;
+    const int ng = Vw ? kGroups / 2 : kGroups;   // half waves on G
+    const bool on_g = group < ng;
+    const int gi = on_g ? group : group - ng;
+    const int gstride = on_g ? ng : kGroups - ng;
+    const int nsteps = N - 1 + (Vw ? 1 : 0);    // V trails G by one p-step
     int sweeps = 0;
     *converged = false;
     while (sweeps < max_sweeps) {
         if (tid == 0) *s_rot = 0;
         int rot = 0;  // this half wave's proper rotations in the sweep
-        for (int st = 0; st < N - 1; ++st) {
-            const unsigned char *ps = tbl + (size_t)st * N;
-            for (int slot = group; slot < half; slot += kGroups) {
-                const int p = ps[2 * slot], q = ps[2 * slot + 1];
-                if (q >= n) continue;  // padding index: uniform in the half wave
-                double *gp = Gw + (size_t)p * m, *gq = Gw + (size_t)q * m;
-                double *vp = V ? V + (size_t)p * n : nullptr, *vq = V ? V + (size_t)q * n : nullptr;
-                double hpp = 0.0, hqq = 0.0, hpq = 0.0;
+        for (int st = 0; st < nsteps; ++st) {
+            if (on_g && st < N - 1) {
+                const unsigned char *ps = tbl + (size_t)st * N;
                 if constexpr (R > 0) {
-                    double a[R], b[R], c[R], d[R];
+                    for (int s0 = gi; s0 < half; s0 += K * gstride) {
+                        int pk[K], qk[K];
+                        bool use[K];
+                        double a[K][R], b[K][R], hpp[K], hqq[K], hpq[K];
 #pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const int i = x + 32 * r;
-                        a[r] = i < m ? gp[i] : 0.0;
-                        b[r] = i < m ? gq[i] : 0.0;
-                        c[r] = (V && i < n) ? vp[i] : 0.0;
-                        d[r] = (V && i < n) ? vq[i] : 0.0;
-                    }
+                        for (int k = 0; k < K; ++k) {
+                            const int slot = s0 + k * gstride;
+                            pk[k] = slot < half ? ps[2 * slot] : 0;
+                            qk[k] = slot < half ? ps[2 * slot + 1] : n;
+                            use[k] = qk[k] < n;  // padding index or no slot: uniform in the half wave
 #pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        hpp = fma(a[r], a[r], hpp);
-                        hqq = fma(b[r], b[r], hqq);
-                        hpq = fma(a[r], b[r], hpq);
-                    }
-                    hpp = hw_sum(hpp);
-                    hqq = hw_sum(hqq);
-                    hpq = hw_sum(hpq);
-                    if (fabs(hpq) <= tol * sqrt(hpp) * sqrt(hqq)) continue;  // subphase 2
-                    double tn, cs;
-                    trig_rotation(hpp, hqq, hpq, tn, cs);
-                    rot += cs != 1.0 ? 1 : 0;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const int i = x + 32 * r;
-                        const double np_ = cs == 1.0 ? fma(-tn, b[r], a[r]) : cs * fma(-tn, b[r], a[r]);
-                        const double nq_ = cs == 1.0 ? fma(tn, a[r], b[r]) : cs * fma(tn, a[r], b[r]);
-                        if (i < m) {
-                            gp[i] = np_;
-                            gq[i] = nq_;
+                            for (int r = 0; r < R; ++r) {
+                                const int i = x + 32 * r;
+                                a[k][r] = (use[k] && i < m) ? Gw[(size_t)pk[k] * m + i] : 0.0;
+                                b[k][r] = (use[k] && i < m) ? Gw[(size_t)qk[k] * m + i] : 0.0;
+                            }
                         }
-                        if (V && i < n) {
-                            vp[i] = cs == 1.0 ? fma(-tn, d[r], c[r]) : cs * fma(-tn, d[r], c[r]);
-                            vq[i] = cs == 1.0 ? fma(tn, c[r], d[r]) : cs * fma(tn, c[r], d[r]);
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            hpp[k] = hqq[k] = hpq[k] = 0.0;
+#pragma unroll
+                            for (int r = 0; r < R; ++r) {
+                                hpp[k] = fma(a[k][r], a[k][r], hpp[k]);
+                                hqq[k] = fma(b[k][r], b[k][r], hqq[k]);
+                                hpq[k] = fma(a[k][r], b[k][r], hpq[k]);
+                            }
+                        }
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            hpp[k] = hw_sum(hpp[k]);
+                            hqq[k] = hw_sum(hqq[k]);
+                            hpq[k] = hw_sum(hpq[k]);
+                        }
+                        // subphases 2-5, branch-free while every operand lies in
+                        // the range of the refined arithmetic (the usual case)
+                        bool fast = true;
+#pragma unroll
+                        for (int k = 0; k < K; ++k)
+                            fast = fast && (!use[k] || (in_fast_range(hpp[k]) && in_fast_range(hqq[k]) &&
+                                                        (hpq[k] == 0.0 || in_fast_range(fabs(hpq[k])))));
+                        double tn[K], cs[K];
+                        bool rk[K];
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            if (K == 1) {  // one pair: skip the rotation when the test says so
+                                tn[k] = 0.0;
+                                cs[k] = 0.0;
+                                rk[k] = use[k] && trig_pair(hpp[k], hqq[k], hpq[k], tol, tn[k], cs[k]);
+                            } else if (fast) {
+                                bool clamped;
+                                rk[k] = use[k] && hpq[k] != 0.0 &&
+                                        !(fabs(hpq[k]) <= tol * nsqrt(hpp[k]) * nsqrt(hqq[k]));
+                                rotation_fast(hpp[k], hqq[k], hpq[k] != 0.0 ? hpq[k] : 1.0, 1, tn[k],
+                                              cs[k], clamped);
+                            } else {
+                                tn[k] = 0.0;
+                                cs[k] = 0.0;
+                                rk[k] = use[k] && trig_pair(hpp[k], hqq[k], hpq[k], tol, tn[k], cs[k]);
+                            }
+                            if (!rk[k]) cs[k] = 0.0;
+                        }
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            if (rk[k]) {
+                                rot += cs[k] != 1.0 ? 1 : 0;
+                                // (4.1); cs == 1 multiplies exactly
+#pragma unroll
+                                for (int r = 0; r < R; ++r) {
+                                    const int i = x + 32 * r;
+                                    const double np_ = cs[k] * fma(-tn[k], b[k][r], a[k][r]);
+                                    const double nq_ = cs[k] * fma(tn[k], a[k][r], b[k][r]);
+                                    if (i < m) {
+                                        Gw[(size_t)pk[k] * m + i] = np_;
+                                        Gw[(size_t)qk[k] * m + i] = nq_;
+                                    }
+                                }
+                            }
+                            if (Vw && x == 0 && use[k]) {
+                                const int slot = s0 + k * gstride;
+                                s_tn[st & 1][slot] = tn[k];
+                                s_cs[st & 1][slot] = cs[k];
+                            }
                         }
                     }
                 } else {
-                    for (int i = x; i < m; i += 32) {
-                        const double a0 = gp[i], b0 = gq[i];
-                        hpp = fma(a0, a0, hpp);
-                        hqq = fma(b0, b0, hqq);
-                        hpq = fma(a0, b0, hpq);
-                    }
-                    hpp = hw_sum(hpp);
-                    hqq = hw_sum(hqq);
-                    hpq = hw_sum(hpq);
-                    if (fabs(hpq) <= tol * sqrt(hpp) * sqrt(hqq)) continue;  // subphase 2
-                    double tn, cs;
-                    trig_rotation(hpp, hqq, hpq, tn, cs);
-                    rot += cs != 1.0 ? 1 : 0;
-                    for (int i = x; i < m; i += 32) {
-                        const double a0 = gp[i], b0 = gq[i];
-                        gp[i] = cs == 1.0 ? fma(-tn, b0, a0) : cs * fma(-tn, b0, a0);
-                        gq[i] = cs == 1.0 ? fma(tn, a0, b0) : cs * fma(tn, a0, b0);
-                    }
-                    if (V)
-                        for (int i = x; i < n; i += 32) {
-                            const double a0 = vp[i], b0 = vq[i];
-                            vp[i] = cs == 1.0 ? fma(-tn, b0, a0) : cs * fma(-tn, b0, a0);
-                            vq[i] = cs == 1.0 ? fma(tn, a0, b0) : cs * fma(tn, a0, b0);
+                    for (int slot = gi; slot < half; slot += gstride) {
+                        const int p = ps[2 * slot], q = ps[2 * slot + 1];
+                        if (q >= n) continue;  // padding index: uniform in the half wave
+                        double *gp = Gw + (size_t)p * m, *gq = Gw + (size_t)q * m;
+                        double hpp = 0.0, hqq = 0.0, hpq = 0.0, tn = 0.0, cs = 0.0;
+                        for (int i = x; i < m; i += 32) {
+                            const double a0 = gp[i], b0 = gq[i];
+                            hpp = fma(a0, a0, hpp);
+                            hqq = fma(b0, b0, hqq);
+                            hpq = fma(a0, b0, hpq);
                         }
+                        hpp = hw_sum(hpp);
+                        hqq = hw_sum(hqq);
+                        hpq = hw_sum(hpq);
+                        if (trig_pair(hpp, hqq, hpq, tol, tn, cs)) {
+                            rot += cs != 1.0 ? 1 : 0;
+                            for (int i = x; i < m; i += 32) {
+                                const double a0 = gp[i], b0 = gq[i];
+                                gp[i] = cs * fma(-tn, b0, a0);
+                                gq[i] = cs * fma(tn, a0, b0);
+                            }
+                        } else {
+                            cs = 0.0;
+                        }
+                        if (Vw && x == 0) {
+                            s_tn[st & 1][slot] = tn;
+                            s_cs[st & 1][slot] = cs;
+                        }
+                    }
+                }
+            } else if (!on_g && st >= 1) {
+                const int s1 = st - 1;
+                const unsigned char *ps = tbl + (size_t)s1 * N;
+                for (int slot = gi; slot < half; slot += gstride) {
+                    const int p = ps[2 * slot], q = ps[2 * slot + 1];
+                    if (q >= n) continue;
+                    const double cs = s_cs[s1 & 1][slot];
+                    if (cs == 0.0) continue;
+                    const double tn = s_tn[s1 & 1][slot];
+                    double *vp = Vw + (size_t)p * n, *vq = Vw + (size_t)q * n;
+                    for (int i = x; i < n; i += 32) {
+                        const double a0 = vp[i], b0 = vq[i];
+                        vp[i] = cs * fma(-tn, b0, a0);
+                        vq[i] = cs * fma(tn, a0, b0);
+                    }
                 }
             }
             __syncthreads();
@@ -173,6 +245,8 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs b) {
     __shared__ int s_rot;
     __shared__ double s_sig[kBatchMaxN];
     __shared__ int s_perm[kBatchMaxN];
+    __shared__ double s_tn[2][kBatchMaxN / 2];  // published rotations, by p-step parity
+    __shared__ double s_cs[2][kBatchMaxN / 2];
     const int tid = threadIdx.x, x = tid & 31;
     const int group = tid >> 5;  // half wave
     double *scratch = b.scratch + (size_t)blockIdx.x * b.scratch_per_wg;
@@ -189,28 +263,32 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs b) {
         double *V = b.V ? b.V + b.v_off[id] : nullptr;
         const int N = b.tbl_order[n];
         const unsigned char *tbl = b.tbls + b.tbl_off[N >> 1];
-        const double tol = kEpsB * sqrt((double)m);  // c(eps) = eps sqrt(m)
+        const double tol = kEps * sqrt((double)m);  // c(eps) = eps sqrt(m)
+        // G in LDS when it fits, then V in what is left
         const bool in_lds = (int64_t)m * n <= b.lds_doubles;
+        const int64_t v_at = in_lds ? (int64_t)m * n : 0;
+        const bool v_lds = V && v_at + (int64_t)n * n <= b.lds_doubles;
         double *Gw = in_lds ? lds_g : G;
+        double *Vw = v_lds ? lds_g + v_at : V;
 
         if (in_lds)
             for (int e = tid; e < m * n; e += kBatchThreads) lds_g[e] = G[e];
         if (V)
-            for (int e = tid; e < n * n; e += kBatchThreads) V[e] = (e % n == e / n) ? 1.0 : 0.0;
+            for (int e = tid; e < n * n; e += kBatchThreads) Vw[e] = (e % n == e / n) ? 1.0 : 0.0;
         __syncthreads();
 
         bool converged = false;
         int sweeps;
         if (m <= 32)
-            sweeps = pointwise_sweeps<1>(Gw, V, m, n, N, tbl, b.max_sweeps, tol, &s_rot, &converged);
+            sweeps = pointwise_sweeps<1, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, &s_rot, s_tn, s_cs, &converged);
         else if (m <= 64)
-            sweeps = pointwise_sweeps<2>(Gw, V, m, n, N, tbl, b.max_sweeps, tol, &s_rot, &converged);
+            sweeps = pointwise_sweeps<2, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, &s_rot, s_tn, s_cs, &converged);
         else if (m <= 128)
-            sweeps = pointwise_sweeps<4>(Gw, V, m, n, N, tbl, b.max_sweeps, tol, &s_rot, &converged);
+            sweeps = pointwise_sweeps<4, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, &s_rot, s_tn, s_cs, &converged);
         else if (m <= 192)
-            sweeps = pointwise_sweeps<6>(Gw, V, m, n, N, tbl, b.max_sweeps, tol, &s_rot, &converged);
+            sweeps = pointwise_sweeps<6, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, &s_rot, s_tn, s_cs, &converged);
         else
-            sweeps = pointwise_sweeps<0>(Gw, V, m, n, N, tbl, b.max_sweeps, tol, &s_rot, &converged);
+            sweeps = pointwise_sweeps<0, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, &s_rot, s_tn, s_cs, &converged);
 
         // sigma_j = ||g_j||, output order, U = G Sigma^{-1}, V permuted
         for (int j = group; j < n; j += kGroups) {
@@ -235,8 +313,11 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs b) {
             for (int e = tid; e < m * n; e += kBatchThreads) scratch[e] = G[e];
             src = scratch;
         }
-        if (V)
+        const double *vsrc = Vw;
+        if (V && !v_lds) {
             for (int e = tid; e < n * n; e += kBatchThreads) scratch[(size_t)m * n + e] = V[e];
+            vsrc = scratch + (size_t)m * n;
+        }
         __syncthreads();
         double *S = b.S + b.s_off[id];
         for (int e = tid; e < m * n; e += kBatchThreads) {
@@ -247,7 +328,7 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs b) {
         if (V)
             for (int e = tid; e < n * n; e += kBatchThreads) {
                 const int k = e / n, i = e % n;
-                V[e] = scratch[(size_t)m * n + (size_t)s_perm[k] * n + i];
+                V[e] = vsrc[(size_t)s_perm[k] * n + i];
             }
         for (int k = tid; k < n; k += kBatchThreads) S[k] = s_sig[s_perm[k]];
         if (tid == 0) {

@@ -499,7 +499,7 @@ int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t ma
         // LDS for the working copy of G: what the CU has, less the static part
         const size_t lds_total = prop.sharedMemPerMultiprocessor ? prop.sharedMemPerMultiprocessor
                                                                  : prop.sharedMemPerBlock;
-        h->batch_lds = (int)std::min<size_t>(lds_total, 160 * 1024) - 8 * 1024;
+        h->batch_lds = (int)std::min<size_t>(lds_total, 160 * 1024) - 12 * 1024;
         if (h->batch_lds < 0 || batched_set_lds(h->batch_lds) != hipSuccess) h->batch_lds = 0;
     }
     const int grid = (int)std::min<int64_t>(batch, std::max(1, h->cu_count));
