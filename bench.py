@@ -306,6 +306,19 @@ def main():
     roof["traffic"] = measured_traffic(dominant, w)
     roof["algorithmic_per_launch"] = {k: v for k, v in per_launch.items()
                                       if k.startswith(dominant)}
+    # FP64 MFMA rate of the two contraction kernels over their HIP-event
+    # times.  The Gram kernel forms only the T(T+1)/2 tiles on and above the
+    # diagonal of each pair's (2w)^2 Gram matrix (T = 2w/16): executed FLOPs
+    # are reported beside the full-tile count of the algorithm.
+    tiles = bw // 16
+    gram_exec = per_launch["gram_flops"] * (tiles * (tiles + 1) / 2) / (tiles * tiles)
+    mfma = {"peak_tflops": PEAK_FP64_TFLOPS}
+    for name, fl in (("gram", gram_exec), ("update", per_launch["update_flops"])):
+        tf = fl / (avg[name] * 1e-3) / 1e12
+        mfma[name] = {"executed_flops_per_launch": fl, "tflops": tf,
+                      "frac": tf / PEAK_FP64_TFLOPS, "avg_launch_us": avg[name] * 1e3}
+    mfma["gram"]["algorithmic_full_tile_tflops"] = (
+        per_launch["gram_flops"] / (avg["gram"] * 1e-3) / 1e12)
 
     # accuracy of the last step against properties that hold at any size
     Ucm = work.t()
@@ -340,6 +353,7 @@ def main():
                    "max_inner_sweeps": args.max_inner_sweeps, "sweeps": sweeps,
                    "rotations": rotations[-1]},
         "roofline": roof,
+        "mfma": mfma,
         "kernels_avg_us": {k: avg[k] * 1e3 for k in avg},
         "kernels_share": {k: kt[k][0] / max(sum(v[0] for v in kt.values()), 1e-9) for k in kt},
         "accuracy": {"fro2_rel": abs(sum_s2 - fro2) / fro2, "orth_u": orth_u, "orth_v": orth_v},

@@ -2,6 +2,7 @@
 
     python -m paper_1401_2720_amd.prof_summary traffic FETCH.csv WRITE.csv OUT.json
     python -m paper_1401_2720_amd.prof_summary stats KERNEL_STATS.csv
+    python -m paper_1401_2720_amd.prof_summary mfma MFMA.csv KERNEL_STATS.csv
 
 ``traffic`` reads two ``rocprofv3 --pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
 counter collections of the same program, averages the counters (KiB per
@@ -13,6 +14,13 @@ Each kernel's entry carries the SHA-256 of the sources it is built from, so
 that a reader can tell whether the figures still describe the code.
 
 ``stats`` prints a markdown table of a ``--kernel-trace --stats`` summary.
+
+``mfma`` reads a ``rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_F64
+SQ_VALU_MFMA_BUSY_CYCLES`` collection (FP64 MFMA operations / 512 and MFMA
+busy cycles summed over SIMDs, per dispatch) and the kernel-trace summary of
+the same workload, and prints per p-step kernel the MFMA FLOPs per launch,
+the achieved FP64 MFMA rate over the traced average duration and the MFMA
+pipe's busy fraction (busy cycles per SIMD / duration in cycles).
 """
 import argparse
 import collections
@@ -100,6 +108,38 @@ def stats(path, keep="jsvd"):
               f"{float(row['MinNs']) / 1e3:.1f} | {float(row['MaxNs']) / 1e3:.1f} |")
 
 
+def mfma(counter_csv, stats_csv, simds=1024, clock_ghz=2.4, peak_tflops=78.6):
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    for row in csv.DictReader(open(counter_csv)):
+        m = PSTEP.search(row["Kernel_Name"])
+        if m:
+            per[m.group(0)][row["Counter_Name"]].append(float(row["Counter_Value"]))
+    avg_us = {}
+    for row in csv.DictReader(open(stats_csv)):
+        m = PSTEP.search(row["Name"])
+        if m:
+            avg_us[m.group(0)] = float(row["AverageNs"]) / 1e3
+    print("| kernel | FP64 MFMA FLOP per launch (mean / max) | MFMA busy cycles per SIMD (mean) | "
+          "average duration (us) | achieved TFLOP/s | of 78.6 peak | MFMA pipe busy |")
+    print("|---|---|---|---|---|---|---|")
+    out = {}
+    for name in sorted(per):
+        mops = per[name].get("SQ_INSTS_VALU_MFMA_MOPS_F64", [0.0])
+        busy = per[name].get("SQ_VALU_MFMA_BUSY_CYCLES", [0.0])
+        flops, fmax = 512 * sum(mops) / len(mops), 512 * max(mops)
+        if flops == 0 or name not in avg_us:
+            continue
+        b = sum(busy) / len(busy) / simds
+        us = avg_us[name]
+        tf = flops / (us * 1e-6) / 1e12
+        frac_busy = b / (us * 1e-6 * clock_ghz * 1e9)
+        out[name] = dict(flops=flops, flops_max=fmax, busy_per_simd=b, avg_us=us, tflops=tf,
+                         peak_frac=tf / peak_tflops, busy_frac=frac_busy)
+        print(f"| {name} | {flops / 1e9:.3f} G / {fmax / 1e9:.3f} G | {b:.0f} | {us:.1f} | {tf:.1f} | "
+              f"{100 * tf / peak_tflops:.1f} % | {100 * frac_busy:.1f} % |")
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -111,6 +151,9 @@ def main(argv=None):
     t.add_argument("--calib-bytes", type=int, default=4096 * 4096 * 8)
     t.add_argument("--workload", default="")
     t.add_argument("--command", default="")
+    mf = sub.add_parser("mfma")
+    mf.add_argument("counter_csv")
+    mf.add_argument("stats_csv")
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--keep", default="jsvd")
@@ -120,6 +163,8 @@ def main(argv=None):
                       a.workload, a.command)
         json.dump(rec, sys.stdout, indent=1)
         print()
+    elif a.cmd == "mfma":
+        mfma(a.counter_csv, a.stats_csv)
     else:
         stats(a.csv, a.keep)
 
