@@ -56,7 +56,8 @@ extern "C" {
 typedef struct jsvd_handle_s *jsvd_handle_t;
 
 typedef struct {
-    int32_t block_w;          /* block-column width w: 0 = choose by size, else 16 or 32 */
+    int32_t block_w;          /* block-column width w: 0 = choose (tuning table of the handle,
+                                 else by size), else 16 or 32 */
     int32_t strategy;         /* JSVD_STRAT_* (default JSVD_STRAT_RREV) */
     int32_t max_inner_sweeps; /* M_s of Section 4.3: 0 = choose (default: 1), 1 = block-oriented,
                                  > 1 = full block (the paper's setting is 30) */
@@ -79,6 +80,30 @@ typedef struct {
     int32_t n_blocks;          /* block-columns in the pivot strategy (with padding) */
     double seconds;            /* wall time of the call */
 } jsvd_info;
+
+/*
+ * Choices measured on the device by the project's autotuner
+ * (python -m paper_1401_2720_amd.autotune), which a handle can hold in place
+ * of its built-in size rule.
+ *   count          : entries used in n_upper and block_w, 1..8 (0: no w table).
+ *   n_upper[i]     : strictly increasing; a problem takes the block_w of the
+ *                    first entry with n <= n_upper[i], or of the last entry.
+ *   block_w[i]     : 16 or 32.
+ *   batch_g_groups : of the 32 half waves of a batched workgroup, those that
+ *                    rotate G when V is wanted (the others apply the
+ *                    rotations to V); 0 = built-in (16), else 4..28.
+ */
+typedef struct {
+    int32_t count;
+    int64_t n_upper[8];
+    int32_t block_w[8];
+    int32_t batch_g_groups;
+} jsvd_tuning;
+
+/* Install (tuning != NULL, copied) or remove (NULL) the tuned choices of a
+ * handle: they decide w when opts->block_w == 0 and the batched kernel's
+ * split.  Returns JSVD_OK, -1 if h is NULL, -2 for an invalid table. */
+int jsvd_set_tuning(jsvd_handle_t h, const jsvd_tuning *tuning);
 
 /* Fill *opts with the defaults listed above.  Returns JSVD_OK, or -1 if
  * opts is NULL. */
@@ -154,7 +179,8 @@ int jsvd_hsvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
  *   status       : device int32[batch] or NULL: 0 converged, JSVD_NOT_CONVERGED otherwise.
  *   sweeps       : device int32[batch] or NULL: sweeps performed.
  * Only opts->max_sweeps and opts->want_v are used (block_w does not apply:
- * the problems are not blocked).  The work is enqueued on the handle's
+ * the problems are not blocked); the handle's tuned batch_g_groups, if any,
+ * sets how a workgroup divides its half waves between G and V.  The work is enqueued on the handle's
  * stream and the call returns without waiting, so a caller can capture it
  * into a HIP graph once the first call (which allocates the workspace and
  * uploads the strategy tables) has run; the problems must not overlap in A,

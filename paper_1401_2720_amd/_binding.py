@@ -37,6 +37,14 @@ class Info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("count", _i32), ("n_upper", _i64 * 8), ("block_w", _i32 * 8),
+                ("batch_g_groups", _i32)]
+
+
+TUNING_PATH = os.path.join(HERE, "tuning.json")
+
+
 class JsvdError(RuntimeError):
     def __init__(self, code, what):
         super().__init__(f"{what}: status {code} ({STATUS.get(code, 'invalid argument' if code < 0 else '?')})")
@@ -47,7 +55,7 @@ _LIB = None
 EXPORTS = ["jsvd_default_opts", "jsvd_create", "jsvd_set_stream", "jsvd_destroy", "jsvd_gesvd",
            "jsvd_hsvd", "jsvd_strategy_table", "jsvd_strategy_order", "jsvd_error_string",
            "jsvd_diag_fp64", "jsvd_kernel_timing", "jsvd_kernel_times", "jsvd_gesvd_batched",
-           "jsvd_svd_backward"]
+           "jsvd_svd_backward", "jsvd_set_tuning"]
 
 
 def lib():
@@ -76,6 +84,7 @@ def lib():
     L.jsvd_gesvd_batched.argtypes = [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                      _vp, ctypes.POINTER(Opts), _vp, _vp]
     L.jsvd_svd_backward.argtypes = [_vp, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.jsvd_set_tuning.argtypes = [_vp, ctypes.POINTER(Tuning)]
     L.jsvd_kernel_timing.argtypes = [_vp, ctypes.c_int]
     L.jsvd_kernel_times.argtypes = [_vp, _vp, _vp]
     for f in ("jsvd_default_opts", "jsvd_create", "jsvd_set_stream", "jsvd_destroy",
@@ -103,10 +112,57 @@ def _handle(device_index, stream_ptr):
                 raise JsvdError(rc, "jsvd_create")
         h = hp
         _HANDLES[device_index] = h
+        table = load_tuning(device_index)
+        if table is not None:
+            set_tuning(device_index, table, handle=h)
     rc = L.jsvd_set_stream(h, _vp(stream_ptr))
     if rc:
         raise JsvdError(rc, "jsvd_set_stream")
     return h
+
+
+def tuning_struct(table):
+    """The jsvd_tuning of a table {"n_upper": [...], "block_w": [...],
+    "batch_g_groups": int} (raises ValueError if it cannot be one)."""
+    nu, bw = list(table.get("n_upper", [])), list(table.get("block_w", []))
+    if len(nu) != len(bw) or len(nu) > 8:
+        raise ValueError("n_upper and block_w must have the same length, at most 8")
+    t = Tuning()
+    t.count = len(nu)
+    for i, (a, b) in enumerate(zip(nu, bw)):
+        t.n_upper[i] = int(a)
+        t.block_w[i] = int(b)
+    t.batch_g_groups = int(table.get("batch_g_groups", 0))
+    return t
+
+
+def load_tuning(device_index=None, path=None):
+    """The tuned table of the autotuner's file for this device's architecture,
+    or None (no file, or tuned on another architecture)."""
+    import json
+    path = path or TUNING_PATH
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if device_index is not None:
+        import torch
+        arch = torch.cuda.get_device_properties(device_index).gcnArchName.split(":")[0]
+        if rec.get("arch") != arch:
+            return None
+    return rec.get("table")
+
+
+def set_tuning(device_index, table, handle=None):
+    """Install a tuned table on the device's handle (None removes it)."""
+    h = handle if handle is not None else _HANDLES.get(device_index)
+    if h is None:
+        import torch
+        h = _handle(device_index, torch.cuda.current_stream(device_index).cuda_stream)
+    t = tuning_struct(table) if table is not None else None
+    rc = lib().jsvd_set_tuning(h, ctypes.byref(t) if t is not None else None)
+    if rc:
+        raise JsvdError(rc, "jsvd_set_tuning")
 
 
 def make_opts(block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,

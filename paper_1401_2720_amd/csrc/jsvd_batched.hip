@@ -13,9 +13,9 @@
 // Work distribution: a persistent grid of workgroups pulls problem indices
 // from a device queue, largest n first (the order comes from a counting
 // sort on the device).  A workgroup (16 waves) owns its problem.  With V
-// wanted, half waves 0-15 rotate G and half waves 16-31 apply the previous
-// p-step's rotations to V (published in LDS), so V is off the path of the
-// rotations; without V all 32 half waves rotate G.  A half wave takes one
+// wanted, the first g_groups half waves (16 unless tuned) rotate G and the
+// others apply the previous p-step's rotations to V (published in LDS), so V
+// is off the path of the rotations; without V all 32 half waves rotate G.  A half wave takes one
 // pivot pair at a time, lane x owning rows x, x + 32, ... of the pair's
 // columns (kept in registers between the dot products and the update); the
 // three dot products are half-wave sums.  G is worked on in LDS when it fits
@@ -73,12 +73,12 @@ constexpr int kGroups = kBatchThreads / 32;
 // proper rotation.
 template <int R, int K>
 __device__ int pointwise_sweeps(double *Gw, double *Vw, int m, int n, int N,
-                                const unsigned char *tbl, int max_sweeps, double tol,
+                                const unsigned char *tbl, int max_sweeps, double tol, int g_groups,
                                 int *s_rot, double (*s_tn)[kBatchMaxN / 2],
                                 double (*s_cs)[kBatchMaxN / 2], bool *converged) {
     const int tid = threadIdx.x, x = tid & 31, group = tid >> 5;
     const int half = N >> 1;
-    const int ng = Vw ? kGroups / 2 : kGroups;   // half waves on G
+    const int ng = Vw ? g_groups : kGroups;      // half waves on G
     const bool on_g = group < ng;
     const int gi = on_g ? group : group - ng;
     const int gstride = on_g ? ng : kGroups - ng;
@@ -280,15 +280,15 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs b) {
         bool converged = false;
         int sweeps;
         if (m <= 32)
-            sweeps = pointwise_sweeps<1, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, &s_rot, s_tn, s_cs, &converged);
+            sweeps = pointwise_sweeps<1, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged);
         else if (m <= 64)
-            sweeps = pointwise_sweeps<2, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, &s_rot, s_tn, s_cs, &converged);
+            sweeps = pointwise_sweeps<2, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged);
         else if (m <= 128)
-            sweeps = pointwise_sweeps<4, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, &s_rot, s_tn, s_cs, &converged);
+            sweeps = pointwise_sweeps<4, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged);
         else if (m <= 192)
-            sweeps = pointwise_sweeps<6, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, &s_rot, s_tn, s_cs, &converged);
+            sweeps = pointwise_sweeps<6, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged);
         else
-            sweeps = pointwise_sweeps<0, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, &s_rot, s_tn, s_cs, &converged);
+            sweeps = pointwise_sweeps<0, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged);
 
         // sigma_j = ||g_j||, output order, U = G Sigma^{-1}, V permuted
         for (int j = group; j < n; j += kGroups) {

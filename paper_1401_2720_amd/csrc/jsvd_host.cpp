@@ -36,6 +36,7 @@ struct jsvd_handle_s {
     void *batch_meta = nullptr;     // int tbl_order[kBatchMaxN+1], int64 tbl_off[kBatchMaxN/2+1]
     int cu_count = 0;
     int batch_lds = 0;              // dynamic LDS bytes of the batched kernel
+    jsvd_tuning tuning{};           // measured choices (count == 0: none)
     // per-kernel timing (measurement aid): 4 events per p-step
     bool timing = false;
     std::vector<hipEvent_t> events;
@@ -168,7 +169,13 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
           const int *perm_in_host) {
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = h->stream;
-    const int w = o.block_w ? o.block_w : choose_w(m, n);
+    int w = o.block_w;
+    if (!w && h->tuning.count > 0) {
+        int i = 0;
+        while (i + 1 < h->tuning.count && n > h->tuning.n_upper[i]) ++i;
+        w = h->tuning.block_w[i];
+    }
+    if (!w) w = choose_w(m, n);
     const int bw = 2 * w;
     const int nb_real = (int)((n + w - 1) / w);
     const int order = strategy_order(nb_real);
@@ -358,6 +365,22 @@ int jsvd_set_stream(jsvd_handle_t h, void *hip_stream) {
     return JSVD_OK;
 }
 
+int jsvd_set_tuning(jsvd_handle_t h, const jsvd_tuning *t) {
+    if (!h) return -1;
+    if (!t) {
+        h->tuning = jsvd_tuning{};
+        return JSVD_OK;
+    }
+    if (t->count < 0 || t->count > 8) return -2;
+    for (int i = 0; i < t->count; ++i) {
+        if (t->block_w[i] != 16 && t->block_w[i] != 32) return -2;
+        if (i > 0 && t->n_upper[i] <= t->n_upper[i - 1]) return -2;
+    }
+    if (t->batch_g_groups != 0 && (t->batch_g_groups < 4 || t->batch_g_groups > 28)) return -2;
+    h->tuning = *t;
+    return JSVD_OK;
+}
+
 int jsvd_destroy(jsvd_handle_t h) {
     if (!h) return -1;
     (void)hipStreamSynchronize(h->stream);
@@ -535,6 +558,7 @@ int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t ma
     b.status = status;
     b.sweeps = sweeps;
     b.lds_doubles = h->batch_lds / (int64_t)sizeof(double);
+    b.g_groups = h->tuning.batch_g_groups ? h->tuning.batch_g_groups : 16;
     HIP_TRY(launch_batched(b, grid, max_n, reinterpret_cast<int *>(ws + off_hist),
                            reinterpret_cast<int32_t *>(ws + off_order), st));
     return JSVD_OK;

@@ -80,6 +80,7 @@ struct BatchArgs {
     int max_sweeps;
     int32_t *status, *sweeps;                   // device, per problem (may be null)
     int64_t lds_doubles;                        // problems with m n <= this work in LDS
+    int g_groups;                               // half waves rotating G when V is wanted (of 32)
 };
 
 hipError_t batched_set_lds(int bytes);

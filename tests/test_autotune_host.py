@@ -1,0 +1,35 @@
+"""Host logic of the autotuner and of the tuning table (no GPU): the
+compression of per-size winners into the (n_upper, block_w) table, and the
+jsvd_tuning structure the binding builds from it."""
+import pytest
+
+from paper_1401_2720_amd import _binding as B
+from paper_1401_2720_amd import autotune
+
+
+def test_table_from_merges_runs_of_the_same_width():
+    rows = [{"n": 256, "block_w": 16}, {"n": 1024, "block_w": 16}, {"n": 512, "block_w": 16},
+            {"n": 2048, "block_w": 32}, {"n": 4096, "block_w": 32}]
+    t = autotune.table_from(rows, {8: 0.3, 16: 0.2, 24: 0.25})
+    assert t == {"n_upper": [1024, 4096], "block_w": [16, 32], "batch_g_groups": 16}
+
+
+def test_table_from_alternating():
+    rows = [{"n": 256, "block_w": 32}, {"n": 512, "block_w": 16}, {"n": 1024, "block_w": 32}]
+    t = autotune.table_from(rows, {})
+    assert t == {"n_upper": [256, 512, 1024], "block_w": [32, 16, 32]}
+
+
+def test_tuning_struct_fields_and_limits():
+    t = B.tuning_struct({"n_upper": [2048, 8192], "block_w": [16, 32], "batch_g_groups": 20})
+    assert t.count == 2 and list(t.n_upper)[:2] == [2048, 8192]
+    assert list(t.block_w)[:2] == [16, 32] and t.batch_g_groups == 20
+    with pytest.raises(ValueError):
+        B.tuning_struct({"n_upper": [1], "block_w": []})
+    with pytest.raises(ValueError):
+        B.tuning_struct({"n_upper": list(range(9)), "block_w": [16] * 9})
+
+
+def test_set_tuning_rejects_null_handle():
+    # argument checks happen before any device work
+    assert B.lib().jsvd_set_tuning(None, None) == -1
