@@ -64,6 +64,8 @@ typedef struct {
     int32_t max_sweeps;       /* limit on block sweeps (default 30) */
     int32_t want_v;           /* 1 = accumulate V (default), 0 = do not touch V */
     int32_t sort;             /* 1 = order the output (default), 0 = column order as computed */
+    int32_t qr;               /* QR preprocessing of a tall G, eq. (2.1), jsvd_gesvd only:
+                                 0 = choose (when m >= 2n, default), 1 = never, 2 = always */
 } jsvd_opts;
 
 typedef struct {
@@ -79,6 +81,7 @@ typedef struct {
     int32_t block_w;           /* w actually used */
     int32_t n_blocks;          /* block-columns in the pivot strategy (with padding) */
     double seconds;            /* wall time of the call */
+    int32_t preprocessed;      /* 1 if the Jacobi method ran on R^T of a QR of G (eq. (2.1)) */
 } jsvd_info;
 
 /*
@@ -132,6 +135,14 @@ int jsvd_destroy(jsvd_handle_t h);
  *            opts->want_v == 0.  Out: right singular vectors.
  *   opts   : host, may be NULL for defaults.
  *   info   : host, may be NULL.  Statistics of the run.
+ * With QR preprocessing (opts->qr; by default when m >= 2n) the columns of
+ * G are presorted by non-increasing norm, G P = Q [R; 0] by blocked
+ * Householder reflections (eq. (2.1); column presorting in place of column
+ * pivoting), the Jacobi method runs on R^T (n x n) giving R^T V_x = U_x Sigma,
+ * and U = Q [V_x; 0], V = P U_x.  If R is numerically singular (some
+ * |r_ii| <= n 2^-53 max |r_jj|) the call solves G directly instead, so that
+ * V stays orthogonal and zero singular values stay exact.
+ * The QR path needs m <= 32768.
  * Returns JSVD_OK, a negative argument index, JSVD_NOT_CONVERGED,
  * JSVD_NONFINITE, JSVD_HIP_ERROR or JSVD_NO_MEMORY.
  */

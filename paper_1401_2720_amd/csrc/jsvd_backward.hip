@@ -23,7 +23,9 @@ __device__ __forceinline__ d4b mfma16b(double a, double b, d4b c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// C = op(A) op(B) [+ E diag(d)] for a batch of column-major matrices.
+// C = alpha op(A) op(B) + beta C [+ E diag(d)] for a batch of column-major
+// matrices, or (split-K) one product whose K range is cut into slices, slice
+// b summed into the b-th C of the batch.
 // op(A) is M x K, op(B) is K x N.  Workgroup tile 64 x 64 (four waves of
 // 32 x 32, each 2 x 2 MFMA tiles of 16 x 16), K step 16 staged in LDS.
 // MFMA lane layout: lane l supplies A[l%16][l/16] and B[l/16][l%16]; the
@@ -33,9 +35,12 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
     __shared__ double Bs[16][64 + 1];  // Bs[k][j] = op(B)[k0 + k][j0 + j]
     const int b = blockIdx.z;
     const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
-    const double *A = g.A + (size_t)b * g.sa;
-    const double *B = g.B + (size_t)b * g.sb;
+    const double *A = g.A + (g.ksplit ? 0 : (size_t)b * g.sa);
+    const double *B = g.B + (g.ksplit ? 0 : (size_t)b * g.sb);
     double *C = g.C + (size_t)b * g.sc;
+    // K range of this product (split-K: one slice per batch index)
+    const int kbeg = g.ksplit ? (int)min((int64_t)g.K, (int64_t)b * g.ksplit) : 0;
+    const int kend = g.ksplit ? (int)min((int64_t)g.K, (int64_t)(b + 1) * g.ksplit) : g.K;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wi = (wave & 1) * 32, wj = (wave >> 1) * 32;
     const int l16 = lane & 15, lg = lane >> 4;
@@ -43,7 +48,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
     for (int x = 0; x < 2; ++x)
         for (int y = 0; y < 2; ++y) acc[x][y] = d4b{0.0, 0.0, 0.0, 0.0};
 
-    for (int k0 = 0; k0 < g.K; k0 += 16) {
+    for (int k0 = kbeg; k0 < kend; k0 += 16) {
         // stage op(A)[i0 .. i0+63][k0 .. k0+15] and op(B)[k0 .. k0+15][j0 .. j0+63]
         for (int e = tid; e < 64 * 16; e += 256) {
             int i, k;
@@ -56,7 +61,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
             }
             const int gi = i0 + i, gk = k0 + k;
             double v = 0.0;
-            if (gi < g.M && gk < g.K) v = g.ta ? A[gk + (size_t)gi * g.lda] : A[gi + (size_t)gk * g.lda];
+            if (gi < g.M && gk < kend) v = g.ta ? A[gk + (size_t)gi * g.lda] : A[gi + (size_t)gk * g.lda];
             As[k][i] = v;
         }
         for (int e = tid; e < 16 * 64; e += 256) {
@@ -70,7 +75,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
             }
             const int gk = k0 + k, gj = j0 + j;
             double v = 0.0;
-            if (gk < g.K && gj < g.N) v = g.tb ? B[gj + (size_t)gk * g.ldb] : B[gk + (size_t)gj * g.ldb];
+            if (gk < kend && gj < g.N) v = g.tb ? B[gj + (size_t)gk * g.ldb] : B[gk + (size_t)gj * g.ldb];
             Bs[k][j] = v;
         }
         __syncthreads();
@@ -97,7 +102,8 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
                 const int gi = i0 + wi + 16 * x + lg + 4 * v;
                 const int gj = j0 + wj + 16 * y + l16;
                 if (gi < g.M && gj < g.N) {
-                    double r = acc[x][y][v];
+                    double r = g.alpha == 1.0 ? acc[x][y][v] : g.alpha * acc[x][y][v];
+                    if (g.beta != 0.0) r = fma(g.beta, C[gi + (size_t)gj * g.ldc], r);
                     if (g.E) r += g.E[(size_t)b * g.se + gi + (size_t)gj * g.lde] * g.d[(size_t)b * g.sd + gj];
                     C[gi + (size_t)gj * g.ldc] = r;
                 }

@@ -5,6 +5,7 @@
 // reached.  Everything else runs in the kernels of jsvd_gram.hip, jsvd_inner.hip,
 // jsvd_update.hip and jsvd_aux.hip.
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -37,6 +38,8 @@ struct jsvd_handle_s {
     int cu_count = 0;
     int batch_lds = 0;              // dynamic LDS bytes of the batched kernel
     jsvd_tuning tuning{};           // measured choices (count == 0: none)
+    void *qr_ws = nullptr;          // QR preprocessing workspace (kept apart from ws,
+    size_t qr_ws_bytes = 0;         // which the Jacobi solve of R^T may reallocate)
     // per-kernel timing (measurement aid): 4 events per p-step
     bool timing = false;
     std::vector<hipEvent_t> events;
@@ -119,6 +122,7 @@ jsvd_opts defaults() {
     o.max_sweeps = 30;
     o.want_v = 1;
     o.sort = 1;
+    o.qr = 0;
     return o;
 }
 
@@ -228,7 +232,7 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
 
     if (want_v) HIP_TRY(launch_init_identity(V, ldv, n, st));
 
-    jsvd_info inf;
+    jsvd_info inf{};
     std::memset(&inf, 0, sizeof inf);
     inf.block_w = w;
     inf.n_blocks = order;
@@ -320,6 +324,171 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     return status;
 }
 
+
+// ------------------------------------------------------------ QR path
+// G P = Q [R; 0] (eq. (2.1), column presorting by norm in place of column
+// pivoting), the Jacobi method on X = R^T, then U = Q [V_x; 0], V = P U_x.
+int gemm_splitk(const double *A, int64_t lda, const double *B, int64_t ldb, int M, int N,
+                int64_t K, double *parts, double *out, hipStream_t st) {
+    // out (M x N, ld M) = A^T B with A K x M and B K x N, K cut into slices
+    const int np = (int)std::max<int64_t>(1, std::min<int64_t>(32, K / 512));
+    const int64_t ks = align_up((size_t)((K + np - 1) / np), 16);
+    const int used = (int)((K + ks - 1) / ks);
+    GemmArgs g;
+    g.batch = used;
+    g.M = M; g.N = N; g.K = (int)K; g.ta = true; g.tb = false;
+    g.A = A; g.lda = lda; g.sa = 0;
+    g.B = B; g.ldb = ldb; g.sb = 0;
+    g.C = parts; g.ldc = M; g.sc = (int64_t)M * N;
+    g.E = nullptr; g.d = nullptr; g.lde = g.se = g.sd = 0;
+    g.ksplit = ks;
+    HIP_TRY(launch_gemm(g, st));
+    HIP_TRY(launch_sum_parts(parts, used, (int64_t)M * N, out, st));
+    return JSVD_OK;
+}
+
+int gemm_plain(bool ta, const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
+               int64_t ldc, int M, int N, int K, double alpha, double beta, hipStream_t st) {
+    GemmArgs g;
+    g.batch = 1;
+    g.M = M; g.N = N; g.K = K; g.ta = ta; g.tb = false;
+    g.A = A; g.lda = lda; g.sa = 0;
+    g.B = B; g.ldb = ldb; g.sb = 0;
+    g.C = C; g.ldc = ldc; g.sc = 0;
+    g.E = nullptr; g.d = nullptr; g.lde = g.se = g.sd = 0;
+    g.alpha = alpha;
+    g.beta = beta;
+    HIP_TRY(launch_gemm(g, st));
+    return JSVD_OK;
+}
+
+int gesvd_qr(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double *S,
+             double *V, int64_t ldv, const jsvd_opts &o, jsvd_info *info) {
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = h->stream;
+    constexpr int NB = kQrPanel;
+    const int64_t npan = (n + NB - 1) / NB;
+    // workspace
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off += align_up(bytes, 256); return at; };
+    const size_t oW = take((size_t)m * n * 8), oX = take((size_t)n * n * 8),
+                 oVx = take((size_t)n * n * 8), oVp = take((size_t)m * NB * 8),
+                 oT = take((size_t)npan * NB * NB * 8), oTau = take((size_t)n * 8),
+                 oParts = take((size_t)32 * NB * n * 8), oY1 = take((size_t)NB * n * 8),
+                 oY2 = take((size_t)NB * n * 8), oPart = take((size_t)2 * 64 * NB * 8),
+                 oProw = take((size_t)2 * NB * 8), oNrm = take((size_t)n * 8),
+                 oPerm = take((size_t)n * 4), oBar = take(64);
+    if (off > h->qr_ws_bytes) {
+        if (h->qr_ws) (void)hipFree(h->qr_ws);
+        h->qr_ws = nullptr;
+        h->qr_ws_bytes = 0;
+        if (hipMalloc(&h->qr_ws, off) != hipSuccess) {
+            h->qr_ws = nullptr;
+            return JSVD_NO_MEMORY;
+        }
+        h->qr_ws_bytes = off;
+    }
+    char *ws = static_cast<char *>(h->qr_ws);
+    double *W = reinterpret_cast<double *>(ws + oW), *X = reinterpret_cast<double *>(ws + oX),
+           *Vx = reinterpret_cast<double *>(ws + oVx), *Vp = reinterpret_cast<double *>(ws + oVp),
+           *T = reinterpret_cast<double *>(ws + oT), *tau = reinterpret_cast<double *>(ws + oTau),
+           *parts = reinterpret_cast<double *>(ws + oParts), *Y1 = reinterpret_cast<double *>(ws + oY1),
+           *Y2 = reinterpret_cast<double *>(ws + oY2), *part = reinterpret_cast<double *>(ws + oPart),
+           *prow = reinterpret_cast<double *>(ws + oProw), *nrm = reinterpret_cast<double *>(ws + oNrm);
+    int *perm = reinterpret_cast<int *>(ws + oPerm);
+    unsigned *bar = reinterpret_cast<unsigned *>(ws + oBar);
+    int *abort_flag = reinterpret_cast<int *>(ws + oBar + 8);
+
+    // presort: W = G P, columns by non-increasing norm (ties by index)
+    HIP_TRY(launch_colnorms(A, lda, m, n, nrm, st));
+    HIP_TRY(launch_rank(nrm, n, n, perm, st));
+    HIP_TRY(launch_gather_cols(A, lda, W, m, m, n, perm, nullptr, nullptr, st));
+    HIP_TRY(launch_qr_reset(bar, abort_flag, st));
+
+    // Householder QR, panel by panel
+    for (int64_t p = 0; p < npan; ++p) {
+        const int64_t j = p * NB;
+        const int nb = (int)std::min<int64_t>(NB, n - j);
+        const int64_t rows = m - j;
+        QrPanelArgs qa;
+        qa.W = W; qa.ldw = m; qa.m = m; qa.n = n; qa.j = j; qa.nb = nb;
+        qa.tau = tau; qa.Vp = Vp; qa.ldvp = m; qa.partials = part; qa.prow = prow;
+        qa.bar = bar; qa.abort_flag = abort_flag; qa.nwg = qr_panel_groups(rows);
+        HIP_TRY(launch_qr_panel(qa, st));
+        // T of the panel from V^T V
+        int rc = gemm_splitk(Vp, m, Vp, m, NB, NB, rows, parts, Y1, st);
+        if (rc) return rc;
+        HIP_TRY(launch_qr_t(Y1, tau + j, nb, T + p * NB * NB, st));
+        if (j + nb < n) {
+            // trailing columns: C <- C - V T^T (V^T C)
+            const int nc = (int)(n - j - nb);
+            double *C = W + j + (j + nb) * m;
+            if ((rc = gemm_splitk(Vp, m, C, m, NB, nc, rows, parts, Y1, st))) return rc;
+            if ((rc = gemm_plain(true, T + p * NB * NB, NB, Y1, NB, Y2, NB, NB, nc, NB, 1.0, 0.0,
+                                 st)))
+                return rc;
+            if ((rc = gemm_plain(false, Vp, m, Y2, NB, C, m, (int)rows, nc, NB, -1.0, 1.0, st)))
+                return rc;
+        }
+    }
+    int hab = 0;
+    HIP_TRY(hipMemcpyAsync(&hab, abort_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (hab) return JSVD_HIP_ERROR;
+
+    // R numerically singular (dependent columns): solve G directly, so that V
+    // stays orthogonal and zero singular values stay exact
+    {
+        std::vector<double> diag((size_t)n);
+        HIP_TRY(hipMemcpy2DAsync(diag.data(), sizeof(double), W, (size_t)(m + 1) * sizeof(double),
+                                 sizeof(double), (size_t)n, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        double dmax = 0.0, dmin = INFINITY;
+        for (double d : diag) {
+            dmax = std::max(dmax, std::fabs(d));
+            dmin = std::min(dmin, std::fabs(d));
+        }
+        if (!(dmin > (double)n * 0x1p-53 * dmax)) {
+            jsvd_opts od = o;
+            od.qr = 1;
+            return solve(h, m, n, A, lda, S, V, ldv, n, od, info, false, nullptr);
+        }
+    }
+
+    // Jacobi on X = R^T: X V_x = U_x Sigma
+    HIP_TRY(launch_r_transpose(W, m, n, X, n, st));
+    jsvd_opts oj = o;
+    oj.want_v = 1;
+    oj.qr = 1;
+    jsvd_info inf{};
+    int status = solve(h, n, n, X, n, S, Vx, n, n, oj, &inf, false, nullptr);
+    if (status != JSVD_OK && status != JSVD_NOT_CONVERGED) return status;
+
+    // U = Q [V_x; 0]: the reflectors applied to [V_x; 0] in reverse panel order
+    HIP_TRY(launch_embed(Vx, n, n, A, lda, m, n, st));
+    for (int64_t p = npan - 1; p >= 0; --p) {
+        const int64_t j = p * NB;
+        const int nb = (int)std::min<int64_t>(NB, n - j);
+        const int64_t rows = m - j;
+        HIP_TRY(launch_qr_extract_v(W, m, m, j, nb, Vp, m, st));
+        double *B = A + j;
+        int rc = gemm_splitk(Vp, m, B, lda, NB, (int)n, rows, parts, Y1, st);
+        if (rc) return rc;
+        if ((rc = gemm_plain(false, T + p * NB * NB, NB, Y1, NB, Y2, NB, NB, (int)n, NB, 1.0, 0.0,
+                             st)))
+            return rc;
+        if ((rc = gemm_plain(false, Vp, m, Y2, NB, B, lda, (int)rows, (int)n, NB, -1.0, 1.0, st)))
+            return rc;
+    }
+    // V = P U_x: row i of U_x is row perm[i] of V
+    if (o.want_v) HIP_TRY(launch_scatter_rows(X, n, V, ldv, n, n, perm, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    inf.preprocessed = 1;
+    inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return status;
+}
+
 int check_common(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
                  const jsvd_opts &o) {
     if (!h) return -1;
@@ -330,6 +499,7 @@ int check_common(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
     if (o.block_w != 0 && o.block_w != 16 && o.block_w != 32) return -9;
     if (o.strategy < JSVD_STRAT_RREV || o.strategy > JSVD_STRAT_C) return -9;
     if (o.max_sweeps < 1 || o.max_inner_sweeps < 0) return -9;
+    if (o.qr < 0 || o.qr > 2) return -9;
     if (m > (int64_t)1 << 31 || n > (int64_t)1 << 20) return -2;
     return JSVD_OK;
 }
@@ -390,6 +560,7 @@ int jsvd_destroy(jsvd_handle_t h) {
     if (h->batch_tables) (void)hipFree(h->batch_tables);
     if (h->batch_meta) (void)hipFree(h->batch_meta);
     if (h->host_counters) (void)hipHostFree(h->host_counters);
+    if (h->qr_ws) (void)hipFree(h->qr_ws);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     delete h;
     return JSVD_OK;
@@ -404,6 +575,8 @@ int jsvd_gesvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda, do
     if (o.want_v && !V) return -7;
     if (o.want_v && ldv < n) return -8;
     if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
+    const bool qr = (o.qr == 2 || (o.qr == 0 && m >= 2 * n)) && m <= 32768 && n >= 1;
+    if (qr) return gesvd_qr(h, m, n, A, lda, S, V, ldv, o, info);
     return solve(h, m, n, A, lda, S, V, ldv, n, o, info, false, nullptr);
 }
 

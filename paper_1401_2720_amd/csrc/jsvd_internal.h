@@ -99,12 +99,46 @@ struct GemmArgs {
     int64_t ldc, sc;
     const double *E, *d;         // optional: C += E diag(d)
     int64_t lde, se, sd;
+    double alpha = 1.0, beta = 0.0;  // C = alpha op(A) op(B) + beta C (+ E diag(d))
+    int64_t ksplit = 0;          // > 0: batch b sums K indices [b ksplit, min(K, (b+1) ksplit))
+                                 // of one product (A, B not strided; C strided by sc)
 };
 
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
 hipError_t launch_adjoint_middle(int64_t batch, int n, const double *s, int64_t ss,
                                  const double *ds, const double *J, const double *K, double *Mp,
                                  double *inv_s, int *degenerate, hipStream_t st);
+
+// ------------------------------------------------------------ QR (eq. (2.1))
+constexpr int kQrPanel = 32;  // Householder panel width
+
+struct QrPanelArgs {
+    double *W;            // m x n, column-major (ld ldw), factored in place
+    int64_t ldw, m, n;
+    int64_t j;            // first column (and pivot row) of the panel
+    int nb;               // columns in the panel, <= kQrPanel
+    double *tau;          // n: reflector scalars
+    double *Vp;           // out: explicit V of the panel, (m - j) x kQrPanel, ld ldvp
+    int64_t ldvp;
+    double *partials;     // 2 x nwg x kQrPanel
+    double *prow;         // 2 x kQrPanel
+    unsigned *bar;        // grid barrier counter
+    int *abort_flag;      // set when a barrier does not complete
+    int nwg;              // workgroups (all co-resident: cooperative launch)
+};
+
+int qr_panel_groups(int64_t rows);
+hipError_t launch_qr_reset(unsigned *bar, int *abort_flag, hipStream_t s);
+hipError_t launch_qr_panel(const QrPanelArgs &a, hipStream_t s);
+hipError_t launch_qr_t(const double *Y, const double *tau, int nb, double *T, hipStream_t s);
+hipError_t launch_sum_parts(const double *parts, int np, int64_t count, double *out,
+                            hipStream_t s);
+hipError_t launch_r_transpose(const double *W, int64_t ldw, int64_t n, double *X, int64_t ldx,
+                              hipStream_t s);
+hipError_t launch_qr_extract_v(const double *W, int64_t ldw, int64_t m, int64_t j, int nb,
+                               double *Vp, int64_t ldvp, hipStream_t s);
+hipError_t launch_embed(const double *X, int64_t ldx, int64_t n, double *B, int64_t ldb,
+                        int64_t rows, int64_t cols, hipStream_t s);
 
 hipError_t launch_reset_counters(unsigned long long *c, hipStream_t s);
 hipError_t launch_init_identity(double *V, int64_t ldv, int64_t n, hipStream_t s);

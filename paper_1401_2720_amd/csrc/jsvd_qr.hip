@@ -1,0 +1,319 @@
+// QR preprocessing of a tall G (Section 2, eq. (2.1)): G P = Q [R; 0] by
+// Householder reflections in panels of 32 columns (compact WY form, Q =
+// H_1 ... H_n, H_k = I - tau_k v_k v_k^T with v_k(k) = 1), the columns P
+// presorted by non-increasing norm.  The Jacobi method then runs on the
+// n x n factor.
+//
+//   qr_panel_kernel   one panel, cooperative grid: every workgroup holds a
+//                     slice of the panel's rows in registers; each column
+//                     is one grid-wide reduction (the norm below the
+//                     diagonal and the dot products with the panel's
+//                     remaining columns), summed in workgroup order, then
+//                     every workgroup applies the reflection to its rows;
+//   qr_t_kernel       the panel's triangular T (Q_panel = I - V T V^T) from
+//                     V^T V and tau, by the column recurrence of the
+//                     compact WY form;
+//   the trailing update C <- C - V T^T (V^T C) and the application of Q run
+//   on the FP64 MFMA GEMM (split-K for the tall V^T C products).
+//
+// All arithmetic is FP64, reductions have a fixed order, so results are
+// bitwise reproducible run to run.
+#include "jsvd_device.h"
+
+namespace jsvd {
+
+namespace {
+
+constexpr int kNb = kQrPanel;      // panel width
+constexpr int kQT = 256;           // threads per workgroup of the panel kernel
+constexpr int kRpt = 2;            // panel rows per thread, at most
+
+// Grid-wide barrier for a cooperative launch: monotonic arrival counter,
+// bounded spin (a barrier that does not complete within the bound sets the
+// abort flag and lets every workgroup leave).
+__device__ __forceinline__ bool grid_sync(unsigned *bar, unsigned target, int *abort_flag) {
+    __threadfence();
+    __syncthreads();
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
+        unsigned spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > (1u << 24)) {
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+        }
+        s_ok = ok;
+    }
+    __syncthreads();
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    return s_ok != 0;
+}
+
+// Sums of the kNb values v[] over the workgroup's 256 threads, in a fixed
+// order: red[c][t] <- v[c] of thread t; 8 segments of 32 threads summed
+// sequentially, then the 8 segment sums.  Result in out[c] for c < nv.
+__device__ __forceinline__ void wg_sum(const double (&v)[kNb], int nv, double (*red)[kQT + 1], double (*seg)[8],
+                       double *out) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < kNb; ++c)
+        if (c < nv) red[c][t] = v[c];
+    __syncthreads();
+    {
+        const int c = t >> 3, sg = t & 7;
+        if (c < nv) {
+            double s = 0.0;
+            for (int i = 0; i < 32; ++i) s += red[c][sg * 32 + i];
+            seg[c][sg] = s;
+        }
+    }
+    __syncthreads();
+    if (t < nv) {
+        double s = 0.0;
+        for (int i = 0; i < 8; ++i) s += seg[t][i];
+        out[t] = s;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kQT, 1) void qr_panel_kernel(QrPanelArgs a) {
+    __shared__ double red[kNb][kQT + 1];
+    __shared__ double seg[kNb][8];
+    __shared__ double wsum[kNb];
+    __shared__ double gsum[kNb];
+    __shared__ double s_prow[kNb];
+    const int wg = blockIdx.x, t = threadIdx.x;
+    const int64_t rows = a.m - a.j;                       // panel rows j .. m-1
+    const int64_t chunk = (rows + a.nwg - 1) / a.nwg;     // rows per workgroup
+    const int64_t r_beg = a.j + wg * chunk;
+    const int64_t r_end = min(a.m, r_beg + chunk);
+    const int nb = a.nb;
+    double *W = a.W;
+    const int64_t ldw = a.ldw;
+
+    double x[kRpt][kNb];
+    int64_t rr[kRpt];
+#pragma unroll
+    for (int q = 0; q < kRpt; ++q) {
+        rr[q] = r_beg + t + (int64_t)q * kQT;
+        const bool in = rr[q] < r_end;
+#pragma unroll
+        for (int c = 0; c < kNb; ++c) x[q][c] = (in && c < nb) ? W[rr[q] + (a.j + c) * ldw] : 0.0;
+    }
+
+    // Column k of the panel is picked out of the register arrays by
+    // selection over the (unrolled) column index, so that the arrays stay in
+    // registers while k runs over the panel.
+    for (int k = 0; k < nb; ++k) {
+        const int64_t pr = a.j + k;  // pivot row
+        const int par = k & 1;
+        double xk[kRpt];
+#pragma unroll
+        for (int q = 0; q < kRpt; ++q) {
+            xk[q] = 0.0;
+#pragma unroll
+            for (int c = 0; c < kNb; ++c) xk[q] = (c == k) ? x[q][c] : xk[q];
+        }
+        // partial sums over own rows below the pivot: column k with columns k .. nb-1
+        double ps[kNb];
+#pragma unroll
+        for (int c = 0; c < kNb; ++c) ps[c] = 0.0;
+#pragma unroll
+        for (int q = 0; q < kRpt; ++q) {
+            if (rr[q] > pr && rr[q] < r_end) {
+#pragma unroll
+                for (int c = 0; c < kNb; ++c)
+                    if (c >= k) ps[c] = fma(xk[q], x[q][c], ps[c]);
+            }
+            if (rr[q] == pr && rr[q] < r_end) {
+#pragma unroll
+                for (int c = 0; c < kNb; ++c)
+                    if (c >= k) a.prow[par * kNb + c] = x[q][c];
+            }
+        }
+        wg_sum(ps, nb, red, seg, wsum);
+        if (t < nb) a.partials[((size_t)par * a.nwg + wg) * kNb + t] = wsum[t];
+        if (!grid_sync(a.bar, (unsigned)(a.nwg * (k + 1)), a.abort_flag)) return;
+        // all workgroups: totals in workgroup order, the pivot row, the reflector
+        if (t < nb) {
+            double sum = 0.0;
+            for (int w = 0; w < a.nwg; ++w) sum += a.partials[((size_t)par * a.nwg + w) * kNb + t];
+            gsum[t] = sum;
+            s_prow[t] = a.prow[par * kNb + t];
+        }
+        __syncthreads();
+        const double alpha = s_prow[k];
+        const double xn2 = gsum[k];  // squared norm below the pivot
+        double tau = 0.0, beta = alpha, scal = 0.0;
+        if (xn2 > 0.0) {
+            beta = -copysign(sqrt(fma(alpha, alpha, xn2)), alpha);
+            tau = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+        }
+        if (wg == 0 && t == 0) a.tau[a.j + k] = tau;
+        // rows: v = e_pivot + scal * x(below); a_c -= tau v (v^T a_c), c > k
+#pragma unroll
+        for (int q = 0; q < kRpt; ++q) {
+            if (rr[q] >= pr && rr[q] < r_end) {
+                const bool piv = rr[q] == pr;
+                const double v = piv ? 1.0 : xk[q] * scal;
+#pragma unroll
+                for (int c = 0; c < kNb; ++c) {
+                    if (c > k && c < nb && tau != 0.0) {
+                        const double wc = fma(scal, gsum[c], s_prow[c]);  // v^T a_c
+                        x[q][c] = fma(-tau * v, wc, x[q][c]);
+                    }
+                    if (c == k) x[q][c] = piv ? beta : v;
+                }
+            }
+        }
+        __syncthreads();  // gsum / s_prow are rewritten by the next column
+    }
+    // write back: R above and on the diagonal, v below; explicit V of the panel
+#pragma unroll
+    for (int q = 0; q < kRpt; ++q) {
+        if (rr[q] >= r_end) continue;
+        const int64_t li = rr[q] - a.j;  // row within the panel
+#pragma unroll
+        for (int c = 0; c < kNb; ++c) {
+            if (c < nb) W[rr[q] + (a.j + c) * ldw] = x[q][c];
+            a.Vp[li + (int64_t)c * a.ldvp] = (c >= nb) ? 0.0 : (li > c ? x[q][c] : (li == c ? 1.0 : 0.0));
+        }
+    }
+}
+
+// T (nb x nb, upper triangular, column-major, ld kNb) with I - V T V^T =
+// H_1 ... H_nb from Y = V^T V (ld kNb) and tau: T(c, c) = tau_c,
+// T(0:c, c) = -tau_c T(0:c, 0:c) Y(0:c, c).
+__global__ void qr_t_kernel(const double *Y, const double *tau, int nb, double *T) {
+    __shared__ double Ts[kNb][kNb + 1];
+    __shared__ double z[kNb];
+    const int t = threadIdx.x;
+    for (int e = t; e < kNb * kNb; e += blockDim.x) Ts[e % kNb][e / kNb] = 0.0;
+    __syncthreads();
+    for (int c = 0; c < nb; ++c) {
+        const double tc = tau[c];
+        if (t < c) z[t] = Y[t + c * kNb];
+        __syncthreads();
+        if (t < c) {
+            double s = 0.0;
+            for (int i = t; i < c; ++i) s = fma(Ts[t][i], z[i], s);
+            Ts[t][c] = -tc * s;
+        }
+        if (t == 0) Ts[c][c] = tc;
+        __syncthreads();
+    }
+    for (int e = t; e < kNb * kNb; e += blockDim.x) T[e] = Ts[e % kNb][e / kNb];
+}
+
+// out = sum of parts[0 .. np) (each count doubles, stride count), in order.
+__global__ void sum_parts_kernel(const double *parts, int np, int64_t count, double *out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double s = 0.0;
+    for (int p = 0; p < np; ++p) s += parts[(size_t)p * count + e];
+    out[e] = s;
+}
+
+// X (n x n, ld ldx) = R^T, R the upper triangle of W's first n rows.
+__global__ void r_transpose_kernel(const double *W, int64_t ldw, int64_t n, double *X,
+                                   int64_t ldx) {
+    const int64_t c = blockIdx.y;  // column of X = row of R
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        X[i + c * ldx] = (i >= c) ? W[c + i * ldw] : 0.0;
+}
+
+// Explicit V of the panel at column j (rows j .. m-1 of W; unit diagonal).
+__global__ void qr_extract_v_kernel(const double *W, int64_t ldw, int64_t m, int64_t j, int nb,
+                                    double *Vp, int64_t ldvp) {
+    const int c = blockIdx.y;
+    for (int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; li < m - j;
+         li += (int64_t)gridDim.x * blockDim.x)
+        Vp[li + c * ldvp] = (c >= nb) ? 0.0 : (li > c ? W[j + li + (j + c) * ldw] : (li == c ? 1.0 : 0.0));
+}
+
+// B (rows x cols, ld ldb): rows < n copied from X (ld ldx), the others zero.
+__global__ void embed_kernel(const double *X, int64_t ldx, int64_t n, double *B, int64_t ldb,
+                             int64_t rows) {
+    const int64_t c = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * blockDim.x)
+        B[i + c * ldb] = i < n ? X[i + c * ldx] : 0.0;
+}
+
+__global__ void qr_reset_kernel(unsigned *bar, int *abort_flag) {
+    if (threadIdx.x == 0) {
+        if (bar) *bar = 0u;
+        if (abort_flag) *abort_flag = 0;
+    }
+}
+
+}  // namespace
+
+int qr_panel_groups(int64_t rows) {
+    const int64_t per = (int64_t)kQT * kRpt;
+    return (int)((rows + per - 1) / per);
+}
+
+hipError_t launch_qr_reset(unsigned *bar, int *abort_flag, hipStream_t s) {
+    hipLaunchKernelGGL(qr_reset_kernel, dim3(1), dim3(64), 0, s, bar, abort_flag);
+    return hipGetLastError();
+}
+
+// The abort flag is left as it is: once a barrier has failed, the later
+// panels fall through at their first barrier and the caller reports it.
+hipError_t launch_qr_panel(const QrPanelArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(qr_reset_kernel, dim3(1), dim3(64), 0, s, a.bar, (int *)nullptr);
+    QrPanelArgs arg = a;
+    void *params[] = {&arg};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&qr_panel_kernel),
+                                      dim3((unsigned)a.nwg), dim3(kQT), params, 0, s);
+}
+
+hipError_t launch_qr_t(const double *Y, const double *tau, int nb, double *T, hipStream_t s) {
+    hipLaunchKernelGGL(qr_t_kernel, dim3(1), dim3(64), 0, s, Y, tau, nb, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_parts(const double *parts, int np, int64_t count, double *out,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                       parts, np, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_r_transpose(const double *W, int64_t ldw, int64_t n, double *X, int64_t ldx,
+                              hipStream_t s) {
+    const int64_t bx = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16));
+    hipLaunchKernelGGL(r_transpose_kernel, dim3((unsigned)bx, (unsigned)n), dim3(256), 0, s, W,
+                       ldw, n, X, ldx);
+    return hipGetLastError();
+}
+
+hipError_t launch_qr_extract_v(const double *W, int64_t ldw, int64_t m, int64_t j, int nb,
+                               double *Vp, int64_t ldvp, hipStream_t s) {
+    const int64_t bx = std::max<int64_t>(1, std::min<int64_t>((m - j + 255) / 256, 64));
+    hipLaunchKernelGGL(qr_extract_v_kernel, dim3((unsigned)bx, (unsigned)kNb), dim3(256), 0, s,
+                       W, ldw, m, j, nb, Vp, ldvp);
+    return hipGetLastError();
+}
+
+hipError_t launch_embed(const double *X, int64_t ldx, int64_t n, double *B, int64_t ldb,
+                        int64_t rows, int64_t cols, hipStream_t s) {
+    const int64_t bx = std::max<int64_t>(1, std::min<int64_t>((rows + 255) / 256, 64));
+    hipLaunchKernelGGL(embed_kernel, dim3((unsigned)bx, (unsigned)cols), dim3(256), 0, s, X, ldx,
+                       n, B, ldb, rows);
+    return hipGetLastError();
+}
+
+}  // namespace jsvd

@@ -1,0 +1,96 @@
+"""QR preprocessing of tall matrices (eq. (2.1)): G P = Q [R; 0] by blocked
+Householder reflections on the GPU, the Jacobi method on R^T, U = Q [V_x; 0],
+V = P U_x.  Checked against the oracle's SVD (one-sided Jacobi on G itself,
+no QR) with the bars of test_gpu_parity.py, against the direct GPU path, for
+ragged panel counts and sizes, for bitwise determinism, and for the
+fallback to the direct path when R is singular."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1401_2720_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _run(A, **kw):
+    torch = _torch()
+    from paper_1401_2720_amd import _binding as B
+    U, S, V, info = B.gesvd(torch.from_numpy(np.asfortranarray(A)).cuda(), **kw)
+    torch.cuda.synchronize()
+    return U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy(), info
+
+
+def _check(A, U, S, V, ref, strict_rel=None):
+    n = S.shape[0]
+    tol = 1e-12 * ref + 1e-13 * ref[0]
+    err = np.abs(S - ref)
+    assert np.all(err <= tol), f"sigma: worst {np.max(err / np.maximum(tol, 1e-300)):.2f} x tol"
+    if strict_rel is not None:
+        big = ref >= 1e-3 * ref[0]
+        assert np.max(err[big] / ref[big]) <= strict_rel
+    assert np.max(np.abs(U.T @ U - np.eye(n))) <= 1e-13 * n
+    assert np.max(np.abs(V.T @ V - np.eye(n))) <= 1e-13 * n
+    assert np.linalg.norm(A - (U * S) @ V.T) <= 1e-13 * n * np.linalg.norm(A)
+    assert np.all(np.diff(S) <= 0)
+
+
+QR_CASES = [
+    # name, m, n, input kind
+    ("tall300x70_graded", 300, 70, "graded"),      # 3 panels, the last of 6 columns
+    ("tall1000x64_gauss", 1000, 64, "gauss"),      # 2 full panels, 2 panel workgroups
+    ("tall2500x33_gauss", 2500, 33, "gauss"),      # a panel of 1 column, 5 workgroups
+    ("square96_graded", 96, 96, "graded"),         # forced QR on a square matrix
+    ("narrow700x5_gauss", 700, 5, "gauss"),
+]
+
+
+@pytest.mark.parametrize("name,m,n,kind", QR_CASES, ids=[c[0] for c in QR_CASES])
+def test_qr_path_matches_oracle(name, m, n, kind):
+    _say(f"qr case {name}: m={m} n={n}")
+    g = inputs.rng(300 + m + n)
+    A = (inputs.prescribed(m, n, inputs.logspaced(n, -6.0), g) if kind == "graded"
+         else inputs.gaussian(m, n, g))
+    U, S, V, info = _run(A, qr="on")
+    assert info["status"] == 0 and info["preprocessed"] == 1, info
+    ref = oracle.gesvj(A)
+    _check(A, U, S, V, ref["S"], strict_rel=(1e-12 if kind == "gauss" else None))
+    # the direct GPU path agrees
+    U2, S2, V2, info2 = _run(A, qr="off")
+    assert info2["preprocessed"] == 0
+    assert np.max(np.abs(S - S2)) <= 1e-13 * S[0] * n
+    _say(f"  sweeps qr={info['sweeps']} direct={info2['sweeps']}")
+
+
+def test_qr_chosen_for_tall_and_deterministic():
+    _say("qr auto choice and determinism")
+    A = inputs.gaussian(800, 96, inputs.rng(41))
+    r1 = _run(A)
+    r2 = _run(A)
+    assert r1[3]["preprocessed"] == 1
+    for x, y in zip(r1[:3], r2[:3]):
+        assert np.array_equal(x, y)
+    r3 = _run(inputs.gaussian(150, 96, inputs.rng(42)))
+    assert r3[3]["preprocessed"] == 0   # m < 2n: direct
+
+
+def test_qr_singular_falls_back_to_direct():
+    _say("qr singular R -> direct")
+    A = inputs.gaussian(400, 40, inputs.rng(43))
+    A[:, 7] = 0.0
+    U, S, V, info = _run(A, qr="on")
+    assert info["preprocessed"] == 0 and info["status"] == 0
+    assert S[-1] == 0.0
+    assert np.max(np.abs(V.T @ V - np.eye(40))) <= 1e-13 * 40
+    ref = oracle.gesvj(A)
+    assert np.max(np.abs(S - ref["S"])) <= 1e-12 * ref["S"][0]
