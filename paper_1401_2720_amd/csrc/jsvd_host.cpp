@@ -377,7 +377,7 @@ int gesvd_qr(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, dou
                  oParts = take((size_t)32 * NB * n * 8), oY1 = take((size_t)NB * n * 8),
                  oY2 = take((size_t)NB * n * 8), oPart = take((size_t)2 * 64 * NB * 8),
                  oProw = take((size_t)2 * NB * 8), oNrm = take((size_t)n * 8),
-                 oPerm = take((size_t)n * 4), oBar = take(64);
+                 oPerm = take((size_t)n * 4), oBar = take(128);
     if (off > h->qr_ws_bytes) {
         if (h->qr_ws) (void)hipFree(h->qr_ws);
         h->qr_ws = nullptr;
@@ -439,15 +439,12 @@ int gesvd_qr(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, dou
     // R numerically singular (dependent columns): solve G directly, so that V
     // stays orthogonal and zero singular values stay exact
     {
-        std::vector<double> diag((size_t)n);
-        HIP_TRY(hipMemcpy2DAsync(diag.data(), sizeof(double), W, (size_t)(m + 1) * sizeof(double),
-                                 sizeof(double), (size_t)n, hipMemcpyDeviceToHost, st));
+        double range[2] = {0.0, 0.0};
+        double *d_range = reinterpret_cast<double *>(ws + oBar + 64);
+        HIP_TRY(launch_diag_range(W, m, n, d_range, st));
+        HIP_TRY(hipMemcpyAsync(range, d_range, sizeof range, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        double dmax = 0.0, dmin = INFINITY;
-        for (double d : diag) {
-            dmax = std::max(dmax, std::fabs(d));
-            dmin = std::min(dmin, std::fabs(d));
-        }
+        const double dmin = range[0], dmax = range[1];
         if (!(dmin > (double)n * 0x1p-53 * dmax)) {
             jsvd_opts od = o;
             od.qr = 1;

@@ -124,11 +124,12 @@ struct QrPanelArgs {
     double *prow;         // 2 x kQrPanel
     unsigned *bar;        // grid barrier counter
     int *abort_flag;      // set when a barrier does not complete
-    int nwg;              // workgroups (all co-resident: cooperative launch)
+    int nwg;              // workgroups, <= 64 (all resident at once)
 };
 
 int qr_panel_groups(int64_t rows);
 hipError_t launch_qr_reset(unsigned *bar, int *abort_flag, hipStream_t s);
+hipError_t launch_diag_range(const double *W, int64_t ldw, int64_t n, double *out, hipStream_t s);
 hipError_t launch_qr_panel(const QrPanelArgs &a, hipStream_t s);
 hipError_t launch_qr_t(const double *Y, const double *tau, int nb, double *T, hipStream_t s);
 hipError_t launch_sum_parts(const double *parts, int np, int64_t count, double *out,

@@ -4,7 +4,7 @@
 // presorted by non-increasing norm.  The Jacobi method then runs on the
 // n x n factor.
 //
-//   qr_panel_kernel   one panel, cooperative grid: every workgroup holds a
+//   qr_panel_kernel   one panel, all workgroups resident: every workgroup holds a
 //                     slice of the panel's rows in registers; each column
 //                     is one grid-wide reduction (the norm below the
 //                     diagonal and the dot products with the panel's
@@ -28,7 +28,7 @@ constexpr int kNb = kQrPanel;      // panel width
 constexpr int kQT = 256;           // threads per workgroup of the panel kernel
 constexpr int kRpt = 2;            // panel rows per thread, at most
 
-// Grid-wide barrier for a cooperative launch: monotonic arrival counter,
+// Grid-wide barrier among resident workgroups: monotonic arrival counter,
 // bounded spin (a barrier that does not complete within the bound sets the
 // abort flag and lets every workgroup leave).
 __device__ __forceinline__ bool grid_sync(unsigned *bar, unsigned target, int *abort_flag) {
@@ -251,6 +251,29 @@ __global__ void embed_kernel(const double *X, int64_t ldx, int64_t n, double *B,
         B[i + c * ldb] = i < n ? X[i + c * ldx] : 0.0;
 }
 
+// out[0] = min |W(i, i)|, out[1] = max |W(i, i)| over i < n (one workgroup;
+// a NaN diagonal gives out[0] = NaN).
+__global__ void diag_range_kernel(const double *W, int64_t ldw, int64_t n, double *out) {
+    __shared__ double lo[256], hi[256];
+    double a = INFINITY, b = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double d = fabs(W[i + i * ldw]);
+        a = (d != d || a != a) ? NAN : fmin(a, d);
+        b = fmax(b, d);
+    }
+    lo[threadIdx.x] = a;
+    hi[threadIdx.x] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int t = 1; t < 256; ++t) {
+            a = (lo[t] != lo[t] || a != a) ? NAN : fmin(a, lo[t]);
+            b = fmax(b, hi[t]);
+        }
+        out[0] = a;
+        out[1] = b;
+    }
+}
+
 __global__ void qr_reset_kernel(unsigned *bar, int *abort_flag) {
     if (threadIdx.x == 0) {
         if (bar) *bar = 0u;
@@ -265,6 +288,11 @@ int qr_panel_groups(int64_t rows) {
     return (int)((rows + per - 1) / per);
 }
 
+hipError_t launch_diag_range(const double *W, int64_t ldw, int64_t n, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(diag_range_kernel, dim3(1), dim3(256), 0, s, W, ldw, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_qr_reset(unsigned *bar, int *abort_flag, hipStream_t s) {
     hipLaunchKernelGGL(qr_reset_kernel, dim3(1), dim3(64), 0, s, bar, abort_flag);
     return hipGetLastError();
@@ -272,12 +300,13 @@ hipError_t launch_qr_reset(unsigned *bar, int *abort_flag, hipStream_t s) {
 
 // The abort flag is left as it is: once a barrier has failed, the later
 // panels fall through at their first barrier and the caller reports it.
+// An ordinary launch in stream order: nwg <= 64 workgroups of 68 kB LDS,
+// one per CU, are all resident on the 256 CUs (a barrier that waited for
+// one that is not would end at its spin bound and report the failure).
 hipError_t launch_qr_panel(const QrPanelArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(qr_reset_kernel, dim3(1), dim3(64), 0, s, a.bar, (int *)nullptr);
-    QrPanelArgs arg = a;
-    void *params[] = {&arg};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&qr_panel_kernel),
-                                      dim3((unsigned)a.nwg), dim3(kQT), params, 0, s);
+    hipLaunchKernelGGL(qr_panel_kernel, dim3((unsigned)a.nwg), dim3(kQT), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_qr_t(const double *Y, const double *tau, int nb, double *T, hipStream_t s) {
