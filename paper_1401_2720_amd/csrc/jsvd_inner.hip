@@ -113,6 +113,28 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
     if (tid < 2) flags[tid] = 0;
     __syncthreads();
 
+    // ---- nothing to do: when every pair (i, j) of the block pair already
+    // passes the relative orthogonality test on H itself, no rotation can
+    // happen in the inner sweep (no column of R would change, so its dot
+    // products stay those of H up to the rounding of the Cholesky factor),
+    // and the pair is left alone as if the sweep had rotated nothing.
+    {
+        const double tol = kEps * sqrt((double)BW);
+        bool need = false;
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + u * NT, i = e / BW, j = e % BW;
+            if (i < j) {
+                const double hij = R[j * LD + i], hii = R[i * LD + i], hjj = R[j * LD + j];
+                need = need || (hij != 0.0 && !(fabs(hij) <= tol * sqrt(hii) * sqrt(hjj)));
+            }
+        }
+        if (!__syncthreads_or(need ? 1 : 0)) {
+            if (tid == 0) a.pair_rot[pair] = 0;
+            return;
+        }
+    }
+
     // ---- Cholesky H = R^T R (Section 4.1).  A pivot that is not positive
     // (H only semidefinite: dependent columns) makes its row of R zero.
 #pragma unroll
