@@ -242,10 +242,12 @@ int32_t jsvd_strategy_order(int32_t nb);
  * Measurement aid: per-kernel GPU time of the block sweeps, taken with HIP
  * events recorded on the handle's stream around every launch of the three
  * p-step kernels (index 0 = Gram, 1 = inner Cholesky and Jacobi, 2 =
- * update).  jsvd_kernel_timing(h, 1) turns it on and zeroes the totals,
- * (h, 0) turns it off.  jsvd_kernel_times writes the totals since the last
- * reset: ms[3] (host) in milliseconds and launches[3] (host).
- * Both return JSVD_OK or -i for a NULL argument i.
+ * update).  jsvd_kernel_timing(h, k) with k > 0 turns it on for every k-th
+ * p-step of each sweep (k = 1: all; a larger k keeps the events' own cost
+ * out of the run) and zeroes the totals; (h, 0) turns it off.
+ * jsvd_kernel_times writes the totals since the last reset: ms[3] (host) in
+ * milliseconds and launches[3] (host), the number of timed launches.
+ * Both return JSVD_OK, -i for a NULL argument i, or -2 for k < 0.
  */
 int jsvd_kernel_timing(jsvd_handle_t h, int enable);
 int jsvd_kernel_times(jsvd_handle_t h, double *ms, int64_t *launches);

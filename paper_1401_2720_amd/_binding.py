@@ -288,11 +288,12 @@ def diag_fp64(a, b):
     return q, r
 
 
-def kernel_timing(device_index, enable=True):
-    """Turn per-kernel event timing on (and zero it) or off for a device's handle."""
+def kernel_timing(device_index, enable=True, stride=1):
+    """Turn per-kernel event timing on (and zero it) or off for a device's
+    handle; with stride k only every k-th p-step of a sweep is timed."""
     import torch
     h = _handle(device_index, torch.cuda.current_stream(device_index).cuda_stream)
-    rc = lib().jsvd_kernel_timing(h, 1 if enable else 0)
+    rc = lib().jsvd_kernel_timing(h, int(stride) if enable else 0)
     if rc:
         raise JsvdError(rc, "jsvd_kernel_timing")
 

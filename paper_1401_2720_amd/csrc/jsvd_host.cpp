@@ -42,6 +42,7 @@ struct jsvd_handle_s {
     size_t qr_ws_bytes = 0;         // which the Jacobi solve of R^T may reallocate)
     // per-kernel timing (measurement aid): 4 events per p-step
     bool timing = false;
+    int timing_stride = 1;          // time every timing_stride-th p-step
     std::vector<hipEvent_t> events;
     double kernel_ms[3] = {0, 0, 0};
     int64_t launches[3] = {0, 0, 0};
@@ -249,7 +250,9 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
         HIP_TRY(launch_reset_counters(a.counters, st));
         for (int s = 0; s < nsteps; ++s) {
             a.pairs = blk + (size_t)s * npairs;
-            hipEvent_t *ev = h->timing ? &h->events[(size_t)4 * s] : nullptr;
+            // events around the kernels of every timing_stride-th p-step
+            const bool timed = h->timing && s % h->timing_stride == 0;
+            hipEvent_t *ev = timed ? &h->events[(size_t)4 * s] : nullptr;
             if (ev) HIP_TRY(hipEventRecord(ev[0], st));
             HIP_TRY(launch_gram(bw, a, st));
             if (ev) HIP_TRY(hipEventRecord(ev[1], st));
@@ -262,7 +265,7 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
                                hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if (h->timing) {
-            for (int s = 0; s < nsteps; ++s) {
+            for (int s = 0; s < nsteps; s += h->timing_stride) {
                 hipEvent_t *ev = &h->events[(size_t)4 * s];
                 for (int k = 0; k < 3; ++k) {
                     float ms = 0.f;
@@ -809,7 +812,9 @@ int jsvd_svd_backward(jsvd_handle_t h, int64_t batch, int64_t m, int64_t n, cons
 
 int jsvd_kernel_timing(jsvd_handle_t h, int enable) {
     if (!h) return -1;
+    if (enable < 0) return -2;
     h->timing = enable != 0;
+    h->timing_stride = enable > 0 ? enable : 1;
     for (int k = 0; k < 3; ++k) {
         h->kernel_ms[k] = 0.0;
         h->launches[k] = 0;
