@@ -85,6 +85,20 @@ __device__ __forceinline__ double row_sum(double v) {
     return v;
 }
 
+// The same over the 8 lanes of a half row (lane l <-> l^1, l^2, 7-l).
+__device__ __forceinline__ double half_row_sum(double v) {
+    v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);  // row_half_mirror
+    return v;
+}
+
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+    static_assert(L == 8 || L == 16, "lane groups of 8 or 16");
+    return L == 16 ? row_sum(v) : half_row_sum(v);
+}
+
 // Value of v in lane l (wave-uniform l).
 __device__ __forceinline__ double lane_value(double v, int l) {
     const unsigned long long u = __builtin_bit_cast(unsigned long long, v);

@@ -156,8 +156,9 @@ Layout plan(int64_t m, int64_t n, int bw, int npairs, int splits, bool hsvd) {
         return o;
     };
     L.hpart = take((size_t)npairs * splits * bw * bw * sizeof(double));
-    L.vprime = take((size_t)npairs * bw * bw * sizeof(double));
-    L.pair_rot = take((size_t)npairs * sizeof(int));
+    // two slots: a p-step's V'_pq is read by the next p-step's launch
+    L.vprime = take((size_t)2 * npairs * bw * bw * sizeof(double));
+    L.pair_rot = take((size_t)2 * npairs * sizeof(int));
     L.counters = take(C_COUNT * sizeof(unsigned long long));
     L.perm = take((size_t)n * sizeof(int));
     L.s_tmp = take((size_t)n * sizeof(double));
@@ -188,15 +189,22 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     const int nsteps = order - 1;
     const bool want_v = o.want_v != 0;
 
-    // Gram row splits (at most 16) and update row
-    // chunks: aim at a few workgroups per CU.
+    // Gram row splits (at most 16) and update row chunks: aim at a few
+    // workgroups per CU.  The V update of a p-step is done by the next
+    // p-step's inner launch, in about two workgroups per CU that the pivot
+    // pairs leave free (a workgroup there has 16 * 2w threads).
     const int target_wg = 1024;
     int splits = std::min(16, std::max(1, 512 / npairs));
     int64_t rps = align_up((size_t)((m + splits - 1) / splits), 64);
     splits = (int)((m + rps - 1) / rps);
-    const int64_t upd_total_rows = m + (want_v ? n : 0);
     const int per_pair = std::max(1, target_wg / npairs);
-    int64_t upd_rows = align_up((size_t)((upd_total_rows + per_pair - 1) / per_pair), 64);
+    const int64_t upd_rows_g = align_up((size_t)((m + per_pair - 1) / per_pair), 64);
+    const int64_t upd_rows_v = align_up((size_t)((n + per_pair - 1) / per_pair), 64);
+    const int free_cu = std::max(h->cu_count - npairs, std::max(1, h->cu_count / 4));
+    const int v_per_pair = std::max(1, 2 * free_cu / npairs);
+    const int inner_waves = 16 * bw / 64;  // 16-row slices per pass of such a workgroup
+    const int64_t prev_rows =
+        align_up((size_t)((n + v_per_pair - 1) / v_per_pair), (size_t)16 * inner_waves);
 
     Layout L = plan(m, n, bw, npairs, splits, hsvd);
     int rc = ensure_workspace(h, L.total);
@@ -222,14 +230,22 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     a.splits = splits;
     a.rows_per_split = (int)rps;
     a.hpart = reinterpret_cast<double *>(ws + L.hpart);
-    a.vprime = reinterpret_cast<double *>(ws + L.vprime);
-    a.pair_rot = reinterpret_cast<int *>(ws + L.pair_rot);
+    double *const vprime0 = reinterpret_cast<double *>(ws + L.vprime);
+    int *const pair_rot0 = reinterpret_cast<int *>(ws + L.pair_rot);
+    a.vprime = vprime0;
+    a.pair_rot = pair_rot0;
     a.counters = reinterpret_cast<unsigned long long *>(ws + L.counters);
     a.inner_tbl = inner;
     a.max_inner_sweeps = o.max_inner_sweeps > 0 ? o.max_inner_sweeps : choose_inner_sweeps(m, n);
-    a.upd_rows = (int)upd_rows;
-    a.upd_chunks_g = (int)((m + upd_rows - 1) / upd_rows);
-    a.upd_chunks_v = want_v ? (int)((n + upd_rows - 1) / upd_rows) : 0;
+    a.upd_rows = (int)upd_rows_g;
+    a.upd_chunks_g = (int)((m + upd_rows_g - 1) / upd_rows_g);
+    a.upd_chunks_v = 0;
+    a.prev_pairs = nullptr;
+    a.prev_vprime = nullptr;
+    a.prev_pair_rot = nullptr;
+    a.prev_chunks = 0;
+    a.prev_rows = (int)prev_rows;
+    const int v_chunks = want_v ? (int)((n + prev_rows - 1) / prev_rows) : 0;
 
     if (want_v) HIP_TRY(launch_init_identity(V, ldv, n, st));
 
@@ -246,10 +262,18 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
             h->events.push_back(e);
         }
     }
+    int64_t g = 0;  // p-steps launched in this solve
     for (int sweep = 0; sweep < o.max_sweeps; ++sweep) {
         HIP_TRY(launch_reset_counters(a.counters, st));
-        for (int s = 0; s < nsteps; ++s) {
+        for (int s = 0; s < nsteps; ++s, ++g) {
+            // the previous p-step's V update rides along with this inner launch
+            a.prev_pairs = a.pairs;
+            a.prev_vprime = a.vprime;
+            a.prev_pair_rot = a.pair_rot;
+            a.prev_chunks = g > 0 ? v_chunks : 0;
             a.pairs = blk + (size_t)s * npairs;
+            a.vprime = vprime0 + (size_t)(g % 2) * npairs * bw * bw;
+            a.pair_rot = pair_rot0 + (size_t)(g % 2) * npairs;
             // events around the kernels of every timing_stride-th p-step
             const bool timed = h->timing && s % h->timing_stride == 0;
             hipEvent_t *ev = timed ? &h->events[(size_t)4 * s] : nullptr;
@@ -294,6 +318,13 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     }
     inf.converged = converged ? 1 : 0;
     if (status == JSVD_OK && !converged) status = JSVD_NOT_CONVERGED;
+    if (want_v && g > 0) {  // the last p-step's V update
+        StepArgs av = a;
+        av.upd_rows = (int)upd_rows_v;
+        av.upd_chunks_g = 0;
+        av.upd_chunks_v = (int)((n + upd_rows_v - 1) / upd_rows_v);
+        HIP_TRY(launch_update(bw, av, st));
+    }
 
     // ---- singular values, U, and the output order
     double *s_tmp = reinterpret_cast<double *>(ws + L.s_tmp);
@@ -525,6 +556,9 @@ int jsvd_create(jsvd_handle_t *h, void *hip_stream) {
         return JSVD_HIP_ERROR;
     }
     p->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipDeviceGetAttribute(&p->cu_count, hipDeviceAttributeMultiprocessorCount, p->device) !=
+        hipSuccess)
+        p->cu_count = 0;
     *h = p;
     return JSVD_OK;
 }

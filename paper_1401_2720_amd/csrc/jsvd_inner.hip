@@ -1,7 +1,11 @@
 // p-step kernel 2 of 3: sum of the partial Gram matrices, Cholesky
 // H_pq = R^T R (Section 4.1) and the inner pointwise Jacobi on R with V'_pq
 // accumulated (Section 4.3), all in LDS, one workgroup per pivot block-pair.
-#include "jsvd_device.h"
+// Further workgroups of the same launch apply the previous p-step's V'_pq
+// to V (eq. (2.9)): V lies off the path from one p-step's Gram matrices to
+// the next, and these workgroups stream it through HBM on the CUs that the
+// pivot pairs leave idle.
+#include "jsvd_rows.h"
 
 namespace jsvd {
 
@@ -18,19 +22,23 @@ namespace {
 // order as in the unblocked row-by-row algorithm.
 //
 // Inner Jacobi (Section 4.3): a p-step of the inner strategy has BW/2 pivot
-// pairs.  Threads [0, 8 BW) handle R: every pair is one DPP row of 16 lanes,
-// lane x owning rows x, x + 16, ... of the pair's two columns; the three
-// dot products (subphase 1) are row sums, each row decides and computes its
-// rotation (subphases 2-5), applies it to its columns of R (subphase 6) and
-// publishes it.  Threads [8 BW, 16 BW) apply the previous p-step's
-// rotations to V' at the same time, so V' never lies on the path of the
-// rotations.  One barrier per p-step.
+// pairs.  Threads [0, 4 BW) handle R: every pair is one DPP half row of 8
+// lanes, lane x owning rows x, x + 8, ... of the pair's two columns; the
+// three dot products (subphase 1) are half-row sums, each half row decides
+// and computes its rotation (subphases 2-5), applies it to its columns of R
+// (subphase 6) and publishes it.  Threads [4 BW, 8 BW) apply the previous
+// p-step's rotations to V' at the same time, so V' never lies on the path of
+// the rotations; the remaining waves only keep the barriers.  One barrier
+// per p-step.  The rotation formulas are computed once per pair and wave
+// lane group, so fewer lanes per pair (more rows per lane) means fewer
+// waves repeating them: with 8 lanes the R side is one wave per SIMD.
 template <int BW>
 struct InnerCfg {
     static constexpr int kThreads = BW * 16;
-    static constexpr int kHalf = kThreads / 2;   // threads on R (and on V')
-    static constexpr int kRows = BW / 16;        // rows per lane and column
+    static constexpr int kLanes = 8;             // lanes per pivot pair
+    static constexpr int kRows = BW / kLanes;    // rows per lane and column
     static constexpr int kPairs = BW / 2;        // pivot pairs per p-step
+    static constexpr int kHalf = kPairs * kLanes;  // threads on R (and on V')
     static constexpr int kSteps = BW - 1;        // p-steps per inner sweep
     static constexpr int kLD = BW + 1;
 };
@@ -54,6 +62,19 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
     __shared__ int flags[2];                // [0] NaN met, [1] zero pivots
     __shared__ int cnt[NWAVES][4];
 
+    if (blockIdx.x >= a.npairs) {
+        // V <- V V'_pq of the previous p-step on one chunk of rows; these
+        // workgroups come after the pivot pairs' in the grid, so the pairs
+        // are dispatched first
+        const int idx = blockIdx.x - a.npairs;
+        const int vpair = idx / a.prev_chunks, chunk = idx % a.prev_chunks;
+        if (a.prev_pair_rot[vpair] == 0) return;
+        const int64_t r0 = (int64_t)chunk * a.prev_rows;
+        const int64_t r1 = min(a.n, r0 + (int64_t)a.prev_rows);
+        update_rows<BW, NWAVES, 1>(a.V, a.ldv, r0, r1, a.prev_pairs[vpair], a.w, a.n,
+                                a.prev_vprime + (size_t)vpair * BW * BW, R);
+        return;
+    }
     const int pair = blockIdx.x;
     const int2 pq = a.pairs[pair];
     const int tid = threadIdx.x;
@@ -112,6 +133,7 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
     }
     if (tid < 2) flags[tid] = 0;
     __syncthreads();
+
 
     // ---- nothing to do: when every pair (i, j) of the block pair already
     // passes the relative orthogonality test on H itself, no rotation can
@@ -200,10 +222,12 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
     if (tid == 0 && flags[1]) atomicAdd(&a.counters[C_BREAKDOWN], (unsigned long long)flags[1]);
 
     // ---- inner Jacobi (Section 4.3)
+    constexpr int LN = Cfg::kLanes;
     const bool on_r = tid < HALF;
-    const int gt = on_r ? tid : tid - HALF;
-    const int x = gt & 15;      // first row owned by this lane
-    const int slot = gt >> 4;   // pivot pair of this 16-lane row
+    const bool on_v = !on_r && tid < 2 * HALF;
+    const int gt = on_r ? tid : (on_v ? tid - HALF : 0);
+    const int x = gt % LN;      // first row owned by this lane
+    const int slot = gt / LN;   // pivot pair of this lane group
     const double tol = kEps * sqrt((double)BW);  // c(eps) = eps sqrt(nhat), nhat = 2w
     int rot_total = 0, proper_total = 0, clamp_total = 0, sweeps = 0;
 
@@ -216,8 +240,8 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
                     double rp[ROWS], rq[ROWS];
 #pragma unroll
                     for (int r = 0; r < ROWS; ++r) {
-                        rp[r] = R[p * LD + x + 16 * r];
-                        rq[r] = R[q * LD + x + 16 * r];
+                        rp[r] = R[p * LD + x + LN * r];
+                        rq[r] = R[q * LD + x + LN * r];
                     }
                     double hpp = 0.0, hqq = 0.0, hpq = 0.0;
 #pragma unroll
@@ -226,9 +250,9 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
                         hqq = fma(rq[r], rq[r], hqq);
                         hpq = fma(rp[r], rq[r], hpq);
                     }
-                    hpp = row_sum(hpp);
-                    hqq = row_sum(hqq);
-                    hpq = row_sum(hpq);
+                    hpp = group_sum<LN>(hpp);
+                    hqq = group_sum<LN>(hqq);
+                    hpq = group_sum<LN>(hpq);
                     // subphase 2: relative orthogonality (reading: <= skips).
                     // h_pq != 0 implies h_pp, h_qq > 0.
                     const bool rotate = hpq != 0.0 && !(fabs(hpq) <= tol * nsqrt(hpp) * nsqrt(hqq));
@@ -258,8 +282,8 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
                         for (int r = 0; r < ROWS; ++r) {
                             const double np = cs * fma(mtn, rq[r], rp[r]);
                             const double nq = cs * fma(tn, rp[r], rq[r]);
-                            R[cp * LD + x + 16 * r] = np;
-                            R[cq * LD + x + 16 * r] = nq;
+                            R[cp * LD + x + LN * r] = np;
+                            R[cq * LD + x + LN * r] = nq;
                         }
                     }
                     if (x == 0) {
@@ -274,7 +298,7 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
                         f = sfl[(st + 1) * NP + slot];
                     }
                 }
-            } else if (st >= 1) {
+            } else if (on_v && st >= 1) {
                 // V' <- V' (rotation of p-step st - 1)
                 const int s1 = st - 1;
                 const d4 pr = prm[s1 & 1][slot];
@@ -286,13 +310,13 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
                     double xp[ROWS], xq[ROWS];
 #pragma unroll
                     for (int r = 0; r < ROWS; ++r) {
-                        xp[r] = Vp[vp * LD + x + 16 * r];
-                        xq[r] = Vp[vq * LD + x + 16 * r];
+                        xp[r] = Vp[vp * LD + x + LN * r];
+                        xq[r] = Vp[vq * LD + x + LN * r];
                     }
 #pragma unroll
                     for (int r = 0; r < ROWS; ++r) {
-                        Vp[cp * LD + x + 16 * r] = cs * fma(mtn, xq[r], xp[r]);
-                        Vp[cq * LD + x + 16 * r] = cs * fma(tn, xp[r], xq[r]);
+                        Vp[cp * LD + x + LN * r] = cs * fma(mtn, xq[r], xp[r]);
+                        Vp[cq * LD + x + LN * r] = cs * fma(tn, xp[r], xq[r]);
                     }
                 }
             }
@@ -347,10 +371,11 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
 }  // namespace
 
 hipError_t launch_inner(int bw, const StepArgs &a, hipStream_t s) {
+    const dim3 grid(a.npairs * (1 + a.prev_chunks));
     if (bw == 32)
-        hipLaunchKernelGGL(inner_kernel<32>, dim3(a.npairs), dim3(InnerCfg<32>::kThreads), 0, s, a);
+        hipLaunchKernelGGL(inner_kernel<32>, grid, dim3(InnerCfg<32>::kThreads), 0, s, a);
     else
-        hipLaunchKernelGGL(inner_kernel<64>, dim3(a.npairs), dim3(InnerCfg<64>::kThreads), 0, s, a);
+        hipLaunchKernelGGL(inner_kernel<64>, grid, dim3(InnerCfg<64>::kThreads), 0, s, a);
     return hipGetLastError();
 }
 

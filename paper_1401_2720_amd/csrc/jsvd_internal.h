@@ -56,6 +56,13 @@ struct StepArgs {
     int upd_rows;       // rows per update workgroup, multiple of 64
     int upd_chunks_g;   // update workgroups over the rows of G (per pair)
     int upd_chunks_v;   // update workgroups over the rows of V (per pair)
+    // the V update of the previous p-step, done by prev_chunks extra
+    // workgroups per pivot pair in the inner kernel's launch (0: none)
+    const int2 *prev_pairs;
+    const double *prev_vprime;
+    const int *prev_pair_rot;
+    int prev_chunks;
+    int prev_rows;      // rows of V per such workgroup
 };
 
 hipError_t launch_gram(int bw, const StepArgs &a, hipStream_t s);
