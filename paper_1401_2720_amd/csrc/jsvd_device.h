@@ -64,6 +64,28 @@ __device__ __forceinline__ double nsqrt(double u) {
     return fma(d, h, s);
 }
 
+// 1/sqrt(u) and sqrt(u) for a positive finite u, normal or subnormal: u is
+// scaled by an even power of two into [0.5, 2), where the reciprocal square
+// root seed is refined by two coupled Newton steps (the root and half its
+// reciprocal) and the root by a final residual correction; the scaling is
+// undone exactly.  No branch.
+__device__ __forceinline__ void rsqrt_sqrt(double u, double &rs, double &d) {
+    const int e = __builtin_amdgcn_frexp_exp(u) >> 1;
+    const double v = ldexp(u, -2 * e);
+    const double y = __builtin_amdgcn_rsq(v);
+    double s = v * y, h = 0.5 * y;
+    double r = fma(-s, h, 0.5);
+    s = fma(s, r, s);
+    h = fma(h, r, h);
+    r = fma(-s, h, 0.5);
+    s = fma(s, r, s);
+    h = fma(h, r, h);
+    const double c = fma(-s, s, v);
+    s = fma(c, h, s);
+    rs = ldexp(h, 1 - e);
+    d = ldexp(s, e);
+}
+
 // 64-bit DPP move within a row of 16 lanes (bound_ctrl: no old value).
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double v) {
@@ -153,6 +175,13 @@ __device__ __forceinline__ void rotation_fast(double hpp, double hqq, double hpq
     tn = sgn * nrcp(act);
     const double c = ndiv(act, nsqrt(fma(act, act, tt)));
     cs = (act >= kSqrt2OverEps) ? 1.0 : c;
+}
+
+// h_pp and h_qq in [2^-450, 2^450]: then the relative orthogonality test
+// can be taken on squares, and a rotating pair has |h_pq| in [2^-500, 2^450],
+// inside the range of rotation_fast.
+__device__ __forceinline__ bool in_trig_range(double hpp, double hqq) {
+    return fmin(hpp, hqq) >= 0x1p-450 && fmax(hpp, hqq) <= 0x1p450;
 }
 
 __device__ __forceinline__ bool in_fast_range(double v) {

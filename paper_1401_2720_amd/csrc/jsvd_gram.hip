@@ -23,7 +23,16 @@ __global__ __launch_bounds__(256) void gram_kernel(StepArgs a) {
     constexpr int SLICE = 4 * S;  // rows per wave and iteration
     __shared__ d4 red[NT * 64];
 
-    const int pair = blockIdx.y, split = blockIdx.x;
+    // Workgroups go to the 8 XCDs round robin by linear index.  When the
+    // pairs divide evenly, all splits of pair k run on XCD k mod 8, where
+    // the inner kernel's workgroup k (linear index k) sums them from L2.
+    int pair = blockIdx.y, split = blockIdx.x;
+    if (a.npairs % 8 == 0) {
+        const int lin = blockIdx.x + gridDim.x * blockIdx.y;
+        const int xcd = lin % 8, s = lin / 8;
+        pair = xcd + 8 * (s / a.splits);
+        split = s % a.splits;
+    }
     const int2 pq = a.pairs[pair];
     if ((int64_t)pq.x * a.w >= a.n) return;  // both block-columns are padding
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

@@ -84,6 +84,24 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
     }
     const int lane = tid & 63, wave = tid >> 6;
 
+    // ---- H_pq: the partial Gram matrices summed in split order (upper
+    // triangle, all loads of a batch of 8 splits issued together); padding
+    // columns become unit vectors orthogonal to everything.  The first batch
+    // is issued before the table setup below, which overlaps its latency.
+    const double *hp = a.hpart + (size_t)pair * a.splits * BW * BW;
+    double hv[8][EPT];
+    auto load_batch = [&](int s0) {
+#pragma unroll
+        for (int sp = 0; sp < 8; ++sp)
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                const int e = tid + u * NT;
+                hv[sp][u] = (s0 + sp < a.splits && e / BW <= e % BW)
+                                ? hp[(size_t)(s0 + sp) * BW * BW + e] : 0.0;
+            }
+    };
+    load_batch(0);
+
     // ---- strategy table and pair flags: 1 hyperbolic (kp < n+ <= kq),
     // 2 a padding column, 4 both columns in the + part, 8 both in the - part
     for (int e = tid; e < NS * NP; e += NT) {
@@ -97,29 +115,17 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
         sfl[e] = (unsigned char)f;
     }
 
-    // ---- H_pq: the partial Gram matrices summed in split order (upper
-    // triangle, all loads of a thread issued together); padding columns
-    // become unit vectors orthogonal to everything
     {
-        const double *hp = a.hpart + (size_t)pair * a.splits * BW * BW;
         double s[EPT];
 #pragma unroll
         for (int u = 0; u < EPT; ++u) s[u] = 0.0;
         for (int s0 = 0; s0 < a.splits; s0 += 8) {
-            double v[8][EPT];
-#pragma unroll
-            for (int sp = 0; sp < 8; ++sp)
-#pragma unroll
-                for (int u = 0; u < EPT; ++u) {
-                    const int e = tid + u * NT;
-                    v[sp][u] = (s0 + sp < a.splits && e / BW <= e % BW)
-                                   ? hp[(size_t)(s0 + sp) * BW * BW + e] : 0.0;
-                }
+            if (s0) load_batch(s0);
 #pragma unroll
             for (int sp = 0; sp < 8; ++sp)
 #pragma unroll
                 for (int u = 0; u < EPT; ++u)
-                    if (s0 + sp < a.splits) s[u] += v[sp][u];
+                    if (s0 + sp < a.splits) s[u] += hv[sp][u];
         }
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
@@ -158,7 +164,10 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
     }
 
     // ---- Cholesky H = R^T R (Section 4.1).  A pivot that is not positive
-    // (H only semidefinite: dependent columns) makes its row of R zero.
+    // (H only semidefinite: dependent columns) makes its row of R zero; a
+    // pivot that is NaN or infinite stops the pair.  The panel has no branch,
+    // so the updates of one pivot overlap the square root of the next; row k
+    // of R is H's row k times 1/sqrt(h_kk).
 #pragma unroll
     for (int kb = 0; kb < BW / 16; ++kb) {
         if (wave == 0) {
@@ -171,16 +180,14 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
             for (int k = 0; k < 16; ++k) {
                 const int kk = 16 * kb + k;
                 const double hkk = lane_value(hb[k], kk);
-                double r = 0.0;
-                if (hkk > 0.0) {
-                    const double d = sqrt(hkk);
-                    r = (j == kk) ? d : hb[k] / d;
-                } else if (hkk != hkk) {
-                    nan_met = 1;
-                } else {
-                    ++zero_pivots;
-                }
-                if (j < kk) r = 0.0;
+                const bool bad = !(fabs(hkk) <= 0x1.fffffffffffffp+1023);  // NaN or infinite
+                const bool pos = !bad && hkk > 0.0;
+                nan_met |= bad ? 1 : 0;
+                zero_pivots += (!bad && !pos) ? 1 : 0;
+                double rs, d;
+                rsqrt_sqrt(pos ? hkk : 1.0, rs, d);
+                double r = (j == kk) ? d : hb[k] * rs;
+                r = (pos && j >= kk) ? r : 0.0;
                 hb[k] = r;
 #pragma unroll
                 for (int i = k + 1; i < 16; ++i) hb[i] = fma(-lane_value(r, 16 * kb + i), r, hb[i]);
@@ -229,6 +236,7 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
     const int x = gt % LN;      // first row owned by this lane
     const int slot = gt / LN;   // pivot pair of this lane group
     const double tol = kEps * sqrt((double)BW);  // c(eps) = eps sqrt(nhat), nhat = 2w
+    const double tol2 = kEps * kEps * BW;        // tol^2, exact
     int rot_total = 0, proper_total = 0, clamp_total = 0, sweeps = 0;
 
     for (int sw = 0; sw < a.max_inner_sweeps; ++sw) {
@@ -253,15 +261,21 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
                     hpp = group_sum<LN>(hpp);
                     hqq = group_sum<LN>(hqq);
                     hpq = group_sum<LN>(hpq);
-                    // subphase 2: relative orthogonality (reading: <= skips).
+                    // subphase 2: relative orthogonality (reading: <= skips),
+                    // on squares where they cannot leave the normal range.
                     // h_pq != 0 implies h_pp, h_qq > 0.
-                    const bool rotate = hpq != 0.0 && !(fabs(hpq) <= tol * nsqrt(hpp) * nsqrt(hqq));
+                    const bool mid = in_trig_range(hpp, hqq);
+                    bool rotate;
+                    if (mid)
+                        rotate = !(hpq * hpq <= tol2 * hpp * hqq);
+                    else
+                        rotate = hpq != 0.0 && !(fabs(hpq) <= tol * sqrt(hpp) * sqrt(hqq));
                     // subphase 4: hyperbolic iff kp < n+ <= kq
                     const int t = (f & 1) ? -1 : 1;
                     double tn = 0.0, cs = 1.0;
                     bool clamped = false;
                     if (rotate) {
-                        if (in_fast_range(hpp) && in_fast_range(hqq) && in_fast_range(fabs(hpq)))
+                        if (mid || (in_fast_range(hpp) && in_fast_range(hqq) && in_fast_range(fabs(hpq))))
                             rotation_fast(hpp, hqq, hpq, t, tn, cs, clamped);
                         else
                             rotation(hpp, hqq, hpq, t, tn, cs, clamped);
