@@ -46,15 +46,18 @@ def parse():
 TIMING_STRIDE = 8
 
 
-def kernel_roofline(name, avg_ms, per_launch, w):
-    """Roofline entry of one p-step kernel from its algorithmic work per launch."""
-    bw = 2 * w
+def kernel_roofline(name, avg_ms, per_launch):
+    """Roofline entry of one p-step kernel from its algorithmic work per
+    launch: HBM- or MFMA-bound by its arithmetic intensity against the
+    ridge point; the inner kernel, whose Cholesky and Jacobi work is a chain
+    of dependent FP64 vector operations, against the FP64 vector peak."""
     sec = avg_ms * 1e-3
     if name == "inner":
         achieved = per_launch["inner_flops"] / sec / 1e12
         return {"kernel": "inner", "bound": "alu", "achieved": achieved,
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                "traffic": None}
+                "traffic": None,
+                "v_stream_gbs": per_launch["inner_v_bytes"] / sec / 1e9}
     flops = per_launch[name + "_flops"]
     bytes_ = per_launch[name + "_bytes"]
     if flops / max(bytes_, 1) >= RIDGE:
@@ -65,7 +68,7 @@ def kernel_roofline(name, avg_ms, per_launch, w):
     achieved = bytes_ / sec / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-            "intensity_flop_per_byte": flops / bytes_, "bw": bw}
+            "intensity_flop_per_byte": flops / bytes_}
 
 
 def measured_traffic(kernel_name, w):
@@ -291,42 +294,53 @@ def main():
     npairs = nb // 2
     steps_per_sweep = nb - 1
 
-    # algorithmic work per launch (every pair of a p-step is active here),
-    # averaged over all p-steps of the timed solves
+    # algorithmic work per launch, averaged over all p-steps of the timed
+    # solves (pairs whose block pair needed no rotation skip the updates):
+    #   gram    the pivot Gram matrices, a symmetric product: bw (bw + 1) m
+    #           flops per pair on the m x bw columns (read once);
+    #   update  [G_p G_q] V'_pq for the pairs with a transformation: 2 m bw^2
+    #           flops, the columns read and written;
+    #   inner   Cholesky (bw^3 / 3), per inner step and pair the three dot
+    #           products (6 bw) and per rotation the update of two columns of
+    #           R and of V' (12 bw), FP64 vector work; the same launch also
+    #           streams the previous p-step's V update (2 n bw^2 flops, n x bw
+    #           columns read and written per transformed pair).
     launches = sum(sweeps) * steps_per_sweep
     upd_per_launch = sum(updates) / max(launches, 1)
     rot_per_launch = sum(rotations) / max(launches, 1)
     isw_per_launch = sum(inner_sweeps) / max(launches, 1)
     per_launch = {
-        "gram_flops": npairs * 2.0 * m * bw * bw,
+        "gram_flops": npairs * float(bw) * (bw + 1) * m,
         "gram_bytes": npairs * m * bw * 8.0,
-        "update_flops": upd_per_launch * 2.0 * (m + n) * bw * bw,
-        "update_bytes": upd_per_launch * (m + n) * bw * 8.0 * 2,
+        "update_flops": upd_per_launch * 2.0 * m * bw * bw,
+        "update_bytes": upd_per_launch * m * bw * 8.0 * 2,
         "inner_flops": (isw_per_launch * (bw - 1) * (bw // 2) * 6.0 * bw
                         + rot_per_launch * 12.0 * bw + npairs * bw ** 3 / 3.0),
+        "inner_v_flops": upd_per_launch * 2.0 * n * bw * bw,
+        "inner_v_bytes": upd_per_launch * n * bw * 8.0 * 2,
     }
     avg = {k: (kt[k][0] / max(kt[k][1], 1)) for k in kt}
+    rooflines = {}
+    for name in ("gram", "inner", "update"):
+        r = kernel_roofline(name, avg[name], per_launch)
+        r["avg_launch_us"] = avg[name] * 1e3
+        r["launches"] = kt[name][1]
+        r["traffic"] = measured_traffic(name, w)
+        r["algorithmic_per_launch"] = {k: v for k, v in per_launch.items() if k.startswith(name)}
+        rooflines[name] = r
     dominant = max(kt, key=lambda k: kt[k][0])
-    roof = kernel_roofline(dominant, avg[dominant], per_launch, w)
-    roof["avg_launch_us"] = avg[dominant] * 1e3
-    roof["launches"] = kt[dominant][1]
+    roof = dict(rooflines[dominant])
     roof["timed_every_nth_pstep"] = TIMING_STRIDE
-    roof["traffic"] = measured_traffic(dominant, w)
-    roof["algorithmic_per_launch"] = {k: v for k, v in per_launch.items()
-                                      if k.startswith(dominant)}
     # FP64 MFMA rate of the two contraction kernels over their HIP-event
-    # times.  The Gram kernel forms only the T(T+1)/2 tiles on and above the
-    # diagonal of each pair's (2w)^2 Gram matrix (T = 2w/16): executed FLOPs
-    # are reported beside the full-tile count of the algorithm.
+    # times.  The Gram kernel forms the T(T+1)/2 tiles on and above the
+    # diagonal of each pair's (2w)^2 Gram matrix (T = 2w/16).
     tiles = bw // 16
-    gram_exec = per_launch["gram_flops"] * (tiles * (tiles + 1) / 2) / (tiles * tiles)
+    gram_exec = npairs * 2.0 * m * bw * bw * (tiles * (tiles + 1) / 2) / (tiles * tiles)
     mfma = {"peak_tflops": PEAK_FP64_TFLOPS}
     for name, fl in (("gram", gram_exec), ("update", per_launch["update_flops"])):
         tf = fl / (avg[name] * 1e-3) / 1e12
         mfma[name] = {"executed_flops_per_launch": fl, "tflops": tf,
                       "frac": tf / PEAK_FP64_TFLOPS, "avg_launch_us": avg[name] * 1e3}
-    mfma["gram"]["algorithmic_full_tile_tflops"] = (
-        per_launch["gram_flops"] / (avg["gram"] * 1e-3) / 1e12)
 
     # accuracy of the last step against properties that hold at any size
     Ucm = work.t()
@@ -361,6 +375,7 @@ def main():
                    "max_inner_sweeps": args.max_inner_sweeps, "sweeps": sweeps,
                    "rotations": rotations[-1]},
         "roofline": roof,
+        "rooflines": rooflines,
         "mfma": mfma,
         "kernels_avg_us": {k: avg[k] * 1e3 for k in avg},
         "kernels_share": {k: kt[k][0] / max(sum(v[0] for v in kt.values()), 1e-9) for k in kt},
