@@ -17,9 +17,8 @@ namespace {
 //
 // Cholesky (Section 4.1) by block rows of 16: wave 0 factors a block row
 // with lane j holding column j, pivots and multipliers broadcast by
-// readlane; then all threads subtract the block row's contribution from the
-// trailing part of H.  The subtractions of each entry happen in the same
-// order as in the unblocked row-by-row algorithm.
+// readlane; then the block row's contribution is subtracted from the
+// trailing part of H on FP64 MFMA, one wave per 16 x 16 tile.
 //
 // Inner Jacobi (Section 4.3): a p-step of the inner strategy has BW/2 pivot
 // pairs.  Threads [0, 4 BW) handle R: every pair is one DPP half row of 8
@@ -86,8 +85,16 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
 
     // ---- H_pq: the partial Gram matrices summed in split order (upper
     // triangle, all loads of a batch of 8 splits issued together); padding
-    // columns become unit vectors orthogonal to everything.  The first batch
-    // is issued before the table setup below, which overlaps its latency.
+    // columns become unit vectors orthogonal to everything.  The strategy
+    // table's loads go first, then the first batch, so that the table setup
+    // below waits for its own loads only.
+    constexpr int TE = (NS * NP + NT - 1) / NT;   // table entries per thread
+    unsigned short tpq[TE];
+#pragma unroll
+    for (int u = 0; u < TE; ++u) {
+        const int e = tid + u * NT;
+        tpq[u] = e < NS * NP ? reinterpret_cast<const unsigned short *>(a.inner_tbl)[e] : 0;
+    }
     const double *hp = a.hpart + (size_t)pair * a.splits * BW * BW;
     double hv[8][EPT];
     auto load_batch = [&](int s0) {
@@ -104,15 +111,19 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
 
     // ---- strategy table and pair flags: 1 hyperbolic (kp < n+ <= kq),
     // 2 a padding column, 4 both columns in the + part, 8 both in the - part
-    for (int e = tid; e < NS * NP; e += NT) {
-        const int p = a.inner_tbl[2 * e], q = a.inner_tbl[2 * e + 1];
-        tb[2 * e] = (unsigned char)p;
-        tb[2 * e + 1] = (unsigned char)q;
-        const int64_t kp = pair_col(p, a.w, pq), kq = pair_col(q, a.w, pq);
-        int f = (kp < a.n_plus && kq >= a.n_plus) ? 1 : 0;
-        f |= (kq >= a.n || kp >= a.n) ? 2 : 0;
-        f |= (kq < a.n_plus) ? 4 : ((kp >= a.n_plus) ? 8 : 0);
-        sfl[e] = (unsigned char)f;
+#pragma unroll
+    for (int u = 0; u < TE; ++u) {
+        const int e = tid + u * NT;
+        if (e < NS * NP) {
+            const int p = tpq[u] & 0xff, q = tpq[u] >> 8;
+            tb[2 * e] = (unsigned char)p;
+            tb[2 * e + 1] = (unsigned char)q;
+            const int64_t kp = pair_col(p, a.w, pq), kq = pair_col(q, a.w, pq);
+            int f = (kp < a.n_plus && kq >= a.n_plus) ? 1 : 0;
+            f |= (kq >= a.n || kp >= a.n) ? 2 : 0;
+            f |= (kq < a.n_plus) ? 4 : ((kp >= a.n_plus) ? 8 : 0);
+            sfl[e] = (unsigned char)f;
+        }
     }
 
     {
@@ -203,17 +214,31 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
         }
         __syncthreads();
         if (kb + 1 < BW / 16) {
-            constexpr int G = NT / BW;
-            const int j = tid % BW, g = tid / BW;
-            if (j >= 16 * (kb + 1)) {
-                double rj[16];
+            // H(i, j) -= sum_k R(16 kb + k, i) R(16 kb + k, j) on the 16 x 16
+            // tiles (ti, tj), kb < ti <= tj, one wave and 4 FP64 MFMAs per tile
+            constexpr int TB = BW / 16;
+            int idx = wave, ti = -1, tj = -1;
 #pragma unroll
-                for (int k = 0; k < 16; ++k) rj[k] = R[j * LD + 16 * kb + k];
-                for (int i = 16 * (kb + 1) + g; i <= j; i += G) {
-                    double h = R[j * LD + i];
+            for (int t0 = kb + 1; t0 < TB; ++t0) {
+                if (ti < 0 && idx < TB - t0) {
+                    ti = t0;
+                    tj = t0 + idx;
+                } else if (ti < 0) {
+                    idx -= TB - t0;
+                }
+            }
+            if (ti >= 0) {
+                const int l16 = lane & 15, l4 = lane >> 4;
+                d4 acc = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                    for (int k = 0; k < 16; ++k) h = fma(-R[i * LD + 16 * kb + k], rj[k], h);
-                    R[j * LD + i] = h;
+                for (int c = 0; c < 4; ++c) {
+                    const int k = 16 * kb + 4 * c + l4;
+                    acc = mfma16(R[(16 * ti + l16) * LD + k], R[(16 * tj + l16) * LD + k], acc);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 16 * ti + l4 + 4 * v, j = 16 * tj + l16;
+                    if (i <= j) R[j * LD + i] -= acc[v];
                 }
             }
             __syncthreads();
