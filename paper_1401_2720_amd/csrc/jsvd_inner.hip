@@ -42,7 +42,9 @@ struct InnerCfg {
     static constexpr int kLD = BW + 1;
 };
 
-template <int BW>
+// HYP: the problem has columns of both signs (J != I); without it every
+// pair is trigonometric and the hyperbolic branches are compiled out.
+template <int BW, bool HYP>
 __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs a) {
     using Cfg = InnerCfg<BW>;
     constexpr int NT = Cfg::kThreads;
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
                     else
                         rotate = hpq != 0.0 && !(fabs(hpq) <= tol * sqrt(hpp) * sqrt(hqq));
                     // subphase 4: hyperbolic iff kp < n+ <= kq
-                    const int t = (f & 1) ? -1 : 1;
+                    const int t = (HYP && (f & 1)) ? -1 : 1;
                     double tn = 0.0, cs = 1.0;
                     bool clamped = false;
                     if (rotate) {
@@ -311,7 +313,7 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
                     if (!(f & 3)) {
                         const double npp = fma(-tn, hpq, hpp);
                         const double nqq = fma(tn, hpq, hqq);
-                        swap = (f & 4) ? (npp < nqq) : ((f & 8) ? (npp > nqq) : false);
+                        swap = (!HYP || (f & 4)) ? (npp < nqq) : ((f & 8) ? (npp > nqq) : false);
                     }
                     // subphase 6, (4.1) / (4.2).  cs == 1 multiplies exactly.
                     const double mtn = (t > 0) ? -tn : tn;
@@ -411,10 +413,18 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
 
 hipError_t launch_inner(int bw, const StepArgs &a, hipStream_t s) {
     const dim3 grid(a.npairs * (1 + a.prev_chunks));
-    if (bw == 32)
-        hipLaunchKernelGGL(inner_kernel<32>, grid, dim3(InnerCfg<32>::kThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL(inner_kernel<64>, grid, dim3(InnerCfg<64>::kThreads), 0, s, a);
+    const bool hyp = a.n_plus < a.n;
+    if (bw == 32) {
+        if (hyp)
+            hipLaunchKernelGGL((inner_kernel<32, true>), grid, dim3(InnerCfg<32>::kThreads), 0, s, a);
+        else
+            hipLaunchKernelGGL((inner_kernel<32, false>), grid, dim3(InnerCfg<32>::kThreads), 0, s, a);
+    } else {
+        if (hyp)
+            hipLaunchKernelGGL((inner_kernel<64, true>), grid, dim3(InnerCfg<64>::kThreads), 0, s, a);
+        else
+            hipLaunchKernelGGL((inner_kernel<64, false>), grid, dim3(InnerCfg<64>::kThreads), 0, s, a);
+    }
     return hipGetLastError();
 }
 

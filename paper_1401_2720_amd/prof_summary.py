@@ -35,7 +35,7 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 COMMON = ["jsvd_device.h", "jsvd_internal.h"]
 KERNEL_SOURCES = {"gram": ["jsvd_gram.hip"], "inner": ["jsvd_inner.hip", "jsvd_rows.h"],
                   "update": ["jsvd_update.hip", "jsvd_rows.h"]}
-PSTEP = re.compile(r"\b(gram|inner|update)_kernel<(\d+)>")
+PSTEP = re.compile(r"\b(gram|inner|update)_kernel<(\d+)(?:, (?:true|false))?>")
 
 
 def kernel_sources_sha256(kernel):
@@ -101,7 +101,7 @@ def stats(path, keep="jsvd"):
         name = row["Name"]
         if keep not in name:
             continue
-        m = re.search(r"(\w+(?:<\d+>)?)\(", name)
+        m = re.search(r"(\w+(?:<[^>]*>)?)\(", name)
         short = m.group(1) if m else name[:48]
         print(f"| {short} | {row['Calls']} | {float(row['TotalDurationNs']) / 1e6:.1f} | "
               f"{float(row['AverageNs']) / 1e3:.1f} | {float(row['Percentage']):.1f} % | "
@@ -113,12 +113,13 @@ def mfma(counter_csv, stats_csv, simds=1024, clock_ghz=2.4, peak_tflops=78.6):
     for row in csv.DictReader(open(counter_csv)):
         m = PSTEP.search(row["Kernel_Name"])
         if m:
-            per[m.group(0)][row["Counter_Name"]].append(float(row["Counter_Value"]))
+            per[f"{m.group(1)}_kernel<{m.group(2)}>"][row["Counter_Name"]].append(
+                float(row["Counter_Value"]))
     avg_us = {}
     for row in csv.DictReader(open(stats_csv)):
         m = PSTEP.search(row["Name"])
         if m:
-            avg_us[m.group(0)] = float(row["AverageNs"]) / 1e3
+            avg_us[f"{m.group(1)}_kernel<{m.group(2)}>"] = float(row["AverageNs"]) / 1e3
     print("| kernel | FP64 MFMA FLOP per launch (mean / max) | MFMA busy cycles per SIMD (mean) | "
           "average duration (us) | achieved TFLOP/s | of 78.6 peak | MFMA pipe busy |")
     print("|---|---|---|---|---|---|---|")
