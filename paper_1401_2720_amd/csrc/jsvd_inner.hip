@@ -67,6 +67,10 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
         // V <- V V'_pq of the previous p-step on one chunk of rows; these
         // workgroups come after the pivot pairs' in the grid, so the pairs
         // are dispatched first
+        // start about 7 us late (2 x 127 x 64 cycles): the pair workgroups'
+        // partial Gram loads then do not queue behind this V stream
+        __builtin_amdgcn_s_sleep(127);
+        __builtin_amdgcn_s_sleep(127);
         const int idx = blockIdx.x - a.npairs;
         const int vpair = idx / a.prev_chunks, chunk = idx % a.prev_chunks;
         if (a.prev_pair_rot[vpair] == 0) return;

@@ -241,3 +241,31 @@ def test_hsvd_identity_signature_equals_svd():
     a = _run_gesvd(A, block_w=16)
     b = _run_hsvd(A, np.ones(64, np.int8), block_w=16)
     assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("w", [16, 32])
+@pytest.mark.parametrize("sweeps", [1, 2, 3])
+def test_stopped_early_keeps_g_and_v_consistent(sweeps, w):
+    """When the sweep limit stops the iteration, G and V have seen the same
+    transformations (eq. (2.4), G' = G V): the V update of each p-step runs
+    in the next p-step's inner launch and the last one after the loop, so
+    A V = U diag(S) and V^T V = I hold for the partial result as well."""
+    _say(f"case stopped early: sweeps={sweeps} w={w}")
+    n = 200
+    A = inputs.gaussian(300, n, inputs.rng(15))
+    U, S, V, info = _run_gesvd(A, block_w=w, max_sweeps=sweeps)
+    assert info["sweeps"] == sweeps and info["converged"] == 0
+    assert np.max(np.abs(V.T @ V - np.eye(n))) <= 1e-13 * n
+    assert np.linalg.norm(A @ V - U * S) <= 1e-13 * n * np.linalg.norm(A)
+
+
+def test_hsvd_stopped_early_keeps_g_and_v_consistent():
+    _say("case hsvd stopped early")
+    m, n, npl = 160, 128, 80
+    G = inputs.gaussian(m, n, inputs.rng(16))
+    J = np.concatenate([np.ones(npl), -np.ones(n - npl)]).astype(np.int8)
+    U, S, V, Jout, info = _run_hsvd(G, J, block_w=16, max_sweeps=2)
+    assert info["sweeps"] == 2 and info["converged"] == 0
+    Jm = np.diag(Jout.astype(np.float64))
+    assert np.max(np.abs(V.T @ Jm @ V - Jm)) <= 1e-13 * n * max(1.0, np.max(np.abs(V)) ** 2)
+    assert np.linalg.norm(G @ V - U * S) <= 1e-13 * n * np.linalg.norm(G) * np.linalg.norm(V, 2)
