@@ -39,19 +39,37 @@ __global__ __launch_bounds__(256) void colnorm_kernel(const double *G, int64_t l
 // Output order: positions [0, n_plus) by non-increasing sigma, [n_plus, n)
 // by non-decreasing sigma, ties by column index; NaN sorts as -infinity so
 // that the ranks always form a permutation.
-__global__ void rank_kernel(const double *s, int64_t n, int64_t n_plus, int *perm) {
+// The keys are staged through LDS in chunks shared by the workgroup (every
+// thread compares its key with all keys of its part).
+constexpr int kRankChunk = 2048;
+
+__global__ __launch_bounds__(256) void rank_kernel(const double *s, int64_t n, int64_t n_plus,
+                                                   int *perm) {
+    __shared__ double ks[kRankChunk];
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const bool pos = j < n_plus;
+    const bool valid = j < n;
+    const bool pos = valid && j < n_plus;
     const int64_t lo = pos ? 0 : n_plus, hi = pos ? n_plus : n;
-    const double kj = (s[j] != s[j]) ? -INFINITY : s[j];
+    const double kj = valid ? ((s[j] != s[j]) ? -INFINITY : s[j]) : 0.0;
     int64_t r = lo;
-    for (int64_t i = lo; i < hi; ++i) {
-        const double ki = (s[i] != s[i]) ? -INFINITY : s[i];
-        const bool before = pos ? (ki > kj) : (ki < kj);
-        if (before || (ki == kj && i < j)) ++r;
+    for (int64_t base = 0; base < n; base += kRankChunk) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < kRankChunk; t += blockDim.x) {
+            const double v = base + t < n ? s[base + t] : 0.0;
+            ks[t] = (v != v) ? -INFINITY : v;
+        }
+        __syncthreads();
+        if (valid) {
+            const int64_t i0 = lo > base ? lo : base;
+            const int64_t i1 = hi < base + kRankChunk ? hi : base + kRankChunk;
+            for (int64_t i = i0; i < i1; ++i) {
+                const double ki = ks[i - base];
+                const bool before = pos ? (ki > kj) : (ki < kj);
+                if (before || (ki == kj && i < j)) ++r;
+            }
+        }
     }
-    perm[r] = (int)j;
+    if (valid) perm[r] = (int)j;
 }
 
 // dst[:, k] = src[:, perm[k]] (perm may be null: identity), divided by
