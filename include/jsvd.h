@@ -66,6 +66,16 @@ typedef struct {
     int32_t sort;             /* 1 = order the output (default), 0 = column order as computed */
     int32_t qr;               /* QR preprocessing of a tall G, eq. (2.1), jsvd_gesvd only:
                                  0 = choose (when m >= 2n, default), 1 = never, 2 = always */
+    int32_t scaled;           /* scaled mode for badly scaled G (Section 4.2): every column
+                                 is scaled by a power of two (exactly) before its Gram
+                                 matrices are formed, so that no square or sum leaves the
+                                 normal range; 0 = when some column norm lies outside
+                                 [2^-480, 2^481) (default; costs one pass over G and one
+                                 stream synchronisation), 1 = never, 2 = always.  Covers
+                                 norms over the whole normal range and, within one pivot
+                                 block-pair, ratios of column norms up to about 2^1000
+                                 (tested to 2^900).
+                                 A badly scaled G skips the QR preprocessing. */
 } jsvd_opts;
 
 typedef struct {
@@ -82,6 +92,7 @@ typedef struct {
     int32_t n_blocks;          /* block-columns in the pivot strategy (with padding) */
     double seconds;            /* wall time of the call */
     int32_t preprocessed;      /* 1 if the Jacobi method ran on R^T of a QR of G (eq. (2.1)) */
+    int32_t scaled;            /* 1 if the scaled mode ran (opts.scaled) */
 } jsvd_info;
 
 /*

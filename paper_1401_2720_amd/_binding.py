@@ -24,14 +24,15 @@ STATUS = {0: "ok", 1: "not converged", 2: "Cholesky breakdown", 3: "non-finite v
 
 class Opts(ctypes.Structure):
     _fields_ = [("block_w", _i32), ("strategy", _i32), ("max_inner_sweeps", _i32),
-                ("max_sweeps", _i32), ("want_v", _i32), ("sort", _i32), ("qr", _i32)]
+                ("max_sweeps", _i32), ("want_v", _i32), ("sort", _i32), ("qr", _i32),
+                ("scaled", _i32)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("sweeps", _i32), ("converged", _i32), ("rotations", _i64),
                 ("proper_rotations", _i64), ("inner_sweeps", _i64), ("pair_updates", _i64),
                 ("chol_breakdowns", _i32), ("hyp_clamps", _i32), ("block_w", _i32),
-                ("n_blocks", _i32), ("seconds", _dbl), ("preprocessed", _i32)]
+                ("n_blocks", _i32), ("seconds", _dbl), ("preprocessed", _i32), ("scaled", _i32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -165,11 +166,11 @@ def set_tuning(device_index, table, handle=None):
         raise JsvdError(rc, "jsvd_set_tuning")
 
 
-QR_MODES = {"auto": 0, "off": 1, "on": 2}
+QR_MODES = {"auto": 0, "off": 1, "on": 2}  # also the scaled-mode choices
 
 
 def make_opts(block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,
-              sort=True, qr="auto"):
+              sort=True, qr="auto", scaled="auto"):
     o = Opts()
     lib().jsvd_default_opts(ctypes.byref(o))
     o.block_w = int(block_w)
@@ -179,6 +180,7 @@ def make_opts(block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, wan
     o.want_v = 1 if want_v else 0
     o.sort = 1 if sort else 0
     o.qr = QR_MODES[qr] if isinstance(qr, str) else int(qr)
+    o.scaled = QR_MODES[scaled] if isinstance(scaled, str) else int(scaled)
     return o
 
 
@@ -196,7 +198,7 @@ def _raise_on(rc, what, allow):
 
 
 def gesvd(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,
-          sort=True, allow=(1,), qr="auto"):
+          sort=True, allow=(1,), qr="auto", scaled="auto"):
     """SVD A = U diag(S) V^T of a float64 CUDA tensor (m >= n).
 
     Returns (U, S, V, info): U (m x n) and V (n x n) column-major views, S (n),
@@ -212,7 +214,7 @@ def gesvd(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want
     stream = torch.cuda.current_stream(dev)
     h = _handle(dev.index if dev.index is not None else torch.cuda.current_device(),
                 stream.cuda_stream)
-    o = make_opts(block_w, strategy, max_inner_sweeps, max_sweeps, want_v, sort, qr)
+    o = make_opts(block_w, strategy, max_inner_sweeps, max_sweeps, want_v, sort, qr, scaled)
     info = Info()
     rc = lib().jsvd_gesvd(h, m, n, _vp(work.data_ptr()), m, _vp(S.data_ptr()),
                           _vp(Vb.data_ptr()) if want_v else None, n, ctypes.byref(o),
@@ -224,7 +226,7 @@ def gesvd(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want
 
 
 def hsvd(G, J, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,
-         sort=True, allow=(1,)):
+         sort=True, allow=(1,), scaled="auto"):
     """Hyperbolic SVD G V = U diag(S), V^T J V = diag(J_out).
 
     J: sequence of n values, each +1 or -1.  Returns (U, S, V, J_out, info)
@@ -244,7 +246,7 @@ def hsvd(G, J, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, wa
     stream = torch.cuda.current_stream(dev)
     h = _handle(dev.index if dev.index is not None else torch.cuda.current_device(),
                 stream.cuda_stream)
-    o = make_opts(block_w, strategy, max_inner_sweeps, max_sweeps, want_v, sort)
+    o = make_opts(block_w, strategy, max_inner_sweeps, max_sweeps, want_v, sort, scaled=scaled)
     info = Info()
     rc = lib().jsvd_hsvd(h, m, n, _vp(work.data_ptr()), m, _vp(Jh.ctypes.data),
                          _vp(Jout.ctypes.data), _vp(S.data_ptr()),

@@ -36,6 +36,56 @@ __global__ __launch_bounds__(256) void colnorm_kernel(const double *G, int64_t l
     if (threadIdx.x == 0) s_out[j] = sqrt(part[0]);
 }
 
+// Column norms without overflow or underflow (the concern of Section 4.2
+// and Appendix A for badly scaled input): the largest magnitude m_j of the
+// column fixes a power of two 2^e0, the squares are summed of the column
+// scaled by 2^-e0 (exactly), and ||g_j|| = 2^e0 sqrt(sum).  Writes, when
+// asked, the norm and the exponent e_j of ||g_j|| (||g_j|| in [2^e_j,
+// 2^(e_j+1)); 0 for a zero column), and folds the exponents of the nonzero
+// columns into range[0] (min) and range[1] (max).
+__global__ __launch_bounds__(256) void colexp_kernel(const double *G, int64_t ldg, int64_t m,
+                                                     double *s_out, int *ex, int *range) {
+    __shared__ double part[256];
+    const int64_t j = blockIdx.x;
+    const double *g = G + j * ldg;
+    double mx = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += 256) mx = fmax(mx, fabs(g[i]));
+    part[threadIdx.x] = mx;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] = fmax(part[threadIdx.x], part[threadIdx.x + h]);
+        __syncthreads();
+    }
+    mx = part[0];
+    __syncthreads();
+    const bool nz = mx > 0.0 && mx <= 0x1.fffffffffffffp+1023;
+    const int e0 = nz ? ilogb(mx) : 0;
+    double sq = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += 256) {
+        const double v = ldexp(g[i], -e0);
+        sq = fma(v, v, sq);
+    }
+    part[threadIdx.x] = sq;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double r = sqrt(part[0]);  // in [1, sqrt(m)] for a finite nonzero column
+        const bool fin = nz && r <= 0x1.fffffffffffffp+1023;  // no NaN met
+        if (s_out) s_out[j] = nz ? ldexp(r, e0) : (mx == 0.0 ? 0.0 : mx * r);
+        if (ex) {
+            const int e = fin ? e0 + ilogb(r) : 0;
+            ex[j] = e;
+            if (fin && range) {
+                atomicMin(&range[0], e);
+                atomicMax(&range[1], e);
+            }
+        }
+    }
+}
+
 // Output order: positions [0, n_plus) by non-increasing sigma, [n_plus, n)
 // by non-decreasing sigma, ties by column index; NaN sorts as -infinity so
 // that the ranks always form a permutation.
@@ -124,6 +174,25 @@ hipError_t launch_init_identity(double *V, int64_t ldv, int64_t n, hipStream_t s
 hipError_t launch_colnorms(const double *G, int64_t ldg, int64_t m, int64_t n, double *s_out,
                            hipStream_t s) {
     hipLaunchKernelGGL(colnorm_kernel, dim3((unsigned)n), dim3(256), 0, s, G, ldg, m, s_out);
+    return hipGetLastError();
+}
+
+__global__ void range_init_kernel(int *range) {
+    if (threadIdx.x == 0) {
+        range[0] = 0x7fffffff;
+        range[1] = -0x7fffffff - 1;
+    }
+}
+
+hipError_t launch_range_init(int *range, hipStream_t s) {
+    hipLaunchKernelGGL(range_init_kernel, dim3(1), dim3(64), 0, s, range);
+    return hipGetLastError();
+}
+
+hipError_t launch_colexp(const double *G, int64_t ldg, int64_t m, int64_t n, double *s_out,
+                         int *ex, int *range, hipStream_t s) {
+    hipLaunchKernelGGL(colexp_kernel, dim3((unsigned)n), dim3(256), 0, s, G, ldg, m, s_out, ex,
+                       range);
     return hipGetLastError();
 }
 

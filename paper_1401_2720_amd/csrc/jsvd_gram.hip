@@ -15,7 +15,8 @@ namespace {
 // symmetric H are formed.
 typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
 
-template <int BW>
+// SC: scaled mode, column c multiplied by 2^-e_c (exact) as it is loaded.
+template <int BW, bool SC>
 __global__ __launch_bounds__(256) void gram_kernel(StepArgs a) {
     constexpr int T = BW / 16;
     constexpr int NT = T * (T + 1) / 2;
@@ -40,11 +41,13 @@ __global__ __launch_bounds__(256) void gram_kernel(StepArgs a) {
 
     const double *col[T];
     bool valid[T];
+    int sh[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         const int64_t gc = pair_col(t * 16 + i16, a.w, pq);
         valid[t] = gc < a.n;
         col[t] = a.G + (valid[t] ? gc : 0) * a.ldg;
+        sh[t] = (SC && valid[t]) ? -a.colexp[gc] : 0;
     }
 
     d4 acc[NT];
@@ -72,6 +75,12 @@ __global__ __launch_bounds__(256) void gram_kernel(StepArgs a) {
 #pragma unroll
                 for (int s = 0; s < S; ++s)
                     x[t][s] = (valid[t] && rb + s < r1) ? col[t][rb + s] : 0.0;
+        }
+        if constexpr (SC) {
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int s = 0; s < S; ++s) x[t][s] = ldexp(x[t][s], sh[t]);
         }
         int k = 0;
 #pragma unroll
@@ -111,10 +120,17 @@ __global__ __launch_bounds__(256) void gram_kernel(StepArgs a) {
 
 hipError_t launch_gram(int bw, const StepArgs &a, hipStream_t s) {
     dim3 grid(a.splits, a.npairs);
-    if (bw == 32)
-        hipLaunchKernelGGL(gram_kernel<32>, grid, dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(gram_kernel<64>, grid, dim3(256), 0, s, a);
+    if (a.colexp) {
+        if (bw == 32)
+            hipLaunchKernelGGL((gram_kernel<32, true>), grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((gram_kernel<64, true>), grid, dim3(256), 0, s, a);
+    } else {
+        if (bw == 32)
+            hipLaunchKernelGGL((gram_kernel<32, false>), grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((gram_kernel<64, false>), grid, dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 

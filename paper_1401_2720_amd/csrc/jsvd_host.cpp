@@ -38,6 +38,8 @@ struct jsvd_handle_s {
     int cu_count = 0;
     int batch_lds = 0;              // dynamic LDS bytes of the batched kernel
     jsvd_tuning tuning{};           // measured choices (count == 0: none)
+    int *colexp = nullptr;          // scaled mode: column exponents (n) + range (2)
+    int64_t colexp_cap = 0;
     void *qr_ws = nullptr;          // QR preprocessing workspace (kept apart from ws,
     size_t qr_ws_bytes = 0;         // which the Jacobi solve of R^T may reallocate)
     // per-kernel timing (measurement aid): 4 events per p-step
@@ -124,6 +126,7 @@ jsvd_opts defaults() {
     o.want_v = 1;
     o.sort = 1;
     o.qr = 0;
+    o.scaled = 0;
     return o;
 }
 
@@ -166,6 +169,38 @@ Layout plan(int64_t m, int64_t n, int bw, int npairs, int splits, bool hsvd) {
     L.perm_in = take(hsvd ? (size_t)n * sizeof(int) : 0);
     L.total = off;
     return L;
+}
+
+// Column exponents of G (e_c with ||g_c|| in [2^e_c, 2^(e_c+1))) into the
+// handle's buffer, and whether G is badly scaled: some column norm outside
+// [2^-480, 2^481), where the squares and sums of the Gram matrices could
+// leave the normal range (Section 4.2).  One pass over G and one stream
+// synchronisation.
+int column_exponents(jsvd_handle_s *h, int64_t m, int64_t n, const double *A, int64_t lda,
+                     bool *bad) {
+    if (n + 2 > h->colexp_cap) {
+        if (h->colexp) {
+            if (hipStreamSynchronize(h->stream) != hipSuccess) return JSVD_HIP_ERROR;
+            (void)hipFree(h->colexp);
+        }
+        h->colexp = nullptr;
+        h->colexp_cap = 0;
+        if (hipMalloc(&h->colexp, (size_t)(n + 2) * sizeof(int)) != hipSuccess) {
+            h->colexp = nullptr;
+            return JSVD_NO_MEMORY;
+        }
+        h->colexp_cap = n + 2;
+    }
+    int *range = h->colexp + n;
+    HIP_TRY(launch_range_init(range, h->stream));
+    HIP_TRY(launch_colexp(A, lda, m, n, nullptr, h->colexp, range, h->stream));
+    if (bad) {
+        int *hr = reinterpret_cast<int *>(h->host_counters);
+        HIP_TRY(hipMemcpyAsync(hr, range, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        *bad = hr[0] <= hr[1] && (hr[0] < -480 || hr[1] > 480);
+    }
+    return JSVD_OK;
 }
 
 // The solver shared by the SVD and the hyperbolic SVD.  A holds G with J
@@ -236,6 +271,14 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     a.pair_rot = pair_rot0;
     a.counters = reinterpret_cast<unsigned long long *>(ws + L.counters);
     a.inner_tbl = inner;
+    // scaled mode (opts.scaled: 2 on, 1 off, 0 when G is badly scaled)
+    bool scaled = o.scaled == 2;
+    if (o.scaled != 1) {
+        bool bad = false;
+        if ((rc = column_exponents(h, m, n, A, lda, o.scaled == 0 ? &bad : nullptr))) return rc;
+        scaled = scaled || bad;
+    }
+    a.colexp = scaled ? h->colexp : nullptr;
     a.max_inner_sweeps = o.max_inner_sweeps > 0 ? o.max_inner_sweeps : choose_inner_sweeps(m, n);
     a.upd_rows = (int)upd_rows_g;
     a.upd_chunks_g = (int)((m + upd_rows_g - 1) / upd_rows_g);
@@ -252,6 +295,7 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     jsvd_info inf{};
     std::memset(&inf, 0, sizeof inf);
     inf.block_w = w;
+    inf.scaled = scaled ? 1 : 0;
     inf.n_blocks = order;
     int status = JSVD_OK;
     bool converged = false;
@@ -330,7 +374,10 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     double *s_tmp = reinterpret_cast<double *>(ws + L.s_tmp);
     int *perm = reinterpret_cast<int *>(ws + L.perm);
     double *tmp = reinterpret_cast<double *>(ws + L.tmp);
-    HIP_TRY(launch_colnorms(A, lda, m, n, s_tmp, st));
+    if (scaled)
+        HIP_TRY(launch_colexp(A, lda, m, n, s_tmp, nullptr, nullptr, st));
+    else
+        HIP_TRY(launch_colnorms(A, lda, m, n, s_tmp, st));
     if (o.sort) {
         HIP_TRY(launch_rank(s_tmp, n, n_plus, perm, st));
         HIP_TRY(hipMemcpy2DAsync(tmp, m * sizeof(double), A, lda * sizeof(double),
@@ -531,6 +578,7 @@ int check_common(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
     if (o.strategy < JSVD_STRAT_RREV || o.strategy > JSVD_STRAT_C) return -9;
     if (o.max_sweeps < 1 || o.max_inner_sweeps < 0) return -9;
     if (o.qr < 0 || o.qr > 2) return -9;
+    if (o.scaled < 0 || o.scaled > 2) return -9;
     if (m > (int64_t)1 << 31 || n > (int64_t)1 << 20) return -2;
     return JSVD_OK;
 }
@@ -595,6 +643,7 @@ int jsvd_destroy(jsvd_handle_t h) {
     if (h->batch_meta) (void)hipFree(h->batch_meta);
     if (h->host_counters) (void)hipHostFree(h->host_counters);
     if (h->qr_ws) (void)hipFree(h->qr_ws);
+    if (h->colexp) (void)hipFree(h->colexp);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     delete h;
     return JSVD_OK;
@@ -609,7 +658,14 @@ int jsvd_gesvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda, do
     if (o.want_v && !V) return -7;
     if (o.want_v && ldv < n) return -8;
     if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
-    const bool qr = (o.qr == 2 || (o.qr == 0 && m >= 2 * n)) && m <= 32768 && n >= 1;
+    bool qr = (o.qr == 2 || (o.qr == 0 && m >= 2 * n)) && m <= 32768 && n >= 1;
+    if (qr && o.scaled != 1) {
+        // the Householder norms of the preprocessing are not scaled: a badly
+        // scaled G goes to the scaled Jacobi method directly
+        bool bad = o.scaled == 2;
+        if (!bad && (rc = column_exponents(h, m, n, A, lda, &bad))) return rc;
+        qr = !bad;
+    }
     if (qr) return gesvd_qr(h, m, n, A, lda, S, V, ldv, o, info);
     return solve(h, m, n, A, lda, S, V, ldv, n, o, info, false, nullptr);
 }

@@ -44,7 +44,16 @@ struct InnerCfg {
 
 // HYP: the problem has columns of both signs (J != I); without it every
 // pair is trigonometric and the hyperbolic branches are compiled out.
-template <int BW, bool HYP>
+// SC: scaled mode (badly scaled input).  The partial sums are of
+// H~ = D^-1 H D^-1, D = diag(2^e_c); R~ = R D^-1 is kept with the column
+// exponents e_c in LDS.  A pair's dot products on R~ are those of R times
+// 2^-(e_p+e_q) after the factors 2^(e_p-e_q), 2^(e_q-e_p) on h_pp, h_qq, so
+// the orthogonality test (scale free) and the rotation formulas see the same
+// values as on R up to one exact power of two; the rotation is applied to R~
+// with tan phi scaled by 2^(e_q-e_p) (into column p) and 2^(e_p-e_q) (into
+// column q), to V' unscaled, and a swap also swaps the two exponents.  At
+// the end the exponents of the transformed columns go back to global memory.
+template <int BW, bool HYP, bool SC>
 __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs a) {
     using Cfg = InnerCfg<BW>;
     constexpr int NT = Cfg::kThreads;
@@ -62,6 +71,7 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
     __shared__ d4 prm[2][NP];               // published rotations: mtn, tn, cs, flags
     __shared__ int flags[2];                // [0] NaN met, [1] zero pivots
     __shared__ int cnt[NWAVES][4];
+    __shared__ int ex[BW];                  // scaled mode: column exponents
 
     if (blockIdx.x >= a.npairs) {
         // V <- V V'_pq of the previous p-step on one chunk of rows; these
@@ -155,6 +165,12 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
         }
     }
     if (tid < 2) flags[tid] = 0;
+    if constexpr (SC) {
+        for (int c = tid; c < BW; c += NT) {
+            const int64_t gc = pair_col(c, a.w, pq);
+            ex[c] = gc < a.n ? a.colexp[gc] : 0;
+        }
+    }
     __syncthreads();
 
 
@@ -303,32 +319,49 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
                         rotate = hpq != 0.0 && !(fabs(hpq) <= tol * sqrt(hpp) * sqrt(hqq));
                     // subphase 4: hyperbolic iff kp < n+ <= kq
                     const int t = (HYP && (f & 1)) ? -1 : 1;
+                    // scaled mode: the pair's h in one common scale
+                    int dl = 0, ep = 0, eq = 0;
+                    double sp = hpp, sq = hqq;
+                    if constexpr (SC) {
+                        ep = ex[p];
+                        eq = ex[q];
+                        dl = eq - ep;
+                        sp = ldexp(hpp, -dl);
+                        sq = ldexp(hqq, dl);
+                    }
                     double tn = 0.0, cs = 1.0;
                     bool clamped = false;
                     if (rotate) {
-                        if (mid || (in_fast_range(hpp) && in_fast_range(hqq) && in_fast_range(fabs(hpq))))
-                            rotation_fast(hpp, hqq, hpq, t, tn, cs, clamped);
+                        if ((!SC && mid) ||
+                            (in_fast_range(sp) && in_fast_range(sq) && in_fast_range(fabs(hpq))))
+                            rotation_fast(sp, sq, hpq, t, tn, cs, clamped);
                         else
-                            rotation(hpp, hqq, hpq, t, tn, cs, clamped);
+                            rotation(sp, sq, hpq, t, tn, cs, clamped);
                     }
                     // subphase 5: keep j*sigma^2 non-increasing for trigonometric
                     // pairs (h_pp' = h_pp - tn h_pq, h_qq' = h_qq + tn h_pq)
                     bool swap = false;
                     if (!(f & 3)) {
-                        const double npp = fma(-tn, hpq, hpp);
-                        const double nqq = fma(tn, hpq, hqq);
+                        const double npp = fma(-tn, hpq, sp);
+                        const double nqq = fma(tn, hpq, sq);
                         swap = (!HYP || (f & 4)) ? (npp < nqq) : ((f & 8) ? (npp > nqq) : false);
                     }
                     // subphase 6, (4.1) / (4.2).  cs == 1 multiplies exactly.
                     const double mtn = (t > 0) ? -tn : tn;
                     if (rotate || swap) {
                         const int cp = swap ? q : p, cq = swap ? p : q;
+                        const double mtr = SC ? ldexp(mtn, dl) : mtn;
+                        const double tr = SC ? ldexp(tn, -dl) : tn;
 #pragma unroll
                         for (int r = 0; r < ROWS; ++r) {
-                            const double np = cs * fma(mtn, rq[r], rp[r]);
-                            const double nq = cs * fma(tn, rp[r], rq[r]);
+                            const double np = cs * fma(mtr, rq[r], rp[r]);
+                            const double nq = cs * fma(tr, rp[r], rq[r]);
                             R[cp * LD + x + LN * r] = np;
                             R[cq * LD + x + LN * r] = nq;
+                        }
+                        if (SC && swap && x == 0) {
+                            ex[p] = eq;
+                            ex[q] = ep;
                         }
                     }
                     if (x == 0) {
@@ -411,6 +444,22 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
         atomicAdd(&a.counters[C_INNER_SW], (unsigned long long)sweeps);
         if (r) atomicAdd(&a.counters[C_UPDATES], 1ull);
     }
+    if constexpr (SC) {
+        // exponents of the transformed columns (||g_c|| = ||r_c|| after the
+        // update), written only when the update will run (some rotation)
+        int all = 0;
+#pragma unroll
+        for (int wv = 0; wv < NWAVES; ++wv) all += cnt[wv][0];
+        if (all != 0) {
+            for (int c = tid; c < BW; c += NT) {
+                const int64_t gc = pair_col(c, a.w, pq);
+                double s2 = 0.0;
+                for (int i = 0; i < BW; ++i) s2 = fma(R[c * LD + i], R[c * LD + i], s2);
+                const double nrm = sqrt(s2);
+                if (gc < a.n) a.colexp[gc] = ex[c] + (nrm > 0.0 && nrm <= 0x1p1000 ? ilogb(nrm) : 0);
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -418,16 +467,31 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
 hipError_t launch_inner(int bw, const StepArgs &a, hipStream_t s) {
     const dim3 grid(a.npairs * (1 + a.prev_chunks));
     const bool hyp = a.n_plus < a.n;
-    if (bw == 32) {
-        if (hyp)
-            hipLaunchKernelGGL((inner_kernel<32, true>), grid, dim3(InnerCfg<32>::kThreads), 0, s, a);
-        else
-            hipLaunchKernelGGL((inner_kernel<32, false>), grid, dim3(InnerCfg<32>::kThreads), 0, s, a);
+    const dim3 blk(InnerCfg<32>::kThreads), blk64(InnerCfg<64>::kThreads);
+    if (a.colexp) {
+        if (bw == 32) {
+            if (hyp)
+                hipLaunchKernelGGL((inner_kernel<32, true, true>), grid, blk, 0, s, a);
+            else
+                hipLaunchKernelGGL((inner_kernel<32, false, true>), grid, blk, 0, s, a);
+        } else {
+            if (hyp)
+                hipLaunchKernelGGL((inner_kernel<64, true, true>), grid, blk64, 0, s, a);
+            else
+                hipLaunchKernelGGL((inner_kernel<64, false, true>), grid, blk64, 0, s, a);
+        }
     } else {
-        if (hyp)
-            hipLaunchKernelGGL((inner_kernel<64, true>), grid, dim3(InnerCfg<64>::kThreads), 0, s, a);
-        else
-            hipLaunchKernelGGL((inner_kernel<64, false>), grid, dim3(InnerCfg<64>::kThreads), 0, s, a);
+        if (bw == 32) {
+            if (hyp)
+                hipLaunchKernelGGL((inner_kernel<32, true, false>), grid, blk, 0, s, a);
+            else
+                hipLaunchKernelGGL((inner_kernel<32, false, false>), grid, blk, 0, s, a);
+        } else {
+            if (hyp)
+                hipLaunchKernelGGL((inner_kernel<64, true, false>), grid, blk64, 0, s, a);
+            else
+                hipLaunchKernelGGL((inner_kernel<64, false, false>), grid, blk64, 0, s, a);
+        }
     }
     return hipGetLastError();
 }

@@ -63,6 +63,11 @@ struct StepArgs {
     const int *prev_pair_rot;
     int prev_chunks;
     int prev_rows;      // rows of V per such workgroup
+    // scaled mode (badly scaled input): per column c of G an exponent e_c
+    // with ||g_c|| in [2^e_c, 2^(e_c+1)); the Gram kernel forms
+    // D^-1 H D^-1 (D = diag(2^e_c)), the inner kernel works on R D^-1 and
+    // writes the exponents of the transformed columns.  Null: not scaled.
+    int *colexp;
 };
 
 hipError_t launch_gram(int bw, const StepArgs &a, hipStream_t s);
@@ -152,6 +157,9 @@ hipError_t launch_reset_counters(unsigned long long *c, hipStream_t s);
 hipError_t launch_init_identity(double *V, int64_t ldv, int64_t n, hipStream_t s);
 hipError_t launch_colnorms(const double *G, int64_t ldg, int64_t m, int64_t n, double *s_out,
                            hipStream_t s);
+hipError_t launch_range_init(int *range, hipStream_t s);
+hipError_t launch_colexp(const double *G, int64_t ldg, int64_t m, int64_t n, double *s_out,
+                         int *ex, int *range, hipStream_t s);
 hipError_t launch_rank(const double *s, int64_t n, int64_t n_plus, int *perm, hipStream_t st);
 hipError_t launch_gather_cols(const double *src, int64_t lds, double *dst, int64_t ldd,
                               int64_t rows, int64_t cols, const int *perm, const double *scale,

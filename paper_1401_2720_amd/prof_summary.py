@@ -35,7 +35,7 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 COMMON = ["jsvd_device.h", "jsvd_internal.h"]
 KERNEL_SOURCES = {"gram": ["jsvd_gram.hip"], "inner": ["jsvd_inner.hip", "jsvd_rows.h"],
                   "update": ["jsvd_update.hip", "jsvd_rows.h"]}
-PSTEP = re.compile(r"\b(gram|inner|update)_kernel<(\d+)(?:, (?:true|false))?>")
+PSTEP = re.compile(r"\b(gram|inner|update)_kernel<(\d+)(?:, (?:true|false))*>")
 
 
 def kernel_sources_sha256(kernel):

@@ -1,0 +1,188 @@
+"""GPU parity of the scaled mode (badly scaled input, Section 4.2).
+
+The references come from the oracle on well scaled matrices and relations
+that are exact in binary floating point:
+  * uniform scaling by 2^k: sigma(2^k B) = 2^k sigma(B), same U and V;
+  * column groups B1 2^a and B2 2^b with a - b large: the largest sigma are
+    2^a sigma(B1) and the others 2^b sigma(P B2), P the projector onto the
+    complement of range(B1), both up to a relative 2^(2(b-a)) (negligible
+    here); P B2 is formed from a Householder QR of B1.
+Bars as in the other parity tests, sigma relative 1e-12 on these
+well-conditioned factors; the reconstruction is checked column by column
+(one-sided Jacobi is columnwise backward stable).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1401_2720_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return torch
+
+
+def _jsvd():
+    import paper_1401_2720_amd as jsvd
+    jsvd.lib()
+    return jsvd
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _gesvd(A, **kw):
+    torch = _torch()
+    U, S, V, info = _jsvd().gesvd(torch.from_numpy(np.asfortranarray(A)).cuda(), **kw)
+    torch.cuda.synchronize()
+    return U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy(), info
+
+
+def _orth(X, n):
+    return np.max(np.abs(X.T @ X - np.eye(n)))
+
+
+def _colnorms(X):
+    """Column 2-norms without overflow or underflow: each column scaled by a
+    power of two near its largest magnitude first."""
+    mx = np.max(np.abs(X), axis=0)
+    e = np.where(mx > 0, np.frexp(np.where(mx > 0, mx, 1.0))[1], 0)
+    return np.ldexp(np.linalg.norm(np.ldexp(X, -e[None, :]), axis=0), e)
+
+
+def _badly_scaled(A):
+    """Whether some column norm lies outside [2^-480, 2^481)."""
+    nz = _colnorms(A)
+    nz = nz[nz > 0]
+    return bool(np.any(nz < 2.0 ** -480) or np.any(nz >= 2.0 ** 481))
+
+
+def _aligned(X, Xr, S):
+    n = S.shape[0]
+    worst = 0.0
+    for i in range(n):
+        gap = np.min(np.abs(np.delete(S, i) - S[i])) / S[0] if n > 1 else 1.0
+        if gap < 1e-8:
+            continue
+        sgn = 1.0 if X[:, i] @ Xr[:, i] >= 0 else -1.0
+        worst = max(worst, np.linalg.norm(X[:, i] - sgn * Xr[:, i]) * gap)
+    return worst
+
+
+@pytest.mark.parametrize("k", [700, -700, 0])
+@pytest.mark.parametrize("m,n,w", [(300, 200, 16), (257, 129, 32)])
+def test_uniform_power_of_two_scaling(m, n, w, k):
+    """2^k B against the oracle on B: sigma scales by 2^k exactly, U and V
+    are those of B.  k = 0 forces the scaled mode on a well scaled B."""
+    _say(f"case uniform m={m} n={n} w={w} k={k}")
+    B = inputs.gaussian(m, n, inputs.rng(900 + m + n))
+    A = np.ldexp(B, k)
+    U, S, V, info = _gesvd(A, block_w=w, scaled=("on" if k == 0 else "auto"))
+    assert info["status"] == 0 and info["converged"] == 1, info
+    assert info["scaled"] == 1
+    ref = oracle.gesvj(B)
+    s = np.ldexp(S, -k)
+    assert np.max(np.abs(s - ref["S"]) / ref["S"]) <= 1e-12
+    assert _orth(U, n) <= 1e-13 * n and _orth(V, n) <= 1e-13 * n
+    assert np.linalg.norm(B - (U * s) @ V.T) <= 1e-13 * n * np.linalg.norm(B)
+    assert _aligned(V, ref["V"], ref["S"]) <= 1e-12
+    assert _aligned(U, ref["U"], ref["S"]) <= 1e-12
+
+
+def test_auto_leaves_well_scaled_input_alone():
+    B = inputs.gaussian(200, 160, inputs.rng(930))
+    _, S, _, info = _gesvd(np.ldexp(B, 400), block_w=16)
+    assert info["status"] == 0 and info["scaled"] == 0
+    ref = oracle.gesvj(B)
+    assert np.max(np.abs(np.ldexp(S, -400) - ref["S"]) / ref["S"]) <= 1e-12
+
+
+def test_unscaled_mode_reports_overflow():
+    """Scaled mode off on 2^700 B: the Gram matrices overflow and the solver
+    says so instead of returning numbers."""
+    B = inputs.gaussian(160, 128, inputs.rng(931))
+    _, _, _, info = _gesvd(np.ldexp(B, 700), block_w=16, scaled="off", allow=(1, 3))
+    assert info["scaled"] == 0
+    assert info["status"] == 3, info
+
+
+def _groups(m, n1, n2, a, b, seed):
+    g = inputs.rng(seed)
+    B1 = inputs.gaussian(m, n1, g)
+    B2 = inputs.gaussian(m, n2, g)
+    Q, _ = np.linalg.qr(B1)
+    P2 = B2 - Q @ (Q.T @ B2)
+    P2 = P2 - Q @ (Q.T @ P2)  # second pass: orthogonal to working accuracy
+    s1 = np.ldexp(oracle.gesvj(B1)["S"], a)
+    s2 = np.ldexp(oracle.gesvj(P2)["S"], b)
+    return np.hstack([np.ldexp(B1, a), np.ldexp(B2, b)]), s1, s2
+
+
+@pytest.mark.parametrize("mode", ["auto", "on"])
+@pytest.mark.parametrize("case", [
+    # m, n1, n2, a, b, w, interleave
+    (300, 96, 104, 520, -300, 16, False),
+    (260, 70, 58, 450, -450, 32, False),
+    (240, 64, 64, 300, -500, 16, True),
+], ids=["520_-300_w16", "450_-450_w32_block_straddles", "300_-500_w16_mixed"])
+def test_column_groups_far_apart(case, mode):
+    """Columns 2^a B1 and 2^b B2 with 2^(a-b) up to 2^900.  interleave
+    permutes the columns so that pivot block-pairs hold both scales.  With
+    a = -b = 450 no square leaves the normal range and the automatic choice
+    keeps the unscaled method."""
+    m, n1, n2, a, b, w, mix = case
+    _say(f"case groups m={m} n1={n1} n2={n2} a={a} b={b} w={w} mix={mix}")
+    A, s1, s2 = _groups(m, n1, n2, a, b, 940 + n1)
+    n = n1 + n2
+    if mix:
+        perm = inputs.rng(941).permutation(n)
+        A = np.asfortranarray(A[:, perm])
+    U, S, V, info = _gesvd(A, block_w=w, scaled=mode)
+    assert info["status"] == 0 and info["converged"] == 1, info
+    assert info["scaled"] == (1 if mode == "on" or _badly_scaled(A) else 0)
+    assert np.all(np.isfinite(S)) and np.all(np.diff(S) <= 0)
+    assert np.max(np.abs(S[:n1] - s1) / s1) <= 1e-12
+    assert np.max(np.abs(S[n1:] - s2) / s2) <= 1e-12
+    assert _orth(U, n) <= 1e-13 * n and _orth(V, n) <= 1e-13 * n
+    R = A - (U * S) @ V.T
+    col = _colnorms(R) / _colnorms(A)
+    assert np.max(col) <= 1e-13 * n
+
+
+def test_tall_badly_scaled_skips_qr():
+    """m >= 2n would take the QR preprocessing; badly scaled input goes to
+    the scaled Jacobi method instead."""
+    B = inputs.gaussian(400, 96, inputs.rng(950))
+    U, S, V, info = _gesvd(np.ldexp(B, -650), block_w=16)
+    assert info["status"] == 0 and info["preprocessed"] == 0 and info["scaled"] == 1
+    ref = oracle.gesvj(B)
+    assert np.max(np.abs(np.ldexp(S, 650) - ref["S"]) / ref["S"]) <= 1e-12
+    assert _orth(U, 96) <= 1e-13 * 96 and _orth(V, 96) <= 1e-13 * 96
+
+
+@pytest.mark.parametrize("k", [640, -640])
+def test_hsvd_uniform_scaling(k):
+    """Hyperbolic SVD of 2^k B against the oracle's on B: V^T J V = J is
+    unchanged by the scaling and sigma scales by 2^k."""
+    torch = _torch()
+    jsvd = _jsvd()
+    m, n, npl = 160, 128, 80
+    _say(f"case hsvd m={m} n={n} n_plus={npl} k={k}")
+    B = inputs.gaussian(m, n, inputs.rng(960))
+    J = np.array([1] * npl + [-1] * (n - npl), dtype=np.int8)
+    G = torch.from_numpy(np.asfortranarray(np.ldexp(B, k))).cuda()
+    U, S, V, Jo, info = jsvd.hsvd(G, J, block_w=16)
+    torch.cuda.synchronize()
+    assert info["status"] == 0 and info["converged"] == 1 and info["scaled"] == 1, info
+    S, V = S.cpu().numpy(), V.cpu().numpy()
+    ref = oracle.gesvj(B, n_plus=npl)
+    vn2 = max(1.0, np.linalg.norm(V, 2) ** 2)
+    s = np.ldexp(S, -k)
+    assert np.all(np.abs(s - ref["S"]) <= vn2 * (1e-12 * ref["S"] + 1e-13 * ref["S"].max()))
+    Jd = np.diag(Jo.astype(np.float64))
+    assert np.max(np.abs(V.T @ Jd @ V - Jd)) <= 1e-13 * n * max(1.0, np.max(np.abs(V)) ** 2)
