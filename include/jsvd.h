@@ -106,17 +106,21 @@ typedef struct {
  *   batch_g_groups : of the 32 half waves of a batched workgroup, those that
  *                    rotate G when V is wanted (the others apply the
  *                    rotations to V); 0 = built-in (16), else 4..28.
+ *   batch_block_min_n : batched problems with n >= this run the blocked
+ *                    method (block-columns of 16); 0 = built-in, 33..257
+ *                    (257: no problem is blocked).
  */
 typedef struct {
     int32_t count;
     int64_t n_upper[8];
     int32_t block_w[8];
     int32_t batch_g_groups;
+    int32_t batch_block_min_n;
 } jsvd_tuning;
 
 /* Install (tuning != NULL, copied) or remove (NULL) the tuned choices of a
- * handle: they decide w when opts->block_w == 0 and the batched kernel's
- * split.  Returns JSVD_OK, -1 if h is NULL, -2 for an invalid table. */
+ * handle: they decide w when opts->block_w == 0, the batched kernel's
+ * split and which batched problems are blocked.  Returns JSVD_OK, -1 if h is NULL, -2 for an invalid table. */
 int jsvd_set_tuning(jsvd_handle_t h, const jsvd_tuning *tuning);
 
 /* Fill *opts with the defaults listed above.  Returns JSVD_OK, or -1 if

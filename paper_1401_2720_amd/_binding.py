@@ -40,7 +40,7 @@ class Info(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("count", _i32), ("n_upper", _i64 * 8), ("block_w", _i32 * 8),
-                ("batch_g_groups", _i32)]
+                ("batch_g_groups", _i32), ("batch_block_min_n", _i32)]
 
 
 TUNING_PATH = os.path.join(HERE, "tuning.json")
@@ -124,7 +124,8 @@ def _handle(device_index, stream_ptr):
 
 def tuning_struct(table):
     """The jsvd_tuning of a table {"n_upper": [...], "block_w": [...],
-    "batch_g_groups": int} (raises ValueError if it cannot be one)."""
+    "batch_g_groups": int, "batch_block_min_n": int} (raises ValueError if it
+    cannot be one)."""
     nu, bw = list(table.get("n_upper", [])), list(table.get("block_w", []))
     if len(nu) != len(bw) or len(nu) > 8:
         raise ValueError("n_upper and block_w must have the same length, at most 8")
@@ -134,6 +135,7 @@ def tuning_struct(table):
         t.n_upper[i] = int(a)
         t.block_w[i] = int(b)
     t.batch_g_groups = int(table.get("batch_g_groups", 0))
+    t.batch_block_min_n = int(table.get("batch_block_min_n", 0))
     return t
 
 

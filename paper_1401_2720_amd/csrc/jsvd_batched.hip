@@ -239,6 +239,363 @@ __device__ int pointwise_sweeps(double *Gw, double *Vw, int m, int n, int N,
     return sweeps;
 }
 
+
+// ---------------------------------------------------------------- blocked
+// Problems with many columns take the two-level method of the dense path
+// inside their workgroup: block-columns of kBlkW columns, the closest
+// parallel strategy of order nb on the blocks, and for every pivot
+// block-pair the Gram matrix (2.7), its Cholesky factor R (Section 4.1),
+// one sweep of the pointwise method on R accumulating V' (Section 4.3,
+// block-oriented) and [G_p G_q] V', [V_p V_q] V' (2.9), skipped when the
+// pair did not rotate (Section 4.4).  A pair whose Gram matrix already
+// passes the relative orthogonality test everywhere is left alone.  Up to
+// kBlkPairs pivot pairs are in flight: four waves per pair form the Gram
+// matrix (rows split, FP64 MFMA) and apply V' (FP64 MFMA), one wave per pair
+// factors it, and 16 lanes per pivot pair of R run the inner sweep.  G and V
+// stay in their global buffers; R and V' live in LDS.
+constexpr int kBlkW = 16, kBlkBW = 2 * kBlkW, kBlkLD = kBlkBW + 1, kBlkPairs = 4;
+constexpr int kBlkMat = kBlkBW * kBlkLD;  // doubles of one R or V'
+
+// X[r0:r1, cols of pq] <- X[r0:r1, cols of pq] V' for the rows of one wave
+// (16-row slices from r0 + 16 sub, stride 16 nsub), V' row-major in LDS
+// with leading dimension kBlkLD.  All loads of a slice precede its stores.
+__device__ __forceinline__ void blk_rows_update(double *X, int ldx, int rows, int2 pq, int n,
+                                                const double *vs, int sub, int nsub) {
+    constexpr int KS = kBlkBW / 4;
+    const int lane = threadIdx.x & 63, i16 = lane & 15, grp = lane >> 4;
+    for (int base = 16 * sub; base < rows; base += 16 * nsub) {
+        // V' is re-read from LDS in every slice rather than held in registers
+        asm volatile("" ::: "memory");
+        const int row = base + i16;
+        const bool rv = row < rows;
+        double bx[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int gc = (int)pair_col(4 * ks + grp, kBlkW, pq);
+            bx[ks] = (rv && gc < n) ? X[gc * ldx + row] : 0.0;
+        }
+#pragma unroll
+        for (int jt = 0; jt < kBlkBW / 16; ++jt) {
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                acc = mfma16(vs[(4 * ks + grp) * kBlkLD + jt * 16 + i16], bx[ks], acc);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gc = (int)pair_col(jt * 16 + grp + 4 * v, kBlkW, pq);
+                if (rv && gc < n) X[gc * ldx + row] = acc[v];
+            }
+        }
+    }
+}
+
+// The sweep loop of the blocked method on one problem (G: m x n, ld m; V:
+// n x n, ld n, identity on entry, or null).  lds holds kBlkLdsDoubles.
+// Returns the sweeps performed, plus kBlkConverged when a sweep performed
+// no proper rotation and kBlkNonfinite when a Cholesky pivot was NaN or
+// infinite.
+constexpr int kBlkLdsDoubles = 2 * kBlkPairs * kBlkMat + kBlkPairs * 3 * 4 * 64 + kBlkPairs * 2 * kBlkBW;
+static_assert(kBlkLdsDoubles == kBatchBlockLds, "host LDS bound of the blocked method");
+
+constexpr int kBlkConverged = 1 << 16, kBlkNonfinite = 1 << 17;
+
+__device__ __forceinline__ int blocked_sweeps(double *G, double *V, int m, int n, int max_sweeps,
+                                              const int *tbl_order, const int64_t *tbl_off,
+                                              const unsigned char *tbls, double *lds) {
+    __shared__ int2 s_pq[kBlkPairs];
+    __shared__ int s_need[kBlkPairs], s_rotk[kBlkPairs], s_prop, s_bad;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i16 = lane & 15, grp = lane >> 4;
+    const int nb = (n + kBlkW - 1) / kBlkW;
+    const int NB = tbl_order[nb];
+    const unsigned char *btbl = tbls + tbl_off[NB >> 1];
+    const unsigned char *itbl = tbls + tbl_off[kBlkBW >> 1];
+    const double tol = kEps * sqrt((double)kBlkBW);  // c(eps) at the inner level, n^ = 2w
+    double *Rm = lds, *Vm = lds + kBlkPairs * kBlkMat, *red = lds + 2 * kBlkPairs * kBlkMat;
+    double *rowbuf = red + kBlkPairs * 3 * 4 * 64;  // pivot rows of the Cholesky, 2 per pair
+    const int wk = wave >> 2, sub = wave & 3;  // pair and quarter of a wave's Gram / update work
+
+    int sweeps = 0, result = 0;
+    if (tid == 0) s_bad = 0;
+    while (sweeps < max_sweeps) {
+        if (tid == 0) s_prop = 0;
+        int prop = 0;  // proper rotations of this lane's pivot pairs (lanes x == 0)
+        for (int st = 0; st < NB - 1; ++st) {
+            const unsigned char *row = btbl + (size_t)st * NB;
+            int slot = 0;
+            for (;;) {
+                // the next pivot pairs of the step with a block inside the
+                // problem (the same walk in every thread)
+                __syncthreads();  // the previous group is done with s_pq, s_rotk
+                int npg = 0;
+                while (slot < NB / 2 && npg < kBlkPairs) {
+                    const int p = row[2 * slot], q = row[2 * slot + 1];
+                    ++slot;
+                    if (p < nb || q < nb) {
+                        if (tid == 0) s_pq[npg] = make_int2(p, q);
+                        ++npg;
+                    }
+                }
+                if (npg == 0) break;
+                if (tid < kBlkPairs) s_need[tid] = s_rotk[tid] = 0;
+                __syncthreads();
+
+                // (1) Gram matrices: each wave sums its 16-row slices; the four
+                // partial sums of a pair are added in wave order.
+                d4 acc[3];
+#pragma unroll
+                for (int t = 0; t < 3; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+                int2 pq = make_int2(0, 0);
+                bool valid[2] = {false, false};
+                if (wk < npg) {
+                    pq = s_pq[wk];
+                    const double *col[2];
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        const int64_t gc = pair_col(16 * t + i16, kBlkW, pq);
+                        valid[t] = gc < n;
+                        col[t] = G + (valid[t] ? gc : 0) * m;
+                    }
+                    for (int base = 16 * sub; base < m; base += 64) {
+                        const int rb = base + 4 * grp;
+                        double x[2][4];
+#pragma unroll
+                        for (int t = 0; t < 2; ++t)
+#pragma unroll
+                            for (int s2 = 0; s2 < 4; ++s2)
+                                x[t][s2] = (valid[t] && rb + s2 < m) ? col[t][rb + s2] : 0.0;
+#pragma unroll
+                        for (int s2 = 0; s2 < 4; ++s2) {
+                            acc[0] = mfma16(x[0][s2], x[0][s2], acc[0]);
+                            acc[1] = mfma16(x[0][s2], x[1][s2], acc[1]);
+                            acc[2] = mfma16(x[1][s2], x[1][s2], acc[2]);
+                        }
+                    }
+                }
+                for (int wv = 0; wv < 4; ++wv) {
+                    if (wk < npg && sub == wv) {
+                        double *Rk = Rm + wk * kBlkMat;
+#pragma unroll
+                        for (int t = 0; t < 3; ++t)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                double *r = red + ((wk * 3 + t) * 4 + v) * 64 + lane;
+                                const double h = (wv == 0) ? acc[t][v] : *r + acc[t][v];
+                                if (wv < 3) {
+                                    *r = h;
+                                } else {
+                                    // tile t: (0,0), (0,1), (1,1); entry (i, j) of H, both
+                                    // triangles; padding columns become unit vectors
+                                    const int i = (t == 2 ? 16 : 0) + grp + 4 * v;
+                                    const int j = (t == 0 ? 0 : 16) + i16;
+                                    const bool ok = pair_col(i, kBlkW, pq) < n && pair_col(j, kBlkW, pq) < n;
+                                    const double hv = ok ? h : (i == j ? 1.0 : 0.0);
+                                    Rk[j * kBlkLD + i] = hv;
+                                    Rk[i * kBlkLD + j] = hv;
+                                }
+                            }
+                    }
+                    __syncthreads();
+                }
+
+                // (2) which pairs need the inner sweep: some (i, j) fails the
+                // relative orthogonality test on H (reading: <= passes)
+#pragma unroll
+                for (int u = 0; u < kBlkPairs; ++u) {
+                    bool need = false;
+                    if (u < npg) {
+                        const double *Rk = Rm + u * kBlkMat;
+                        const int i = tid & 31, j = tid >> 5;
+                        if (i < j) {
+                            const double hij = Rk[j * kBlkLD + i];
+                            const double hii = Rk[i * kBlkLD + i], hjj = Rk[j * kBlkLD + j];
+                            need = hij != 0.0 && !(fabs(hij) <= tol * sqrt(hii) * sqrt(hjj));
+                        }
+                    }
+                    if (__ballot(need) != 0ull && lane == 0) atomicOr(&s_need[u], 1);
+                }
+                __syncthreads();
+                int any = 0;
+#pragma unroll
+                for (int u = 0; u < kBlkPairs; ++u) any |= (u < npg) ? s_need[u] : 0;
+                if (!any) continue;
+
+                // (3) Cholesky H = R^T R (right-looking, unpivoted; Section 4.1):
+                // 256 threads per pair, four entries each in registers; the
+                // pivot row goes through LDS (double-buffered, one barrier per
+                // step).  Row k of R is H's row k (as updated) times 1/sqrt(h_kk);
+                // a pivot that is not positive makes row k zero, a NaN or
+                // infinite one ends the problem.
+                {
+                    const int k = tid >> 8, ll = tid & 255, ci = ll & 31, cj = ll >> 5;
+                    const bool act = k < npg && s_need[k];
+                    double *Rk = Rm + k * kBlkMat, *rb = rowbuf + k * 2 * kBlkBW;
+                    double h[4], fin[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        h[u] = act ? Rk[(cj + 8 * u) * kBlkLD + ci] : 0.0;
+                        fin[u] = 0.0;
+                    }
+                    int bad_met = 0;
+                    for (int kk = 0; kk < kBlkBW; ++kk) {
+                        double *rk = rb + (kk & 1) * kBlkBW;
+                        if (act && ci == kk) {
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) rk[cj + 8 * u] = h[u];
+                        }
+                        __syncthreads();
+                        if (act && ci >= kk) {
+                            const double hkk = rk[kk];
+                            const bool bad = !(fabs(hkk) <= 0x1.fffffffffffffp+1023);
+                            const bool pos = !bad && hkk > 0.0;
+                            bad_met |= bad ? 1 : 0;
+                            double rs, d;
+                            rsqrt_sqrt(pos ? hkk : 1.0, rs, d);
+                            const double ri = rk[ci] * rs;
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int j = cj + 8 * u;
+                                if (ci == kk) {
+                                    fin[u] = (!pos || j < kk) ? 0.0 : (j == kk ? d : h[u] * rs);
+                                } else if (pos && j >= ci) {
+                                    h[u] = fma(-ri, rk[j] * rs, h[u]);
+                                }
+                            }
+                        }
+                    }
+                    if (act) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) Rk[(cj + 8 * u) * kBlkLD + ci] = fin[u];
+                    }
+                    if (bad_met) s_bad = 1;
+                }
+                for (int e = tid; e < kBlkPairs * kBlkBW * kBlkBW; e += kBatchThreads) {
+                    const int k = e / (kBlkBW * kBlkBW), r = e % kBlkBW, c = (e / kBlkBW) % kBlkBW;
+                    Vm[k * kBlkMat + r * kBlkLD + c] = (r == c) ? 1.0 : 0.0;
+                }
+                __syncthreads();
+
+                // (4) one inner sweep on R, 16 lanes per pivot pair (rows x and
+                // x + 16), V' row-major
+                {
+                    const int gid = tid >> 4, k = gid >> 4, slot2 = gid & 15, x = tid & 15;
+                    const bool act = k < npg && s_need[k];
+                    double *Rk = Rm + k * kBlkMat, *Vk = Vm + k * kBlkMat;
+                    for (int st2 = 0; st2 < kBlkBW - 1; ++st2) {
+                        if (act) {
+                            const int p = itbl[st2 * kBlkBW + 2 * slot2];
+                            const int q = itbl[st2 * kBlkBW + 2 * slot2 + 1];
+                            double *rp = Rk + p * kBlkLD, *rq = Rk + q * kBlkLD;
+                            const double a0 = rp[x], a1 = rp[x + 16], b0 = rq[x], b1 = rq[x + 16];
+                            const double hpp = row_sum(fma(a0, a0, a1 * a1));
+                            const double hqq = row_sum(fma(b0, b0, b1 * b1));
+                            const double hpq = row_sum(fma(a0, b0, a1 * b1));
+                            double tn = 0.0, cs = 0.0;
+                            if (trig_pair(hpp, hqq, hpq, tol, tn, cs)) {
+                                rp[x] = cs * fma(-tn, b0, a0);
+                                rq[x] = cs * fma(tn, a0, b0);
+                                rp[x + 16] = cs * fma(-tn, b1, a1);
+                                rq[x + 16] = cs * fma(tn, a1, b1);
+                                double *v0 = Vk + x * kBlkLD, *v1 = Vk + (x + 16) * kBlkLD;
+                                const double c0 = v0[p], d0 = v0[q], c1 = v1[p], d1 = v1[q];
+                                v0[p] = cs * fma(-tn, d0, c0);
+                                v0[q] = cs * fma(tn, c0, d0);
+                                v1[p] = cs * fma(-tn, d1, c1);
+                                v1[q] = cs * fma(tn, c1, d1);
+                                if (x == 0) {
+                                    atomicAdd(&s_rotk[k], 1);
+                                    prop += cs != 1.0 ? 1 : 0;
+                                }
+                            }
+                        }
+                        __syncthreads();
+                    }
+                }
+
+                // (5) [G_p G_q] V' and [V_p V_q] V' for the pairs that rotated
+                if (wk < npg && s_rotk[wk] > 0) {
+                    const double *vs = Vm + wk * kBlkMat;
+                    blk_rows_update(G, m, m, pq, n, vs, sub, 4);
+                    if (V) blk_rows_update(V, n, n, pq, n, vs, sub, 4);
+                }
+            }
+        }
+        if (prop) atomicAdd(&s_prop, prop);
+        __syncthreads();
+        const int all = s_prop, bad = s_bad;
+        ++sweeps;
+        __syncthreads();
+        if (bad) {
+            result = kBlkNonfinite;
+            break;
+        }
+        if (all == 0) {
+            result = kBlkConverged;
+            break;
+        }
+    }
+    return sweeps | result;
+}
+
+// The end of a problem: sigma_j = ||g_j||, the output order (non-increasing,
+// ties by index, NaN last), U = G Sigma^{-1} and V in that order, status
+// and sweeps.  Gw / Vw are the working copies (LDS or the global buffers;
+// in_lds / v_lds say which), G / V the global buffers.
+__device__ __forceinline__ void finish_problem(const BatchArgs &b, int id, int m, int n, double *G,
+                                               double *V, const double *Gw, const double *Vw,
+                                               bool in_lds, bool v_lds, double *scratch,
+                                               int sweeps, int status, double *s_sig,
+                                               int *s_perm) {
+    const int tid = threadIdx.x, x = tid & 31, group = tid >> 5;
+    for (int j = group; j < n; j += kGroups) {
+        const double *g = Gw + (size_t)j * m;
+        double sacc = 0.0;
+        for (int i = x; i < m; i += 32) sacc = fma(g[i], g[i], sacc);
+        sacc = hw_sum(sacc);
+        if (x == 0) s_sig[j] = sqrt(sacc);
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += kBatchThreads) {
+        const double kj = s_sig[j] != s_sig[j] ? -INFINITY : s_sig[j];
+        int r = 0;
+        for (int i = 0; i < n; ++i) {
+            const double ki = s_sig[i] != s_sig[i] ? -INFINITY : s_sig[i];
+            r += (ki > kj || (ki == kj && i < j)) ? 1 : 0;
+        }
+        s_perm[r] = j;
+    }
+    const double *src = Gw;
+    if (!in_lds) {
+        for (int e = tid; e < m * n; e += kBatchThreads) scratch[e] = G[e];
+        src = scratch;
+    }
+    const double *vsrc = Vw;
+    if (V && !v_lds) {
+        for (int e = tid; e < n * n; e += kBatchThreads) scratch[(size_t)m * n + e] = V[e];
+        vsrc = scratch + (size_t)m * n;
+    }
+    __syncthreads();
+    double *S = b.S + b.s_off[id];
+    for (int e = tid; e < m * n; e += kBatchThreads) {
+        const int k = e / m, i = e % m, c = s_perm[k];
+        const double sg = s_sig[c];
+        G[e] = sg > 0.0 ? src[(size_t)c * m + i] / sg : 0.0;
+    }
+    if (V)
+        for (int e = tid; e < n * n; e += kBatchThreads) {
+            const int k = e / n, i = e % n;
+            V[e] = vsrc[(size_t)s_perm[k] * n + i];
+        }
+    for (int k = tid; k < n; k += kBatchThreads) S[k] = s_sig[s_perm[k]];
+    if (tid == 0) {
+        if (b.status) b.status[id] = status;
+        if (b.sweeps) b.sweeps[id] = sweeps;
+    }
+    __syncthreads();
+}
+
+// Problems at positions [queue[2], count) of the work order: the pointwise
+// method, G in LDS when it fits, V in what LDS is left.
 __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs b) {
     extern __shared__ double lds_g[];  // working copy of G when it fits
     __shared__ int s_item;
@@ -247,12 +604,11 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs b) {
     __shared__ int s_perm[kBatchMaxN];
     __shared__ double s_tn[2][kBatchMaxN / 2];  // published rotations, by p-step parity
     __shared__ double s_cs[2][kBatchMaxN / 2];
-    const int tid = threadIdx.x, x = tid & 31;
-    const int group = tid >> 5;  // half wave
+    const int tid = threadIdx.x;
     double *scratch = b.scratch + (size_t)blockIdx.x * b.scratch_per_wg;
 
     for (;;) {
-        if (tid == 0) s_item = atomicAdd(b.queue, 1);
+        if (tid == 0) s_item = atomicAdd(&b.queue[1], 1);
         __syncthreads();
         const int item = s_item;
         __syncthreads();
@@ -264,7 +620,6 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs b) {
         const int N = b.tbl_order[n];
         const unsigned char *tbl = b.tbls + b.tbl_off[N >> 1];
         const double tol = kEps * sqrt((double)m);  // c(eps) = eps sqrt(m)
-        // G in LDS when it fits, then V in what is left
         const bool in_lds = (int64_t)m * n <= b.lds_doubles;
         const int64_t v_at = in_lds ? (int64_t)m * n : 0;
         const bool v_lds = V && v_at + (int64_t)n * n <= b.lds_doubles;
@@ -289,53 +644,42 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs b) {
             sweeps = pointwise_sweeps<6, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged);
         else
             sweeps = pointwise_sweeps<0, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged);
+        finish_problem(b, id, m, n, G, V, Gw, Vw, in_lds, v_lds, scratch, sweeps,
+                       converged ? 0 : JSVD_NOT_CONVERGED, s_sig, s_perm);
+    }
+}
 
-        // sigma_j = ||g_j||, output order, U = G Sigma^{-1}, V permuted
-        for (int j = group; j < n; j += kGroups) {
-            const double *g = Gw + (size_t)j * m;
-            double sacc = 0.0;
-            for (int i = x; i < m; i += 32) sacc = fma(g[i], g[i], sacc);
-            sacc = hw_sum(sacc);
-            if (x == 0) s_sig[j] = sqrt(sacc);
-        }
+// Problems at positions [0, queue[2]) of the work order (the largest, n >=
+// blk_min_n): the blocked method, G and V in their global buffers.  A
+// kernel of its own so that its registers are allocated apart from the
+// pointwise method's.
+__global__ __launch_bounds__(kBatchThreads) void batched_blocked_kernel(BatchArgs b) {
+    extern __shared__ double lds_g[];  // R, V' and the Gram reduction of the pivot pairs
+    __shared__ int s_item;
+    __shared__ double s_sig[kBatchMaxN];
+    __shared__ int s_perm[kBatchMaxN];
+    const int tid = threadIdx.x;
+    double *scratch = b.scratch + (size_t)blockIdx.x * b.scratch_per_wg;
+    const int nblk = b.queue[2];
+
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(&b.queue[0], 1);
         __syncthreads();
-        for (int j = tid; j < n; j += kBatchThreads) {
-            const double kj = s_sig[j] != s_sig[j] ? -INFINITY : s_sig[j];
-            int r = 0;
-            for (int i = 0; i < n; ++i) {
-                const double ki = s_sig[i] != s_sig[i] ? -INFINITY : s_sig[i];
-                r += (ki > kj || (ki == kj && i < j)) ? 1 : 0;
-            }
-            s_perm[r] = j;
-        }
-        const double *src = Gw;
-        if (!in_lds) {
-            for (int e = tid; e < m * n; e += kBatchThreads) scratch[e] = G[e];
-            src = scratch;
-        }
-        const double *vsrc = Vw;
-        if (V && !v_lds) {
-            for (int e = tid; e < n * n; e += kBatchThreads) scratch[(size_t)m * n + e] = V[e];
-            vsrc = scratch + (size_t)m * n;
-        }
+        const int item = s_item;
         __syncthreads();
-        double *S = b.S + b.s_off[id];
-        for (int e = tid; e < m * n; e += kBatchThreads) {
-            const int k = e / m, i = e % m, c = s_perm[k];
-            const double sg = s_sig[c];
-            G[e] = sg > 0.0 ? src[(size_t)c * m + i] / sg : 0.0;
-        }
+        if (item >= nblk) break;
+        const int id = b.order[item];
+        const int m = b.m[id], n = b.n[id];
+        double *G = b.A + b.a_off[id];
+        double *V = b.V ? b.V + b.v_off[id] : nullptr;
         if (V)
-            for (int e = tid; e < n * n; e += kBatchThreads) {
-                const int k = e / n, i = e % n;
-                V[e] = vsrc[(size_t)s_perm[k] * n + i];
-            }
-        for (int k = tid; k < n; k += kBatchThreads) S[k] = s_sig[s_perm[k]];
-        if (tid == 0) {
-            if (b.status) b.status[id] = converged ? 0 : JSVD_NOT_CONVERGED;
-            if (b.sweeps) b.sweeps[id] = sweeps;
-        }
+            for (int e = tid; e < n * n; e += kBatchThreads) V[e] = (e % n == e / n) ? 1.0 : 0.0;
         __syncthreads();
+        const int r = blocked_sweeps(G, V, m, n, b.max_sweeps, b.tbl_order, b.tbl_off, b.tbls, lds_g);
+        const int status = (r & kBlkNonfinite) ? JSVD_NONFINITE
+                           : (r & kBlkConverged) ? 0 : JSVD_NOT_CONVERGED;
+        finish_problem(b, id, m, n, G, V, G, V, false, false, scratch, r & 0xffff, status, s_sig,
+                       s_perm);
     }
 }
 
@@ -345,16 +689,20 @@ __global__ void batch_count_kernel(const int32_t *n, int64_t count, int *hist) {
     if (i < count) atomicAdd(&hist[n[i]], 1);
 }
 
-__global__ void batch_scan_kernel(int *hist, int max_n, int *queue) {
-    // one thread: bucket start positions, largest n first
+__global__ void batch_scan_kernel(int *hist, int max_n, int blk_min_n, int *queue) {
+    // one thread: bucket start positions, largest n first; the problems with
+    // n >= blk_min_n (blk_min_n > 0) come first and go to the blocked kernel
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int pos = 0;
+        int pos = 0, nblk = 0;
         for (int v = max_n; v >= 0; --v) {
             const int c = hist[v];
             hist[v] = pos;
             pos += c;
+            if (blk_min_n > 0 && v >= blk_min_n) nblk = pos;
         }
-        *queue = 0;
+        queue[0] = 0;     // next blocked problem
+        queue[1] = nblk;  // next pointwise problem
+        queue[2] = nblk;  // number of blocked problems
     }
 }
 
@@ -370,8 +718,13 @@ __global__ void batch_zero_kernel(int *p, int count) {
 }  // namespace
 
 hipError_t batched_set_lds(int bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&batched_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&batched_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess && bytes >= kBlkLdsDoubles * (int)sizeof(double))
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&batched_blocked_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kBlkLdsDoubles * (int)sizeof(double));
+    return e;
 }
 
 hipError_t launch_batched(const BatchArgs &b, int grid, int max_n, int *hist, int32_t *order,
@@ -379,9 +732,13 @@ hipError_t launch_batched(const BatchArgs &b, int grid, int max_n, int *hist, in
     hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(256), 0, s, hist, max_n + 1);
     const unsigned blocks = (unsigned)((b.count + 255) / 256);
     hipLaunchKernelGGL(batch_count_kernel, dim3(blocks), dim3(256), 0, s, b.n, b.count, hist);
-    hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(64), 0, s, hist, max_n, b.queue);
+    hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(64), 0, s, hist, max_n, b.blk_min_n,
+                       b.queue);
     hipLaunchKernelGGL(batch_place_kernel, dim3(blocks), dim3(256), 0, s, b.n, b.count, hist,
                        order);
+    if (b.blk_min_n > 0 && max_n >= b.blk_min_n)
+        hipLaunchKernelGGL(batched_blocked_kernel, dim3(grid), dim3(kBatchThreads),
+                           (unsigned)(kBlkLdsDoubles * sizeof(double)), s, b);
     hipLaunchKernelGGL(batched_kernel, dim3(grid), dim3(kBatchThreads),
                        (unsigned)(b.lds_doubles * sizeof(double)), s, b);
     return hipGetLastError();

@@ -629,6 +629,8 @@ int jsvd_set_tuning(jsvd_handle_t h, const jsvd_tuning *t) {
         if (i > 0 && t->n_upper[i] <= t->n_upper[i - 1]) return -2;
     }
     if (t->batch_g_groups != 0 && (t->batch_g_groups < 4 || t->batch_g_groups > 28)) return -2;
+    if (t->batch_block_min_n != 0 && (t->batch_block_min_n < 33 || t->batch_block_min_n > 257))
+        return -2;
     h->tuning = *t;
     return JSVD_OK;
 }
@@ -822,6 +824,12 @@ int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t ma
     b.sweeps = sweeps;
     b.lds_doubles = h->batch_lds / (int64_t)sizeof(double);
     b.g_groups = h->tuning.batch_g_groups ? h->tuning.batch_g_groups : 16;
+    {
+        const int mn = h->tuning.batch_block_min_n ? h->tuning.batch_block_min_n
+                                                   : kBatchBlockMinN;
+        const bool room = b.lds_doubles >= kBatchBlockLds;
+        b.blk_min_n = (room && mn <= kBatchMaxN) ? mn : 0;
+    }
     HIP_TRY(launch_batched(b, grid, max_n, reinterpret_cast<int *>(ws + off_hist),
                            reinterpret_cast<int32_t *>(ws + off_order), st));
     return JSVD_OK;

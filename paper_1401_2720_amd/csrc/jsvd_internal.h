@@ -76,6 +76,8 @@ hipError_t launch_update(int bw, const StepArgs &a, hipStream_t s);
 
 // ------------------------------------------------------ batched small SVDs
 constexpr int kBatchMaxN = 256;  // largest n of a problem in the batched path
+constexpr int kBatchBlockMinN = 65;     // built-in: batched problems with n >= this are blocked
+constexpr int kBatchBlockLds = 11776;   // doubles of LDS the blocked method needs
 
 struct BatchArgs {
     int64_t count;
@@ -83,7 +85,7 @@ struct BatchArgs {
     const int64_t *a_off, *s_off, *v_off;       // device, element offsets
     double *A, *S, *V;                          // V may be null
     const int32_t *order;                       // device, work order (by non-increasing n)
-    int *queue;                                 // device work counter
+    int *queue;                                 // device: next blocked, next pointwise, blocked count
     const int *tbl_order;                       // device [kBatchMaxN + 1]: strategy order for n
     const int64_t *tbl_off;                     // device: offset of the order-N table at [N/2]
     const unsigned char *tbls;                  // device: concatenated zero-based pair tables
@@ -93,6 +95,7 @@ struct BatchArgs {
     int32_t *status, *sweeps;                   // device, per problem (may be null)
     int64_t lds_doubles;                        // problems with m n <= this work in LDS
     int g_groups;                               // half waves rotating G when V is wanted (of 32)
+    int blk_min_n;                              // problems with n >= this are blocked (0: none)
 };
 
 hipError_t batched_set_lds(int bytes);

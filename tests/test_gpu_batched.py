@@ -118,3 +118,85 @@ def test_batched_full_workload_sampled():
     for i, ref in zip(pick, refs):
         U, Si, V = b.results(int(i))
         _check(mats[i], U, Si, V, ref)
+
+
+def _large_batch(seed=33):
+    """Sizes around the blocking threshold and the block width (16): n not a
+    multiple of 16, odd block counts (a padding block), n = 256 (the largest),
+    m = n .. n + 64, graded spectra, and dependent columns (a zero column and
+    a repeated one: semidefinite Gram matrices, zero Cholesky pivots)."""
+    g = np.random.default_rng(seed)
+    mats = []
+    for n in (33, 47, 48, 64, 65, 80, 97, 113, 128, 144, 160, 193, 256):
+        for extra in (0, 17, 64):
+            mats.append(inputs.gaussian(n + extra, n, g))
+        mats.append(inputs.prescribed(n + 5, n, inputs.logspaced(n, -8.0), g))
+    A = inputs.gaussian(120, 100, g)
+    A[:, 7] = 0.0
+    A[:, 50] = A[:, 3]
+    mats.append(A)
+    return mats
+
+
+def _with_block_threshold(dev, min_n):
+    import paper_1401_2720_amd._binding as B
+    base = B.load_tuning(dev)
+    table = dict(base) if base else {"n_upper": [], "block_w": []}
+    table["batch_block_min_n"] = min_n
+    B.set_tuning(dev, table)
+    return base
+
+
+@pytest.mark.parametrize("min_n", [33, 0, 257], ids=["all_blocked", "default", "none_blocked"])
+def test_batched_blocked_matches_oracle(min_n):
+    """The blocked method (block-columns of 16, one inner sweep per pivot
+    pair) against the oracle, with every problem of n >= 33 blocked, the
+    built-in threshold, and blocking off."""
+    torch = _torch()
+    import paper_1401_2720_amd as jsvd
+    import paper_1401_2720_amd._binding as B
+    mats = _large_batch()
+    dev = torch.cuda.current_device()
+    print(f"batched blocked parity: min_n={min_n}, {len(mats)} problems", flush=True)
+    base = _with_block_threshold(dev, min_n)
+    try:
+        b = jsvd.Batch(mats)
+        jsvd.gesvd_batched(b)
+        torch.cuda.synchronize()
+    finally:
+        B.set_tuning(dev, base)
+    assert int(b.status.abs().sum()) == 0
+    refs = oracle.gesvj_many(mats)
+    for i, (A, ref) in enumerate(zip(mats[:-1], refs[:-1])):
+        U, S, V = b.results(i)
+        _check(A, U, S, V, ref)
+    # dependent columns: two zero singular values
+    A, ref = mats[-1], refs[-1]
+    U, S, V = b.results(len(mats) - 1)
+    n = A.shape[1]
+    assert np.all(np.abs(S - ref["S"]) <= 1e-12 * ref["S"] + 1e-13 * ref["S"][0])
+    assert S[-1] <= 1e-13 * S[0] and S[-2] <= 1e-13 * S[0] and S[-3] > 1e-3 * S[0]
+    assert np.max(np.abs(V.T @ V - np.eye(n))) <= 1e-13 * n
+    big = S > 1e-8 * S[0]
+    Ub = U[:, big]
+    assert np.max(np.abs(Ub.T @ Ub - np.eye(Ub.shape[1]))) <= 1e-13 * n
+    assert np.linalg.norm(A - (U * S) @ V.T) <= 1e-13 * n * np.linalg.norm(A)
+
+
+def test_batched_blocked_nonfinite_input():
+    """A NaN in a blocked problem ends that problem with JSVD_NONFINITE; the
+    other problems of the batch are unaffected."""
+    torch = _torch()
+    import paper_1401_2720_amd as jsvd
+    g = np.random.default_rng(34)
+    mats = [inputs.gaussian(100, 96, g), inputs.gaussian(90, 80, g), inputs.gaussian(40, 30, g)]
+    mats[0][5, 40] = np.nan
+    b = jsvd.Batch(mats)
+    jsvd.gesvd_batched(b)
+    torch.cuda.synchronize()
+    st = b.status.cpu().numpy()
+    assert st[0] == 3 and st[1] == 0 and st[2] == 0, st
+    refs = oracle.gesvj_many(mats[1:])
+    for i, ref in zip((1, 2), refs):
+        U, S, V = b.results(i)
+        _check(mats[i], U, S, V, ref)
