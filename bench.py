@@ -147,8 +147,20 @@ def bench_batched(args):
     sw = b.sweeps.cpu().numpy().astype(np.float64)
     m = b.m_host.astype(np.float64)
     n = b.n_host.astype(np.float64)
-    # algorithmic flops: per sweep n(n-1)/2 pairs x (dots 6m + rotation of G and V 6(m+n))
-    flops = float(np.sum(sw * n * (n - 1) / 2 * (6 * m + 6 * (m + n))))
+    # algorithmic flops of the method each problem takes, per sweep:
+    # pointwise: n(n-1)/2 pairs x (dots 6m + rotation of G and V 6(m+n));
+    # blocked (block-columns of w = 16, nb = ceil(n/16), nb(nb-1)/2 pivot
+    # pairs of 2w = 32 columns): per pair the Gram matrix 2w(2w+1)m, the
+    # Cholesky (2w)^3/3, one inner sweep of 2w(2w-1)/2 pairs x (dots 6(2w)
+    # + rotation of R and V' 6(4w)), and G and V times V' 2(m+n)(2w)^2
+    blk = n >= jsvd.batched_block_min_n()
+    w2 = 32.0
+    nb = np.ceil(n / 16.0)
+    per_pair = (w2 * (w2 + 1) * m + w2 ** 3 / 3 + w2 * (w2 - 1) / 2 * (6 * w2 + 12 * w2)
+                + 2 * (m + n) * w2 ** 2)
+    f_blk = nb * (nb - 1) / 2 * per_pair
+    f_pt = n * (n - 1) / 2 * (6 * m + 6 * (m + n))
+    flops = float(np.sum(sw * np.where(blk, f_blk, f_pt)))
     achieved = flops / (ms * 1e-3) / 1e12
     status = int(b.status.abs().sum())
     cpu = None

@@ -188,11 +188,14 @@ int jsvd_hsvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
 
 /*
  * Many independent ordinary SVDs of uneven sizes (the same one-sided Jacobi
- * method, Section 2 eqs. (2.3)-(2.5) with the rotations (4.3)-(4.6), applied
- * pointwise to each problem in the p-steps of the closest parallel strategy
- * of Section 3), in one persistent launch: workgroups pull problems from a
- * device queue, largest n first, and each runs its problem to its own
- * convergence (a sweep with no proper rotation, Section 4.5) or opts->max_sweeps.
+ * method, Section 2 eqs. (2.3)-(2.5) with the rotations (4.3)-(4.6), in the
+ * p-steps of the closest parallel strategy of Section 3: pointwise for the
+ * smaller problems, and for those with n >= jsvd_batched_block_min_n(h) the
+ * two-level method with block-columns of 16 (Gram matrix (2.7), Cholesky,
+ * one inner sweep on R, update (2.9))), in two persistent launches (the
+ * blocked problems, then the others): workgroups pull problems from a device
+ * queue, largest n first, and each runs its problem to its own convergence (a
+ * sweep with no proper rotation, Section 4.5) or opts->max_sweeps.
  *   batch        : number of problems (0 is allowed: nothing is done).
  *   max_m, max_n : host bounds on the sizes, 1 <= max_n <= 256, max_n <= max_m;
  *                  they size the per-workgroup scratch.
@@ -202,11 +205,14 @@ int jsvd_hsvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
  *   s_off        : device int64[batch]: singular values of i at S + s_off[i] (n[i], non-increasing).
  *   v_off        : device int64[batch] or NULL when opts->want_v == 0: V_i at V + v_off[i],
  *                  n[i] x n[i], ldv = n[i].
- *   status       : device int32[batch] or NULL: 0 converged, JSVD_NOT_CONVERGED otherwise.
+ *   status       : device int32[batch] or NULL: 0 converged, JSVD_NOT_CONVERGED when
+ *                  max_sweeps ended it, JSVD_NONFINITE when a blocked problem met a
+ *                  NaN or infinite Cholesky pivot.
  *   sweeps       : device int32[batch] or NULL: sweeps performed.
  * Only opts->max_sweeps and opts->want_v are used (block_w does not apply:
- * the problems are not blocked); the handle's tuned batch_g_groups, if any,
- * sets how a workgroup divides its half waves between G and V.  The work is enqueued on the handle's
+ * blocked problems use 16); the handle's tuned batch_g_groups, if any, sets
+ * how a workgroup of the pointwise kernel divides its half waves between G
+ * and V, and its batch_block_min_n which problems are blocked.  The work is enqueued on the handle's
  * stream and the call returns without waiting, so a caller can capture it
  * into a HIP graph once the first call (which allocates the workspace and
  * uploads the strategy tables) has run; the problems must not overlap in A,
@@ -252,6 +258,11 @@ int jsvd_strategy_table(int32_t order, int32_t kind, int32_t *pairs);
 
 /* Smallest supported strategy order >= max(nb, 2) (even, 2^k * o, o <= 11). */
 int32_t jsvd_strategy_order(int32_t nb);
+
+/* The smallest n of a problem that jsvd_gesvd_batched solves by the blocked
+ * method on this handle (its tuned batch_block_min_n, else the built-in
+ * value); a value above 256 means none.  Returns -1 if h is NULL. */
+int32_t jsvd_batched_block_min_n(jsvd_handle_t h);
 
 /*
  * Measurement aid: per-kernel GPU time of the block sweeps, taken with HIP

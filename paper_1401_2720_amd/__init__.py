@@ -4,9 +4,9 @@ The computation runs in the HIP library ``_lib/libjsvd.so`` (C ABI in
 ``include/jsvd.h``); this package is its Python binding.  See
 ``_binding`` for the calls.
 """
-from ._binding import (EXPORTS, Batch, JsvdError, STRATEGIES, diag_fp64, gesvd,  # noqa: F401
-                       gesvd_batched, hsvd, lib, strategy_order, strategy_table,
-                       svd_backward)
+from ._binding import (EXPORTS, Batch, JsvdError, STRATEGIES, batched_block_min_n,  # noqa: F401
+                       diag_fp64, gesvd, gesvd_batched, hsvd, lib, strategy_order,
+                       strategy_table, svd_backward)
 from .autograd import JacobiSVD, svd  # noqa: F401,E402
 
-__all__ = ["gesvd", "hsvd", "gesvd_batched", "Batch", "svd", "JacobiSVD", "svd_backward", "strategy_table", "strategy_order", "diag_fp64", "lib", "JsvdError"]
+__all__ = ["gesvd", "hsvd", "gesvd_batched", "Batch", "svd", "JacobiSVD", "svd_backward", "strategy_table", "strategy_order", "diag_fp64", "lib", "JsvdError", "batched_block_min_n"]

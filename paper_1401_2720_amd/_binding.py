@@ -56,7 +56,7 @@ _LIB = None
 EXPORTS = ["jsvd_default_opts", "jsvd_create", "jsvd_set_stream", "jsvd_destroy", "jsvd_gesvd",
            "jsvd_hsvd", "jsvd_strategy_table", "jsvd_strategy_order", "jsvd_error_string",
            "jsvd_diag_fp64", "jsvd_kernel_timing", "jsvd_kernel_times", "jsvd_gesvd_batched",
-           "jsvd_svd_backward", "jsvd_set_tuning"]
+           "jsvd_svd_backward", "jsvd_set_tuning", "jsvd_batched_block_min_n"]
 
 
 def lib():
@@ -79,6 +79,8 @@ def lib():
     L.jsvd_strategy_table.argtypes = [_i32, _i32, _vp]
     L.jsvd_strategy_order.argtypes = [_i32]
     L.jsvd_strategy_order.restype = _i32
+    L.jsvd_batched_block_min_n.argtypes = [_vp]
+    L.jsvd_batched_block_min_n.restype = _i32
     L.jsvd_error_string.argtypes = [ctypes.c_int]
     L.jsvd_error_string.restype = ctypes.c_char_p
     L.jsvd_diag_fp64.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp]
@@ -273,6 +275,14 @@ def strategy_table(order, kind="rrev"):
 
 def strategy_order(nb):
     return int(lib().jsvd_strategy_order(int(nb)))
+
+
+def batched_block_min_n(device_index=None):
+    """Smallest n that the batched call blocks on this device's handle."""
+    import torch
+    dev = torch.cuda.current_device() if device_index is None else device_index
+    h = _handle(dev, torch.cuda.current_stream(dev).cuda_stream)
+    return int(lib().jsvd_batched_block_min_n(h))
 
 
 def diag_fp64(a, b):

@@ -11,7 +11,10 @@ Tuned:
     that is >= its n, or the last one);
   * the split of the batched kernel's 32 half waves between rotating G and
     applying the rotations to V, on the 10000-problem ragged batch (n 8..128,
-    m = n + 0..64, the synthetic stand-in of the batched workload).
+    m = n + 0..64, the synthetic stand-in of the batched workload), with
+    blocking off so that every problem takes the pointwise kernel;
+  * then, with that split, the smallest n of a batched problem that takes
+    the blocked method (block-columns of 16), same batch.
 
 Every candidate is timed twice after a warm-up run and the faster time is
 kept; times are the library's own solve times (dense) and the wall time of
@@ -30,6 +33,7 @@ from . import inputs
 DENSE_ORDERS = (256, 512, 1024, 2048, 3072, 4096)
 WIDTHS = (16, 32)
 G_GROUPS = (8, 12, 16, 20, 24)
+BLOCK_MIN_N = (33, 49, 65, 81, 97, 257)  # 257: no problem blocked
 
 
 def _time_dense(B, A, w, reps=2):
@@ -57,7 +61,22 @@ def tune_dense(orders=DENSE_ORDERS, widths=WIDTHS, seed=11):
     return rows
 
 
-def tune_batched(groups=G_GROUPS, count=10000):
+def _time_batched(B, batch, reps=2):
+    import torch
+    best = None
+    for it in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.gesvd_batched(batch)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if it:
+            best = dt if best is None else min(best, dt)
+    return best
+
+
+def tune_batched(groups=G_GROUPS, block_min=BLOCK_MIN_N, count=10000):
+    """Returns ({g_groups: seconds}, {block_min_n: seconds})."""
     import torch
     from . import _binding as B
     data = inputs.ragged_batch(count=count)
@@ -65,23 +84,22 @@ def tune_batched(groups=G_GROUPS, count=10000):
     dev = torch.cuda.current_device()
     times = {}
     for g in groups:
-        B.set_tuning(dev, {"n_upper": [], "block_w": [], "batch_g_groups": g})
-        best = None
-        for it in range(3):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            B.gesvd_batched(batch)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            if it:
-                best = dt if best is None else min(best, dt)
-        times[g] = best
-        print(json.dumps({"batch_g_groups": g, "seconds": best}), flush=True)
+        B.set_tuning(dev, {"n_upper": [], "block_w": [], "batch_g_groups": g,
+                           "batch_block_min_n": 257})
+        times[g] = _time_batched(B, batch)
+        print(json.dumps({"batch_g_groups": g, "seconds": times[g]}), flush=True)
+    g_best = int(min(times, key=times.get))
+    btimes = {}
+    for mn in block_min:
+        B.set_tuning(dev, {"n_upper": [], "block_w": [], "batch_g_groups": g_best,
+                           "batch_block_min_n": mn})
+        btimes[mn] = _time_batched(B, batch)
+        print(json.dumps({"batch_block_min_n": mn, "seconds": btimes[mn]}), flush=True)
     B.set_tuning(dev, None)
-    return times
+    return times, btimes
 
 
-def table_from(dense_rows, batched_times):
+def table_from(dense_rows, batched_times, block_times=None):
     dense_rows = sorted(dense_rows, key=lambda r: r["n"])
     n_upper, block_w = [], []
     for r in dense_rows:
@@ -93,6 +111,8 @@ def table_from(dense_rows, batched_times):
     table = {"n_upper": n_upper, "block_w": block_w}
     if batched_times:
         table["batch_g_groups"] = int(min(batched_times, key=batched_times.get))
+    if block_times:
+        table["batch_block_min_n"] = int(min(block_times, key=block_times.get))
     return table
 
 
@@ -108,12 +128,13 @@ def main(argv=None):
     B.set_tuning(dev, None)  # measure from the built-in rule, not an older table
     orders = tuple(n for n in DENSE_ORDERS if n <= 1024) if a.quick else DENSE_ORDERS
     dense = tune_dense(orders)
-    batched = tune_batched(count=2000 if a.quick else 10000)
-    table = table_from(dense, batched)
+    batched, blocked = tune_batched(count=2000 if a.quick else 10000)
+    table = table_from(dense, batched, blocked)
     props = torch.cuda.get_device_properties(dev)
     rec = {"arch": props.gcnArchName.split(":")[0], "device": props.name,
            "date": datetime.date.today().isoformat(),
            "dense": dense, "batched_seconds": {str(k): v for k, v in batched.items()},
+           "batched_block_min_n_seconds": {str(k): v for k, v in blocked.items()},
            "table": table}
     with open(a.out, "w") as f:
         json.dump(rec, f, indent=1)

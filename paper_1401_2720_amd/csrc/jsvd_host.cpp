@@ -730,6 +730,11 @@ int jsvd_strategy_table(int32_t order, int32_t kind, int32_t *pairs) {
 
 int32_t jsvd_strategy_order(int32_t nb) { return strategy_order(nb); }
 
+int32_t jsvd_batched_block_min_n(jsvd_handle_t h) {
+    if (!h) return -1;
+    return h->tuning.batch_block_min_n ? h->tuning.batch_block_min_n : kBatchBlockMinN;
+}
+
 int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t max_n,
                        const int32_t *m, const int32_t *n, const int64_t *a_off,
                        const int64_t *s_off, const int64_t *v_off, double *A, double *S,

@@ -14,6 +14,13 @@ def test_table_from_merges_runs_of_the_same_width():
     assert t == {"n_upper": [1024, 4096], "block_w": [16, 32], "batch_g_groups": 16}
 
 
+def test_table_from_takes_the_fastest_block_threshold():
+    rows = [{"n": 256, "block_w": 16}]
+    t = autotune.table_from(rows, {16: 0.2}, {33: 0.13, 65: 0.12, 257: 0.17})
+    assert t == {"n_upper": [256], "block_w": [16], "batch_g_groups": 16,
+                 "batch_block_min_n": 65}
+
+
 def test_table_from_alternating():
     rows = [{"n": 256, "block_w": 32}, {"n": 512, "block_w": 16}, {"n": 1024, "block_w": 32}]
     t = autotune.table_from(rows, {})
@@ -24,6 +31,8 @@ def test_tuning_struct_fields_and_limits():
     t = B.tuning_struct({"n_upper": [2048, 8192], "block_w": [16, 32], "batch_g_groups": 20})
     assert t.count == 2 and list(t.n_upper)[:2] == [2048, 8192]
     assert list(t.block_w)[:2] == [16, 32] and t.batch_g_groups == 20
+    assert t.batch_block_min_n == 0
+    assert B.tuning_struct({"batch_block_min_n": 81}).batch_block_min_n == 81
     with pytest.raises(ValueError):
         B.tuning_struct({"n_upper": [1], "block_w": []})
     with pytest.raises(ValueError):

@@ -44,7 +44,9 @@ def test_invalid_table_refused(dev):
     from paper_1401_2720_amd import _binding as B
     for bad in ({"n_upper": [10], "block_w": [24]},
                 {"n_upper": [10, 5], "block_w": [16, 32]},
-                {"n_upper": [], "block_w": [], "batch_g_groups": 2}):
+                {"n_upper": [], "block_w": [], "batch_g_groups": 2},
+                {"n_upper": [], "block_w": [], "batch_block_min_n": 20},
+                {"n_upper": [], "block_w": [], "batch_block_min_n": 300}):
         with pytest.raises(B.JsvdError):
             B.set_tuning(dev, bad)
 
