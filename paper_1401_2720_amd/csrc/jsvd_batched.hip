@@ -251,7 +251,7 @@ __device__ int pointwise_sweeps(double *Gw, double *Vw, int m, int n, int N,
 // passes the relative orthogonality test everywhere is left alone.  Up to
 // kBlkPairs pivot pairs are in flight: four waves per pair form the Gram
 // matrix (rows split, FP64 MFMA) and apply V' (FP64 MFMA), one wave per pair
-// factors it, and 16 lanes per pivot pair of R run the inner sweep.  G and V
+// factors it, and 8 lanes per pivot pair of R run the inner sweep.  G and V
 // stay in their global buffers; R and V' live in LDS.
 constexpr int kBlkW = 16, kBlkBW = 2 * kBlkW, kBlkLD = kBlkBW + 1, kBlkPairs = 4;
 constexpr int kBlkMat = kBlkBW * kBlkLD;  // doubles of one R or V'
@@ -475,33 +475,59 @@ __device__ __forceinline__ int blocked_sweeps(double *G, double *V, int m, int n
                 }
                 __syncthreads();
 
-                // (4) one inner sweep on R, 16 lanes per pivot pair (rows x and
-                // x + 16), V' row-major
+                // (4) one inner sweep on R, 8 lanes per pivot pair (rows x + 8r) on
+                // waves 0-7, V' row-major.  Subphase 2 on squares where they cannot
+                // leave the normal range (h_pq != 0 implies h_pp, h_qq > 0), else
+                // in IEEE operations.
                 {
-                    const int gid = tid >> 4, k = gid >> 4, slot2 = gid & 15, x = tid & 15;
-                    const bool act = k < npg && s_need[k];
+                    constexpr int RL = kBlkBW / 8;  // rows per lane
+                    const int gid = tid >> 3, k = gid >> 4, slot2 = gid & 15, x = tid & 7;
+                    const bool act = tid < 512 && k < npg && s_need[k];
+                    const double tol2 = kEps * kEps * kBlkBW;  // tol^2, exact
                     double *Rk = Rm + k * kBlkMat, *Vk = Vm + k * kBlkMat;
                     for (int st2 = 0; st2 < kBlkBW - 1; ++st2) {
                         if (act) {
                             const int p = itbl[st2 * kBlkBW + 2 * slot2];
                             const int q = itbl[st2 * kBlkBW + 2 * slot2 + 1];
                             double *rp = Rk + p * kBlkLD, *rq = Rk + q * kBlkLD;
-                            const double a0 = rp[x], a1 = rp[x + 16], b0 = rq[x], b1 = rq[x + 16];
-                            const double hpp = row_sum(fma(a0, a0, a1 * a1));
-                            const double hqq = row_sum(fma(b0, b0, b1 * b1));
-                            const double hpq = row_sum(fma(a0, b0, a1 * b1));
+                            double a[RL], bq[RL];
+#pragma unroll
+                            for (int r = 0; r < RL; ++r) {
+                                a[r] = rp[x + 8 * r];
+                                bq[r] = rq[x + 8 * r];
+                            }
+                            double hpp = a[0] * a[0], hqq = bq[0] * bq[0], hpq = a[0] * bq[0];
+#pragma unroll
+                            for (int r = 1; r < RL; ++r) {
+                                hpp = fma(a[r], a[r], hpp);
+                                hqq = fma(bq[r], bq[r], hqq);
+                                hpq = fma(a[r], bq[r], hpq);
+                            }
+                            hpp = half_row_sum(hpp);
+                            hqq = half_row_sum(hqq);
+                            hpq = half_row_sum(hpq);
                             double tn = 0.0, cs = 0.0;
-                            if (trig_pair(hpp, hqq, hpq, tol, tn, cs)) {
-                                rp[x] = cs * fma(-tn, b0, a0);
-                                rq[x] = cs * fma(tn, a0, b0);
-                                rp[x + 16] = cs * fma(-tn, b1, a1);
-                                rq[x + 16] = cs * fma(tn, a1, b1);
-                                double *v0 = Vk + x * kBlkLD, *v1 = Vk + (x + 16) * kBlkLD;
-                                const double c0 = v0[p], d0 = v0[q], c1 = v1[p], d1 = v1[q];
-                                v0[p] = cs * fma(-tn, d0, c0);
-                                v0[q] = cs * fma(tn, c0, d0);
-                                v1[p] = cs * fma(-tn, d1, c1);
-                                v1[q] = cs * fma(tn, c1, d1);
+                            bool rot;
+                            if (in_trig_range(hpp, hqq)) {
+                                rot = !(hpq * hpq <= tol2 * hpp * hqq);
+                                bool clamped;
+                                if (rot) rotation_fast(hpp, hqq, hpq, 1, tn, cs, clamped);
+                            } else {
+                                rot = trig_pair(hpp, hqq, hpq, tol, tn, cs);
+                            }
+                            if (rot) {
+#pragma unroll
+                                for (int r = 0; r < RL; ++r) {
+                                    rp[x + 8 * r] = cs * fma(-tn, bq[r], a[r]);
+                                    rq[x + 8 * r] = cs * fma(tn, a[r], bq[r]);
+                                }
+#pragma unroll
+                                for (int r = 0; r < RL; ++r) {
+                                    double *vr = Vk + (x + 8 * r) * kBlkLD;
+                                    const double c0 = vr[p], d0 = vr[q];
+                                    vr[p] = cs * fma(-tn, d0, c0);
+                                    vr[q] = cs * fma(tn, c0, d0);
+                                }
                                 if (x == 0) {
                                     atomicAdd(&s_rotk[k], 1);
                                     prop += cs != 1.0 ? 1 : 0;
