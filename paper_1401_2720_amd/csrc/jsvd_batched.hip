@@ -41,6 +41,15 @@ __device__ __forceinline__ double hw_sum(double v) {
     return v + __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
+// Order the LDS accesses of one wave around this point: what the wave
+// wrote before is what its lanes read after (the wave's LDS operations
+// complete in order).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Relative orthogonality test (subphase 2, reading: <= skips) and the
 // trigonometric rotation, eqs. (4.3)-(4.6) with t = +1 and cs_2: refined
 // reciprocal and square roots inside [2^-900, 2^900], IEEE outside.
@@ -420,54 +429,58 @@ __device__ __forceinline__ int blocked_sweeps(double *G, double *V, int m, int n
                 for (int u = 0; u < kBlkPairs; ++u) any |= (u < npg) ? s_need[u] : 0;
                 if (!any) continue;
 
-                // (3) Cholesky H = R^T R (right-looking, unpivoted; Section 4.1):
-                // 256 threads per pair, four entries each in registers; the
-                // pivot row goes through LDS (double-buffered, one barrier per
-                // step).  Row k of R is H's row k (as updated) times 1/sqrt(h_kk);
-                // a pivot that is not positive makes row k zero, a NaN or
-                // infinite one ends the problem.
-                {
-                    const int k = tid >> 8, ll = tid & 255, ci = ll & 31, cj = ll >> 5;
-                    const bool act = k < npg && s_need[k];
-                    double *Rk = Rm + k * kBlkMat, *rb = rowbuf + k * 2 * kBlkBW;
-                    double h[4], fin[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        h[u] = act ? Rk[(cj + 8 * u) * kBlkLD + ci] : 0.0;
-                        fin[u] = 0.0;
-                    }
+                // (3) Cholesky H = R^T R (right-looking, unpivoted; Section 4.1),
+                // one wave per pair in two panels of 16 rows: lane j holds rows
+                // 16 kb .. 16 kb + 15 of column j in registers and the pivots and
+                // multipliers are broadcast with readlane (no barrier); between the
+                // panels each lane subtracts the first panel's rows from its column
+                // of the trailing block, reading them from LDS.  Row k of R is H's
+                // row k (as updated) times 1/sqrt(h_kk); a pivot that is not
+                // positive makes row k zero, a NaN or infinite one ends the problem.
+                if (wave < npg && s_need[wave]) {
+                    double *Rk = Rm + wave * kBlkMat;
+                    const int j = lane & 31;
                     int bad_met = 0;
-                    for (int kk = 0; kk < kBlkBW; ++kk) {
-                        double *rk = rb + (kk & 1) * kBlkBW;
-                        if (act && ci == kk) {
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) rk[cj + 8 * u] = h[u];
+                    for (int kb = 0; kb < 2; ++kb) {
+                        if (kb == 1 && j >= 16) {
+                            // H[16 + i][j] -= sum_k R[k][16 + i] R[k][j], k < 16, in k order
+                            for (int i = 0; i <= j - 16; ++i) {
+                                double hv = Rk[j * kBlkLD + 16 + i];
+#pragma unroll
+                                for (int k = 0; k < 16; ++k)
+                                    hv = fma(-Rk[(16 + i) * kBlkLD + k], Rk[j * kBlkLD + k], hv);
+                                Rk[j * kBlkLD + 16 + i] = hv;
+                            }
                         }
-                        __syncthreads();
-                        if (act && ci >= kk) {
-                            const double hkk = rk[kk];
+                        wave_lds_sync();
+                        double hb[16];
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) hb[i] = Rk[j * kBlkLD + 16 * kb + i];
+#pragma unroll
+                        for (int k = 0; k < 16; ++k) {
+                            const int kk = 16 * kb + k;
+                            const double hkk = lane_value(hb[k], kk);
                             const bool bad = !(fabs(hkk) <= 0x1.fffffffffffffp+1023);
                             const bool pos = !bad && hkk > 0.0;
                             bad_met |= bad ? 1 : 0;
                             double rs, d;
                             rsqrt_sqrt(pos ? hkk : 1.0, rs, d);
-                            const double ri = rk[ci] * rs;
+                            double r = (j == kk) ? d : hb[k] * rs;
+                            r = (pos && j >= kk) ? r : 0.0;
+                            hb[k] = r;
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const int j = cj + 8 * u;
-                                if (ci == kk) {
-                                    fin[u] = (!pos || j < kk) ? 0.0 : (j == kk ? d : h[u] * rs);
-                                } else if (pos && j >= ci) {
-                                    h[u] = fma(-ri, rk[j] * rs, h[u]);
-                                }
-                            }
+                            for (int i = k + 1; i < 16; ++i)
+                                hb[i] = fma(-lane_value(r, 16 * kb + i), r, hb[i]);
                         }
-                    }
-                    if (act) {
+                        if (lane < kBlkBW) {
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) Rk[(cj + 8 * u) * kBlkLD + ci] = fin[u];
+                            for (int i = 0; i < 16; ++i)
+                                Rk[j * kBlkLD + 16 * kb + i] = (j >= 16 * kb + i) ? hb[i] : 0.0;
+                        }
+                        wave_lds_sync();
                     }
-                    if (bad_met) s_bad = 1;
+                    if (lane == 0 && bad_met) s_bad = 1;
                 }
                 for (int e = tid; e < kBlkPairs * kBlkBW * kBlkBW; e += kBatchThreads) {
                     const int k = e / (kBlkBW * kBlkBW), r = e % kBlkBW, c = (e / kBlkBW) % kBlkBW;
