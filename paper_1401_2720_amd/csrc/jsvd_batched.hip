@@ -303,7 +303,7 @@ __device__ __forceinline__ void blk_rows_update(double *X, int ldx, int rows, in
 // Returns the sweeps performed, plus kBlkConverged when a sweep performed
 // no proper rotation and kBlkNonfinite when a Cholesky pivot was NaN or
 // infinite.
-constexpr int kBlkLdsDoubles = 2 * kBlkPairs * kBlkMat + kBlkPairs * 3 * 4 * 64 + kBlkPairs * 2 * kBlkBW;
+constexpr int kBlkLdsDoubles = 2 * kBlkPairs * kBlkMat + kBlkPairs * 3 * 4 * 64;
 static_assert(kBlkLdsDoubles == kBatchBlockLds, "host LDS bound of the blocked method");
 
 constexpr int kBlkConverged = 1 << 16, kBlkNonfinite = 1 << 17;
@@ -321,7 +321,6 @@ __device__ __forceinline__ int blocked_sweeps(double *G, double *V, int m, int n
     const unsigned char *itbl = tbls + tbl_off[kBlkBW >> 1];
     const double tol = kEps * sqrt((double)kBlkBW);  // c(eps) at the inner level, n^ = 2w
     double *Rm = lds, *Vm = lds + kBlkPairs * kBlkMat, *red = lds + 2 * kBlkPairs * kBlkMat;
-    double *rowbuf = red + kBlkPairs * 3 * 4 * 64;  // pivot rows of the Cholesky, 2 per pair
     const int wk = wave >> 2, sub = wave & 3;  // pair and quarter of a wave's Gram / update work
 
     int sweeps = 0, result = 0;

@@ -77,7 +77,7 @@ hipError_t launch_update(int bw, const StepArgs &a, hipStream_t s);
 // ------------------------------------------------------ batched small SVDs
 constexpr int kBatchMaxN = 256;  // largest n of a problem in the batched path
 constexpr int kBatchBlockMinN = 65;     // built-in: batched problems with n >= this are blocked
-constexpr int kBatchBlockLds = 11776;   // doubles of LDS the blocked method needs
+constexpr int kBatchBlockLds = 11520;   // doubles of LDS the blocked method needs
 
 struct BatchArgs {
     int64_t count;
