@@ -265,8 +265,8 @@ __device__ int pointwise_sweeps(double *Gw, double *Vw, int m, int n, int N,
 constexpr int kBlkW = 16, kBlkBW = 2 * kBlkW, kBlkLD = kBlkBW + 1, kBlkPairs = 4;
 constexpr int kBlkMat = kBlkBW * kBlkLD;  // doubles of one R or V'
 
-// X[r0:r1, cols of pq] <- X[r0:r1, cols of pq] V' for the rows of one wave
-// (16-row slices from r0 + 16 sub, stride 16 nsub), V' row-major in LDS
+// X[0:rows, cols of pq] <- X[0:rows, cols of pq] V' for the rows of one
+// wave (16-row slices from row 16 sub, stride 16 nsub), V' row-major in LDS
 // with leading dimension kBlkLD.  All loads of a slice precede its stores.
 __device__ __forceinline__ void blk_rows_update(double *X, int ldx, int rows, int2 pq, int n,
                                                 const double *vs, int sub, int nsub) {
@@ -300,9 +300,9 @@ __device__ __forceinline__ void blk_rows_update(double *X, int ldx, int rows, in
 
 // The sweep loop of the blocked method on one problem (G: m x n, ld m; V:
 // n x n, ld n, identity on entry, or null).  lds holds kBlkLdsDoubles.
-// Returns the sweeps performed, plus kBlkConverged when a sweep performed
-// no proper rotation and kBlkNonfinite when a Cholesky pivot was NaN or
-// infinite.
+// Returns the sweeps performed (max_sweeps <= 0xffff), plus kBlkConverged
+// when a sweep performed no proper rotation and kBlkNonfinite when a
+// Cholesky pivot was NaN or infinite.
 constexpr int kBlkLdsDoubles = 2 * kBlkPairs * kBlkMat + kBlkPairs * 3 * 4 * 64;
 static_assert(kBlkLdsDoubles == kBatchBlockLds, "host LDS bound of the blocked method");
 
@@ -713,7 +713,8 @@ __global__ __launch_bounds__(kBatchThreads) void batched_blocked_kernel(BatchArg
         if (V)
             for (int e = tid; e < n * n; e += kBatchThreads) V[e] = (e % n == e / n) ? 1.0 : 0.0;
         __syncthreads();
-        const int r = blocked_sweeps(G, V, m, n, b.max_sweeps, b.tbl_order, b.tbl_off, b.tbls, lds_g);
+        const int r = blocked_sweeps(G, V, m, n, min(b.max_sweeps, 0xffff), b.tbl_order,
+                                     b.tbl_off, b.tbls, lds_g);
         const int status = (r & kBlkNonfinite) ? JSVD_NONFINITE
                            : (r & kBlkConverged) ? 0 : JSVD_NOT_CONVERGED;
         finish_problem(b, id, m, n, G, V, G, V, false, false, scratch, r & 0xffff, status, s_sig,
