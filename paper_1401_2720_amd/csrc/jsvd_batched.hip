@@ -258,11 +258,13 @@ __device__ int pointwise_sweeps(double *Gw, double *Vw, int m, int n, int N,
 // block-oriented) and [G_p G_q] V', [V_p V_q] V' (2.9), skipped when the
 // pair did not rotate (Section 4.4).  A pair whose Gram matrix already
 // passes the relative orthogonality test everywhere is left alone.  Up to
-// kBlkPairs pivot pairs are in flight: four waves per pair form the Gram
+// kBlkPairs pivot pairs are in flight: two waves per pair form the Gram
 // matrix (rows split, FP64 MFMA) and apply V' (FP64 MFMA), one wave per pair
 // factors it, and 8 lanes per pivot pair of R run the inner sweep.  G and V
-// stay in their global buffers; R and V' live in LDS.
+// stay in their global buffers; R and V' live in LDS, small enough for two
+// workgroups (two problems) per CU, which hide each other's latencies.
 constexpr int kBlkW = 16, kBlkBW = 2 * kBlkW, kBlkLD = kBlkBW + 1, kBlkPairs = 4;
+constexpr int kBlkThreads = 512;  // 8 waves: two per pivot pair in the Gram and update phases
 constexpr int kBlkMat = kBlkBW * kBlkLD;  // doubles of one R or V'
 
 // X[0:rows, cols of pq] <- X[0:rows, cols of pq] V' for the rows of one
@@ -303,7 +305,8 @@ __device__ __forceinline__ void blk_rows_update(double *X, int ldx, int rows, in
 // Returns the sweeps performed (max_sweeps <= 0xffff), plus kBlkConverged
 // when a sweep performed no proper rotation and kBlkNonfinite when a
 // Cholesky pivot was NaN or infinite.
-constexpr int kBlkLdsDoubles = 2 * kBlkPairs * kBlkMat + kBlkPairs * 3 * 4 * 64;
+constexpr int kBlkLdsDoubles = 2 * kBlkPairs * kBlkMat;  // R, V' (the Gram sums use V' space)
+static_assert(kBlkPairs * 3 * 4 * 64 <= kBlkPairs * kBlkMat, "Gram partial sums fit in V' space");
 static_assert(kBlkLdsDoubles == kBatchBlockLds, "host LDS bound of the blocked method");
 
 constexpr int kBlkConverged = 1 << 16, kBlkNonfinite = 1 << 17;
@@ -320,8 +323,8 @@ __device__ __forceinline__ int blocked_sweeps(double *G, double *V, int m, int n
     const unsigned char *btbl = tbls + tbl_off[NB >> 1];
     const unsigned char *itbl = tbls + tbl_off[kBlkBW >> 1];
     const double tol = kEps * sqrt((double)kBlkBW);  // c(eps) at the inner level, n^ = 2w
-    double *Rm = lds, *Vm = lds + kBlkPairs * kBlkMat, *red = lds + 2 * kBlkPairs * kBlkMat;
-    const int wk = wave >> 2, sub = wave & 3;  // pair and quarter of a wave's Gram / update work
+    double *Rm = lds, *Vm = lds + kBlkPairs * kBlkMat, *red = Vm;  // red: before V' is set
+    const int wk = wave >> 1, sub = wave & 1;  // pair and half of a wave's Gram / update work
 
     int sweeps = 0, result = 0;
     if (tid == 0) s_bad = 0;
@@ -348,7 +351,7 @@ __device__ __forceinline__ int blocked_sweeps(double *G, double *V, int m, int n
                 if (tid < kBlkPairs) s_need[tid] = s_rotk[tid] = 0;
                 __syncthreads();
 
-                // (1) Gram matrices: each wave sums its 16-row slices; the four
+                // (1) Gram matrices: each wave sums its 16-row slices; the two
                 // partial sums of a pair are added in wave order.
                 d4 acc[3];
 #pragma unroll
@@ -364,7 +367,7 @@ __device__ __forceinline__ int blocked_sweeps(double *G, double *V, int m, int n
                         valid[t] = gc < n;
                         col[t] = G + (valid[t] ? gc : 0) * m;
                     }
-                    for (int base = 16 * sub; base < m; base += 64) {
+                    for (int base = 16 * sub; base < m; base += 32) {
                         const int rb = base + 4 * grp;
                         double x[2][4];
 #pragma unroll
@@ -380,7 +383,7 @@ __device__ __forceinline__ int blocked_sweeps(double *G, double *V, int m, int n
                         }
                     }
                 }
-                for (int wv = 0; wv < 4; ++wv) {
+                for (int wv = 0; wv < 2; ++wv) {
                     if (wk < npg && sub == wv) {
                         double *Rk = Rm + wk * kBlkMat;
 #pragma unroll
@@ -389,7 +392,7 @@ __device__ __forceinline__ int blocked_sweeps(double *G, double *V, int m, int n
                             for (int v = 0; v < 4; ++v) {
                                 double *r = red + ((wk * 3 + t) * 4 + v) * 64 + lane;
                                 const double h = (wv == 0) ? acc[t][v] : *r + acc[t][v];
-                                if (wv < 3) {
+                                if (wv < 1) {
                                     *r = h;
                                 } else {
                                     // tile t: (0,0), (0,1), (1,1); entry (i, j) of H, both
@@ -413,11 +416,14 @@ __device__ __forceinline__ int blocked_sweeps(double *G, double *V, int m, int n
                     bool need = false;
                     if (u < npg) {
                         const double *Rk = Rm + u * kBlkMat;
-                        const int i = tid & 31, j = tid >> 5;
-                        if (i < j) {
-                            const double hij = Rk[j * kBlkLD + i];
-                            const double hii = Rk[i * kBlkLD + i], hjj = Rk[j * kBlkLD + j];
-                            need = hij != 0.0 && !(fabs(hij) <= tol * sqrt(hii) * sqrt(hjj));
+                        for (int e = tid; e < kBlkBW * kBlkBW; e += kBlkThreads) {
+                            const int i = e & 31, j = e >> 5;
+                            if (i < j) {
+                                const double hij = Rk[j * kBlkLD + i];
+                                const double hii = Rk[i * kBlkLD + i], hjj = Rk[j * kBlkLD + j];
+                                need = need || (hij != 0.0 &&
+                                                !(fabs(hij) <= tol * sqrt(hii) * sqrt(hjj)));
+                            }
                         }
                     }
                     if (__ballot(need) != 0ull && lane == 0) atomicOr(&s_need[u], 1);
@@ -481,7 +487,7 @@ __device__ __forceinline__ int blocked_sweeps(double *G, double *V, int m, int n
                     }
                     if (lane == 0 && bad_met) s_bad = 1;
                 }
-                for (int e = tid; e < kBlkPairs * kBlkBW * kBlkBW; e += kBatchThreads) {
+                for (int e = tid; e < kBlkPairs * kBlkBW * kBlkBW; e += kBlkThreads) {
                     const int k = e / (kBlkBW * kBlkBW), r = e % kBlkBW, c = (e / kBlkBW) % kBlkBW;
                     Vm[k * kBlkMat + r * kBlkLD + c] = (r == c) ? 1.0 : 0.0;
                 }
@@ -494,7 +500,7 @@ __device__ __forceinline__ int blocked_sweeps(double *G, double *V, int m, int n
                 {
                     constexpr int RL = kBlkBW / 8;  // rows per lane
                     const int gid = tid >> 3, k = gid >> 4, slot2 = gid & 15, x = tid & 7;
-                    const bool act = tid < 512 && k < npg && s_need[k];
+                    const bool act = k < npg && s_need[k];
                     const double tol2 = kEps * kEps * kBlkBW;  // tol^2, exact
                     double *Rk = Rm + k * kBlkMat, *Vk = Vm + k * kBlkMat;
                     for (int st2 = 0; st2 < kBlkBW - 1; ++st2) {
@@ -553,8 +559,8 @@ __device__ __forceinline__ int blocked_sweeps(double *G, double *V, int m, int n
                 // (5) [G_p G_q] V' and [V_p V_q] V' for the pairs that rotated
                 if (wk < npg && s_rotk[wk] > 0) {
                     const double *vs = Vm + wk * kBlkMat;
-                    blk_rows_update(G, m, m, pq, n, vs, sub, 4);
-                    if (V) blk_rows_update(V, n, n, pq, n, vs, sub, 4);
+                    blk_rows_update(G, m, m, pq, n, vs, sub, 2);
+                    if (V) blk_rows_update(V, n, n, pq, n, vs, sub, 2);
                 }
             }
         }
@@ -579,13 +585,14 @@ __device__ __forceinline__ int blocked_sweeps(double *G, double *V, int m, int n
 // ties by index, NaN last), U = G Sigma^{-1} and V in that order, status
 // and sweeps.  Gw / Vw are the working copies (LDS or the global buffers;
 // in_lds / v_lds say which), G / V the global buffers.
+template <int NT>
 __device__ __forceinline__ void finish_problem(const BatchArgs &b, int id, int m, int n, double *G,
                                                double *V, const double *Gw, const double *Vw,
                                                bool in_lds, bool v_lds, double *scratch,
                                                int sweeps, int status, double *s_sig,
                                                int *s_perm) {
     const int tid = threadIdx.x, x = tid & 31, group = tid >> 5;
-    for (int j = group; j < n; j += kGroups) {
+    for (int j = group; j < n; j += NT / 32) {
         const double *g = Gw + (size_t)j * m;
         double sacc = 0.0;
         for (int i = x; i < m; i += 32) sacc = fma(g[i], g[i], sacc);
@@ -593,7 +600,7 @@ __device__ __forceinline__ void finish_problem(const BatchArgs &b, int id, int m
         if (x == 0) s_sig[j] = sqrt(sacc);
     }
     __syncthreads();
-    for (int j = tid; j < n; j += kBatchThreads) {
+    for (int j = tid; j < n; j += NT) {
         const double kj = s_sig[j] != s_sig[j] ? -INFINITY : s_sig[j];
         int r = 0;
         for (int i = 0; i < n; ++i) {
@@ -604,27 +611,27 @@ __device__ __forceinline__ void finish_problem(const BatchArgs &b, int id, int m
     }
     const double *src = Gw;
     if (!in_lds) {
-        for (int e = tid; e < m * n; e += kBatchThreads) scratch[e] = G[e];
+        for (int e = tid; e < m * n; e += NT) scratch[e] = G[e];
         src = scratch;
     }
     const double *vsrc = Vw;
     if (V && !v_lds) {
-        for (int e = tid; e < n * n; e += kBatchThreads) scratch[(size_t)m * n + e] = V[e];
+        for (int e = tid; e < n * n; e += NT) scratch[(size_t)m * n + e] = V[e];
         vsrc = scratch + (size_t)m * n;
     }
     __syncthreads();
     double *S = b.S + b.s_off[id];
-    for (int e = tid; e < m * n; e += kBatchThreads) {
+    for (int e = tid; e < m * n; e += NT) {
         const int k = e / m, i = e % m, c = s_perm[k];
         const double sg = s_sig[c];
         G[e] = sg > 0.0 ? src[(size_t)c * m + i] / sg : 0.0;
     }
     if (V)
-        for (int e = tid; e < n * n; e += kBatchThreads) {
+        for (int e = tid; e < n * n; e += NT) {
             const int k = e / n, i = e % n;
             V[e] = vsrc[(size_t)s_perm[k] * n + i];
         }
-    for (int k = tid; k < n; k += kBatchThreads) S[k] = s_sig[s_perm[k]];
+    for (int k = tid; k < n; k += NT) S[k] = s_sig[s_perm[k]];
     if (tid == 0) {
         if (b.status) b.status[id] = status;
         if (b.sweeps) b.sweeps[id] = sweeps;
@@ -682,7 +689,7 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs b) {
             sweeps = pointwise_sweeps<6, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged);
         else
             sweeps = pointwise_sweeps<0, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged);
-        finish_problem(b, id, m, n, G, V, Gw, Vw, in_lds, v_lds, scratch, sweeps,
+        finish_problem<kBatchThreads>(b, id, m, n, G, V, Gw, Vw, in_lds, v_lds, scratch, sweeps,
                        converged ? 0 : JSVD_NOT_CONVERGED, s_sig, s_perm);
     }
 }
@@ -691,7 +698,8 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs b) {
 // blk_min_n): the blocked method, G and V in their global buffers.  A
 // kernel of its own so that its registers are allocated apart from the
 // pointwise method's.
-__global__ __launch_bounds__(kBatchThreads) void batched_blocked_kernel(BatchArgs b) {
+__global__ __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void batched_blocked_kernel(BatchArgs b) {
     extern __shared__ double lds_g[];  // R, V' and the Gram reduction of the pivot pairs
     __shared__ int s_item;
     __shared__ double s_sig[kBatchMaxN];
@@ -711,14 +719,14 @@ __global__ __launch_bounds__(kBatchThreads) void batched_blocked_kernel(BatchArg
         double *G = b.A + b.a_off[id];
         double *V = b.V ? b.V + b.v_off[id] : nullptr;
         if (V)
-            for (int e = tid; e < n * n; e += kBatchThreads) V[e] = (e % n == e / n) ? 1.0 : 0.0;
+            for (int e = tid; e < n * n; e += kBlkThreads) V[e] = (e % n == e / n) ? 1.0 : 0.0;
         __syncthreads();
         const int r = blocked_sweeps(G, V, m, n, min(b.max_sweeps, 0xffff), b.tbl_order,
                                      b.tbl_off, b.tbls, lds_g);
         const int status = (r & kBlkNonfinite) ? JSVD_NONFINITE
                            : (r & kBlkConverged) ? 0 : JSVD_NOT_CONVERGED;
-        finish_problem(b, id, m, n, G, V, G, V, false, false, scratch, r & 0xffff, status, s_sig,
-                       s_perm);
+        finish_problem<kBlkThreads>(b, id, m, n, G, V, G, V, false, false, scratch, r & 0xffff,
+                                    status, s_sig, s_perm);
     }
 }
 
@@ -766,8 +774,8 @@ hipError_t batched_set_lds(int bytes) {
     return e;
 }
 
-hipError_t launch_batched(const BatchArgs &b, int grid, int max_n, int *hist, int32_t *order,
-                          hipStream_t s) {
+hipError_t launch_batched(const BatchArgs &b, int grid, int bgrid, int max_n, int *hist,
+                          int32_t *order, hipStream_t s) {
     hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(256), 0, s, hist, max_n + 1);
     const unsigned blocks = (unsigned)((b.count + 255) / 256);
     hipLaunchKernelGGL(batch_count_kernel, dim3(blocks), dim3(256), 0, s, b.n, b.count, hist);
@@ -776,7 +784,7 @@ hipError_t launch_batched(const BatchArgs &b, int grid, int max_n, int *hist, in
     hipLaunchKernelGGL(batch_place_kernel, dim3(blocks), dim3(256), 0, s, b.n, b.count, hist,
                        order);
     if (b.blk_min_n > 0 && max_n >= b.blk_min_n)
-        hipLaunchKernelGGL(batched_blocked_kernel, dim3(grid), dim3(kBatchThreads),
+        hipLaunchKernelGGL(batched_blocked_kernel, dim3(bgrid), dim3(kBlkThreads),
                            (unsigned)(kBlkLdsDoubles * sizeof(double)), s, b);
     hipLaunchKernelGGL(batched_kernel, dim3(grid), dim3(kBatchThreads),
                        (unsigned)(b.lds_doubles * sizeof(double)), s, b);

@@ -796,12 +796,14 @@ int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t ma
         if (h->batch_lds < 0 || batched_set_lds(h->batch_lds) != hipSuccess) h->batch_lds = 0;
     }
     const int grid = (int)std::min<int64_t>(batch, std::max(1, h->cu_count));
+    const int bgrid = (int)std::min<int64_t>(batch, 2 * (int64_t)std::max(1, h->cu_count));
     const int64_t scratch_per_wg = (int64_t)max_m * max_n + (int64_t)max_n * max_n;
     const size_t off_hist = 0;
     const size_t off_order = align_up((size_t)(kBatchMaxN + 1) * sizeof(int), 256);
     const size_t off_queue = off_order + align_up((size_t)batch * sizeof(int32_t), 256);
     const size_t off_scratch = off_queue + 256;
-    const size_t total = off_scratch + (size_t)grid * scratch_per_wg * sizeof(double);
+    const size_t total =
+        off_scratch + (size_t)std::max(grid, bgrid) * scratch_per_wg * sizeof(double);
     int rc = ensure_workspace(h, total);
     if (rc) return rc;
     char *ws = static_cast<char *>(h->ws);
@@ -835,7 +837,7 @@ int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t ma
         const bool room = b.lds_doubles >= kBatchBlockLds;
         b.blk_min_n = (room && mn <= kBatchMaxN) ? mn : 0;
     }
-    HIP_TRY(launch_batched(b, grid, max_n, reinterpret_cast<int *>(ws + off_hist),
+    HIP_TRY(launch_batched(b, grid, bgrid, max_n, reinterpret_cast<int *>(ws + off_hist),
                            reinterpret_cast<int32_t *>(ws + off_order), st));
     return JSVD_OK;
 }

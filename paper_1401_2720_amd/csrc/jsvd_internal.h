@@ -77,7 +77,7 @@ hipError_t launch_update(int bw, const StepArgs &a, hipStream_t s);
 // ------------------------------------------------------ batched small SVDs
 constexpr int kBatchMaxN = 256;  // largest n of a problem in the batched path
 constexpr int kBatchBlockMinN = 65;     // built-in: batched problems with n >= this are blocked
-constexpr int kBatchBlockLds = 11520;   // doubles of LDS the blocked method needs
+constexpr int kBatchBlockLds = 8448;   // doubles of LDS the blocked method needs
 
 struct BatchArgs {
     int64_t count;
@@ -100,8 +100,10 @@ struct BatchArgs {
 
 hipError_t batched_set_lds(int bytes);
 
-hipError_t launch_batched(const BatchArgs &b, int grid, int max_n, int *hist, int32_t *order,
-                          hipStream_t s);
+// grid: workgroups of the pointwise kernel; bgrid: of the blocked kernel
+// (two fit on a CU); the scratch holds max(grid, bgrid) areas.
+hipError_t launch_batched(const BatchArgs &b, int grid, int bgrid, int max_n, int *hist,
+                          int32_t *order, hipStream_t s);
 
 // ------------------------------------------------------------ SVD adjoint
 struct GemmArgs {
