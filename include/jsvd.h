@@ -22,9 +22,10 @@
  *     jsvd_set_stream.  A call returns after its work has finished (it
  *     synchronises the stream once per block sweep to read the one
  *     convergence counter, as the paper's host loop does).
- *   - The library owns the handle, its strategy tables and a workspace it
+ *   - The library owns the handle, its strategy tables and the workspaces it
  *     allocates with hipMalloc on first use for a shape and keeps until
- *     jsvd_destroy.  A handle must not be used by two threads at once.
+ *     jsvd_destroy (jsvd_workspace_size and jsvd_workspace_size_batched say
+ *     how much).  A handle must not be used by two threads at once.
  *   - Return codes: JSVD_OK; a negative value -i means argument i is
  *     invalid (nothing was run); a positive value is a run-time condition,
  *     after which the outputs are still written.
@@ -41,11 +42,16 @@ extern "C" {
 
 #define JSVD_OK 0
 #define JSVD_NOT_CONVERGED 1   /* max_sweeps reached with proper rotations left */
-#define JSVD_CHOL_BREAKDOWN 2  /* reserved: zero Cholesky pivots are handled, see jsvd_info */
+/* 2 is not used: a Cholesky pivot that is not positive (Section 4.1 is silent
+ * on it; the pivot block Gram matrix is then only semidefinite) is not an
+ * error here -- it makes its row of R zero, the iteration goes on and
+ * jsvd_info.chol_breakdowns counts it; a NaN or infinite pivot returns
+ * JSVD_NONFINITE. */
 #define JSVD_NONFINITE 3       /* a NaN or infinity appeared in the input or the iteration */
 #define JSVD_HIP_ERROR 4       /* a HIP runtime call failed */
-#define JSVD_NO_MEMORY 5       /* workspace allocation failed */
-#define JSVD_DEGENERATE 6      /* equal singular values: the adjoint of U and V is undefined */
+#define JSVD_DEGENERATE 5      /* equal singular values: the adjoint of U and V is undefined */
+#define JSVD_NO_MEMORY 6       /* workspace allocation failed, or a workspace that a captured
+                                  graph uses would have to grow */
 
 /* Parallel pivot strategies of Section 3, used at both levels. */
 #define JSVD_STRAT_RREV 0 /* reverse of the p-strategy closest to row-cyclic (default) */
@@ -212,17 +218,59 @@ int jsvd_hsvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
  * Only opts->max_sweeps and opts->want_v are used (block_w does not apply:
  * blocked problems use 16); the handle's tuned batch_g_groups, if any, sets
  * how a workgroup of the pointwise kernel divides its half waves between G
- * and V, and its batch_block_min_n which problems are blocked.  The work is enqueued on the handle's
- * stream and the call returns without waiting, so a caller can capture it
- * into a HIP graph once the first call (which allocates the workspace and
- * uploads the strategy tables) has run; the problems must not overlap in A,
- * S or V.  Returns JSVD_OK, a negative argument index, JSVD_HIP_ERROR or
+ * and V, and its batch_block_min_n which problems are blocked.  The work is
+ * enqueued on the handle's stream and the call returns without waiting; the
+ * problems must not overlap in A, S or V.
+ * Workspace: the batched call has a device workspace of its own (apart from
+ * the one of jsvd_gesvd, jsvd_hsvd and jsvd_svd_backward, which therefore
+ * never free it).  It grows when a call needs more, unless the stream is
+ * being captured or a capture has used it: a graph holds its address, so
+ * from then on a call that would need more returns JSVD_NO_MEMORY instead
+ * (nothing enqueued).  To capture the first call, size the workspace with
+ * jsvd_reserve_batched beforehand.
+ * Returns JSVD_OK, a negative argument index, JSVD_HIP_ERROR or
  * JSVD_NO_MEMORY.
  */
 int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t max_n,
                        const int32_t *m, const int32_t *n, const int64_t *a_off,
                        const int64_t *s_off, const int64_t *v_off, double *A, double *S,
                        double *V, const jsvd_opts *opts, int32_t *status, int32_t *sweeps);
+
+/*
+ * Device workspace, in bytes, that jsvd_gesvd (or, for a J with both signs,
+ * jsvd_hsvd) needs for an m x n problem with these options (NULL: defaults):
+ * the pivot Gram partials, V'_pq slots and counters of the block sweeps
+ * (Sections 4.1-4.5), and for the QR preprocessing of a tall G (eq. (2.1))
+ * its factor and reflectors.  The library allocates it on first use and
+ * keeps it in the handle; nothing is allocated by this call.
+ * Returns JSVD_OK, -1 if h is NULL, -2/-3 for invalid m/n, -4 for invalid
+ * options, -5 if bytes is NULL.
+ */
+int jsvd_workspace_size(jsvd_handle_t h, int64_t m, int64_t n, const jsvd_opts *opts,
+                        size_t *bytes);
+
+/*
+ * Device workspace, in bytes, of jsvd_gesvd_batched for a batch of `batch`
+ * problems within the bounds max_m, max_n (arguments as for that call;
+ * opts may be NULL): the work order, the queue counters and one area of
+ * max_m max_n + max_n^2 doubles per workgroup of the persistent launches.
+ * Returns JSVD_OK, -1 if h is NULL, -2..-4 as jsvd_gesvd_batched, -5 for
+ * invalid options, -6 if bytes is NULL.
+ */
+int jsvd_workspace_size_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t max_n,
+                                const jsvd_opts *opts, size_t *bytes);
+
+/*
+ * Allocate now the batched workspace for such a batch (and upload the
+ * batched strategy tables), so that the next jsvd_gesvd_batched within these
+ * bounds allocates nothing and can be captured into a HIP graph even as the
+ * first call.  Synchronises the handle's stream if the workspace grows.
+ * Returns JSVD_OK, the argument errors of jsvd_workspace_size_batched (-6
+ * does not occur), JSVD_HIP_ERROR or JSVD_NO_MEMORY (also when a captured
+ * graph already uses a smaller workspace).
+ */
+int jsvd_reserve_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t max_n,
+                         const jsvd_opts *opts);
 
 /*
  * Adjoint (reverse-mode derivative) of the SVD for a batch of equally sized
@@ -289,6 +337,27 @@ const char *jsvd_error_string(int code);
  */
 int jsvd_diag_fp64(jsvd_handle_t h, int64_t count, const double *a, const double *b,
                    double *quot, double *root);
+
+/*
+ * Diagnostic: the refined FP64 operations that the inner rotations (4.3)-(4.6)
+ * and the Cholesky pivots of Section 4.1 use in place of IEEE division and
+ * square root, evaluated on the device by the very functions of the kernels,
+ * for count operand pairs (a[i], b[i]):
+ *   out[0 count + i] = reciprocal of b[i]     (Newton-refined hardware seed)
+ *   out[1 count + i] = a[i] / b[i]            (that reciprocal and one residual
+ *                                              correction)
+ *   out[2 count + i] = sqrt(a[i])             (coupled root / half-reciprocal
+ *                                              iteration, residual correction)
+ *   out[3 count + i] = 1 / sqrt(a[i])         (the Cholesky's pair, after an
+ *   out[4 count + i] = sqrt(a[i])              exact power-of-two scaling)
+ * a, b: device arrays of count doubles; out: device array of 5 count doubles.
+ * The operands are meant for the ranges the kernels use them in (positive
+ * normal numbers in [2^-900, 2^900]; for the last pair any positive finite
+ * a).  Returns JSVD_OK, -1 if h is NULL, -2 for count < 0, -3 for a NULL
+ * array, or JSVD_HIP_ERROR.
+ */
+int jsvd_diag_refined(jsvd_handle_t h, int64_t count, const double *a, const double *b,
+                      double *out);
 
 #ifdef __cplusplus
 }

@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(HERE, "_lib", "libjsvd.so")
 _i32, _i64, _dbl, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 
 STRATEGIES = {"rrev": 0, "r": 1, "crev": 2, "c": 3}
-STATUS = {0: "ok", 1: "not converged", 2: "Cholesky breakdown", 3: "non-finite value",
-          4: "HIP error", 5: "out of device memory", 6: "equal singular values"}
+STATUS = {0: "ok", 1: "not converged", 3: "non-finite value", 4: "HIP error",
+          5: "equal singular values", 6: "out of device memory"}
 
 
 class Opts(ctypes.Structure):
@@ -56,7 +56,9 @@ _LIB = None
 EXPORTS = ["jsvd_default_opts", "jsvd_create", "jsvd_set_stream", "jsvd_destroy", "jsvd_gesvd",
            "jsvd_hsvd", "jsvd_strategy_table", "jsvd_strategy_order", "jsvd_error_string",
            "jsvd_diag_fp64", "jsvd_kernel_timing", "jsvd_kernel_times", "jsvd_gesvd_batched",
-           "jsvd_svd_backward", "jsvd_set_tuning", "jsvd_batched_block_min_n"]
+           "jsvd_svd_backward", "jsvd_set_tuning", "jsvd_batched_block_min_n",
+           "jsvd_workspace_size", "jsvd_workspace_size_batched", "jsvd_reserve_batched",
+           "jsvd_diag_refined"]
 
 
 def lib():
@@ -88,12 +90,19 @@ def lib():
                                      _vp, ctypes.POINTER(Opts), _vp, _vp]
     L.jsvd_svd_backward.argtypes = [_vp, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.jsvd_set_tuning.argtypes = [_vp, ctypes.POINTER(Tuning)]
+    L.jsvd_workspace_size.argtypes = [_vp, _i64, _i64, ctypes.POINTER(Opts),
+                                      ctypes.POINTER(ctypes.c_size_t)]
+    L.jsvd_workspace_size_batched.argtypes = [_vp, _i64, _i32, _i32, ctypes.POINTER(Opts),
+                                              ctypes.POINTER(ctypes.c_size_t)]
+    L.jsvd_reserve_batched.argtypes = [_vp, _i64, _i32, _i32, ctypes.POINTER(Opts)]
+    L.jsvd_diag_refined.argtypes = [_vp, _i64, _vp, _vp, _vp]
     L.jsvd_kernel_timing.argtypes = [_vp, ctypes.c_int]
     L.jsvd_kernel_times.argtypes = [_vp, _vp, _vp]
     for f in ("jsvd_default_opts", "jsvd_create", "jsvd_set_stream", "jsvd_destroy",
               "jsvd_gesvd", "jsvd_hsvd", "jsvd_strategy_table", "jsvd_diag_fp64",
               "jsvd_kernel_timing", "jsvd_kernel_times", "jsvd_gesvd_batched",
-              "jsvd_svd_backward"):
+              "jsvd_svd_backward", "jsvd_workspace_size", "jsvd_workspace_size_batched",
+              "jsvd_reserve_batched", "jsvd_diag_refined"):
         getattr(L, f).restype = ctypes.c_int
     _LIB = L
     return L
@@ -300,6 +309,64 @@ def diag_fp64(a, b):
     if rc:
         raise JsvdError(rc, "jsvd_diag_fp64")
     return q, r
+
+
+def diag_refined(a, b):
+    """The kernels' refined reciprocal, quotient and square roots on the
+    device: returns (rcp(b), a/b, sqrt(a), 1/sqrt(a), sqrt(a)) as float64
+    CUDA tensors (the last two from the Cholesky's scaled pair)."""
+    import torch
+    a = a.contiguous()
+    b = b.contiguous()
+    out = torch.empty(5 * a.numel(), dtype=torch.float64, device=a.device)
+    dev = a.device
+    h = _handle(dev.index if dev.index is not None else torch.cuda.current_device(),
+                torch.cuda.current_stream(dev).cuda_stream)
+    rc = lib().jsvd_diag_refined(h, a.numel(), _vp(a.data_ptr()), _vp(b.data_ptr()),
+                                 _vp(out.data_ptr()))
+    if rc:
+        raise JsvdError(rc, "jsvd_diag_refined")
+    return tuple(out.view(5, -1)[k] for k in range(5))
+
+
+def workspace_size(m, n, device_index=None, **opts):
+    """Device workspace bytes of jsvd_gesvd / jsvd_hsvd for an m x n problem."""
+    import torch
+    dev = torch.cuda.current_device() if device_index is None else device_index
+    h = _handle(dev, torch.cuda.current_stream(dev).cuda_stream)
+    o = make_opts(**opts)
+    out = ctypes.c_size_t(0)
+    rc = lib().jsvd_workspace_size(h, int(m), int(n), ctypes.byref(o), ctypes.byref(out))
+    if rc:
+        raise JsvdError(rc, "jsvd_workspace_size")
+    return int(out.value)
+
+
+def workspace_size_batched(batch, device_index=None, max_sweeps=30):
+    """Device workspace bytes of jsvd_gesvd_batched for a Batch."""
+    import torch
+    dev = torch.cuda.current_device() if device_index is None else device_index
+    h = _handle(dev, torch.cuda.current_stream(dev).cuda_stream)
+    o = make_opts(max_sweeps=max_sweeps, want_v=batch.want_v)
+    out = ctypes.c_size_t(0)
+    rc = lib().jsvd_workspace_size_batched(h, batch.count, batch.max_m, batch.max_n,
+                                           ctypes.byref(o), ctypes.byref(out))
+    if rc:
+        raise JsvdError(rc, "jsvd_workspace_size_batched")
+    return int(out.value)
+
+
+def reserve_batched(batch, max_sweeps=30):
+    """Allocate the batched workspace for a Batch now, so that the next
+    gesvd_batched on it allocates nothing (and can be captured first)."""
+    import torch
+    dev = batch.A.device
+    h = _handle(dev.index if dev.index is not None else torch.cuda.current_device(),
+                torch.cuda.current_stream(dev).cuda_stream)
+    o = make_opts(max_sweeps=max_sweeps, want_v=batch.want_v)
+    rc = lib().jsvd_reserve_batched(h, batch.count, batch.max_m, batch.max_n, ctypes.byref(o))
+    if rc:
+        raise JsvdError(rc, "jsvd_reserve_batched")
 
 
 def kernel_timing(device_index, enable=True, stride=1):

@@ -11,30 +11,33 @@ import torch
 from . import _binding as B
 
 
-def _forward(A):
+def _forward(A, max_sweeps=30):
     """(U, S, V) of A (m, n) or (b, m, n), float64 CUDA."""
     if A.dim() == 2:
-        U, S, V, _ = B.gesvd(A)
+        # every non-zero status raises, as for the batched form: a result
+        # that did not converge must not flow into the backward
+        U, S, V, _ = B.gesvd(A, max_sweeps=max_sweeps, allow=())
         return U, S, V
     b, m, n = A.shape
     if n <= 256:
         batch = B.Batch.from_uniform(A)
-        B.gesvd_batched(batch, restore=False)
+        B.gesvd_batched(batch, max_sweeps=max_sweeps, restore=False)
         Ub = batch.A.view(b, n, m).transpose(-1, -2)
         Sb = batch.S.view(b, n)
         Vb = batch.V.view(b, n, n).transpose(-1, -2)
         if int(batch.status.abs().sum()) != 0:
             raise B.JsvdError(1, "jsvd_gesvd_batched")
         return Ub, Sb, Vb
-    outs = [B.gesvd(A[i])[:3] for i in range(b)]
+    outs = [B.gesvd(A[i], max_sweeps=max_sweeps, allow=())[:3] for i in range(b)]
     return tuple(torch.stack([o[k] for o in outs]) for k in range(3))
 
 
 class JacobiSVD(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, A, recompute=False):
-        U, S, V = _forward(A)
+    def forward(ctx, A, recompute=False, max_sweeps=30):
+        U, S, V = _forward(A, max_sweeps)
         ctx.recompute = recompute
+        ctx.max_sweeps = max_sweeps
         if recompute:
             ctx.save_for_backward(A)
         else:
@@ -46,13 +49,14 @@ class JacobiSVD(torch.autograd.Function):
     def backward(ctx, gU, gS, gV):
         if ctx.recompute:
             (A,) = ctx.saved_tensors
-            U, S, V = _forward(A.detach())
+            U, S, V = _forward(A.detach(), ctx.max_sweeps)
         else:
             U, S, V = ctx.saved_tensors
         dA = B.svd_backward(U, S, V, gU, gS, gV)
-        return dA, None
+        return dA, None, None
 
 
-def svd(A, recompute=False):
-    """U, S, V with A = U diag(S) V^T (economy), differentiable."""
-    return JacobiSVD.apply(A, recompute)
+def svd(A, recompute=False, max_sweeps=30):
+    """U, S, V with A = U diag(S) V^T (economy), differentiable.  Raises
+    JsvdError when the forward does not converge within max_sweeps."""
+    return JacobiSVD.apply(A, recompute, max_sweeps)

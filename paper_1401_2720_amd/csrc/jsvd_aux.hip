@@ -157,6 +157,23 @@ __global__ void diag_fp64_kernel(int64_t count, const double *a, const double *b
     }
 }
 
+// The refined operations of the rotation formulas and the Cholesky pivots,
+// through the same device functions the kernels call, for a rounding check.
+__global__ void diag_refined_kernel(int64_t count, const double *a, const double *b,
+                                    double *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        const double x = a[i], y = b[i];
+        out[i] = nrcp(y);
+        out[count + i] = ndiv(x, y);
+        out[2 * count + i] = nsqrt(x);
+        double rs, d;
+        rsqrt_sqrt(x, rs, d);
+        out[3 * count + i] = rs;
+        out[4 * count + i] = d;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_reset_counters(unsigned long long *c, hipStream_t s) {
@@ -223,6 +240,13 @@ hipError_t launch_diag_fp64(int64_t count, const double *a, const double *b, dou
                             double *r, hipStream_t s) {
     hipLaunchKernelGGL(diag_fp64_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
                        count, a, b, q, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_refined(int64_t count, const double *a, const double *b, double *out,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(diag_refined_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                       s, count, a, b, out);
     return hipGetLastError();
 }
 

@@ -24,12 +24,22 @@ struct DeviceTable {
 
 }  // namespace
 
+// Pinned host words of a handle: the per-sweep counters, then single
+// values read back from the device (QR abort flag, R's diagonal range,
+// the adjoint's degeneracy flag).
+constexpr int kHostSlots = 16;
+constexpr int kSlotFlag = C_COUNT;       // one int
+constexpr int kSlotRange = C_COUNT + 2;  // two doubles
+
 struct jsvd_handle_s {
     int device = 0;
     hipStream_t stream = nullptr;
-    void *ws = nullptr;          // device workspace
+    void *ws = nullptr;          // device workspace of gesvd / hsvd / backward
     size_t ws_bytes = 0;
-    unsigned long long *host_counters = nullptr;  // pinned
+    void *bws = nullptr;         // device workspace of the batched call, never freed
+    size_t bws_bytes = 0;        // while the handle lives except to grow it
+    bool bws_captured = false;   // a graph capture used bws: it must not move
+    unsigned long long *host_counters = nullptr;  // pinned, kHostSlots words
     std::map<std::pair<int, int>, DeviceTable> block_tables;  // (order, kind) -> int2[]
     std::map<std::pair<int, int>, DeviceTable> inner_tables;  // (bw, kind) -> uchar[]
     // batched path: strategy tables of every order up to kBatchMaxN
@@ -42,6 +52,7 @@ struct jsvd_handle_s {
     int64_t colexp_cap = 0;
     void *qr_ws = nullptr;          // QR preprocessing workspace (kept apart from ws,
     size_t qr_ws_bytes = 0;         // which the Jacobi solve of R^T may reallocate)
+    int qr_resident = 0;            // QR panel workgroups that can be resident at once
     // per-kernel timing (measurement aid): 4 events per p-step
     bool timing = false;
     int timing_stride = 1;          // time every timing_stride-th p-step
@@ -59,6 +70,32 @@ namespace {
     } while (0)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// The batched call's workspace: grows like the other one, except while the
+// stream is being captured or after a capture used it (the graph holds its
+// address), when a call that needs more gets JSVD_NO_MEMORY.
+int ensure_batch_workspace(jsvd_handle_s *h, size_t bytes, bool capturing) {
+    if (bytes <= h->bws_bytes) return JSVD_OK;
+    if (capturing || h->bws_captured) return JSVD_NO_MEMORY;
+    if (h->bws) {
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return JSVD_HIP_ERROR;
+        (void)hipFree(h->bws);
+        h->bws = nullptr;
+        h->bws_bytes = 0;
+    }
+    if (hipMalloc(&h->bws, bytes) != hipSuccess) {
+        h->bws = nullptr;
+        return JSVD_NO_MEMORY;
+    }
+    h->bws_bytes = bytes;
+    return JSVD_OK;
+}
+
+bool stream_capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
+    return cs == hipStreamCaptureStatusActive;
+}
 
 int ensure_workspace(jsvd_handle_s *h, size_t bytes) {
     if (bytes <= h->ws_bytes) return JSVD_OK;
@@ -145,6 +182,28 @@ int choose_inner_sweeps(int64_t m, int64_t n) {
     return 1;
 }
 
+// Block width of a solve: the caller's, else the handle's tuning table,
+// else the built-in size rule.
+int pick_w(const jsvd_handle_s *h, const jsvd_opts &o, int64_t m, int64_t n) {
+    int w = o.block_w;
+    if (!w && h->tuning.count > 0) {
+        int i = 0;
+        while (i + 1 < h->tuning.count && n > h->tuning.n_upper[i]) ++i;
+        w = h->tuning.block_w[i];
+    }
+    if (!w) w = choose_w(m, n);
+    return w;
+}
+
+// Gram row splits of a solve (at most 16, rows per split a multiple of 64),
+// aiming at a few workgroups per CU.
+int gram_splits(int64_t m, int npairs, int64_t *rows_per_split) {
+    int splits = std::min(16, std::max(1, 512 / npairs));
+    const int64_t rps = (int64_t)align_up((size_t)((m + splits - 1) / splits), 64);
+    *rows_per_split = rps;
+    return (int)((m + rps - 1) / rps);
+}
+
 // Workspace carve-up for one solve.
 struct Layout {
     size_t hpart, vprime, pair_rot, counters, perm, s_tmp, tmp, perm_in, total;
@@ -210,13 +269,7 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
           const int *perm_in_host) {
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = h->stream;
-    int w = o.block_w;
-    if (!w && h->tuning.count > 0) {
-        int i = 0;
-        while (i + 1 < h->tuning.count && n > h->tuning.n_upper[i]) ++i;
-        w = h->tuning.block_w[i];
-    }
-    if (!w) w = choose_w(m, n);
+    const int w = pick_w(h, o, m, n);
     const int bw = 2 * w;
     const int nb_real = (int)((n + w - 1) / w);
     const int order = strategy_order(nb_real);
@@ -229,9 +282,8 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     // p-step's inner launch, in about two workgroups per CU that the pivot
     // pairs leave free (a workgroup there has 16 * 2w threads).
     const int target_wg = 1024;
-    int splits = std::min(16, std::max(1, 512 / npairs));
-    int64_t rps = align_up((size_t)((m + splits - 1) / splits), 64);
-    splits = (int)((m + rps - 1) / rps);
+    int64_t rps = 0;
+    const int splits = gram_splits(m, npairs, &rps);
     const int per_pair = std::max(1, target_wg / npairs);
     const int64_t upd_rows_g = align_up((size_t)((m + per_pair - 1) / per_pair), 64);
     const int64_t upd_rows_v = align_up((size_t)((n + per_pair - 1) / per_pair), 64);
@@ -443,22 +495,46 @@ int gemm_plain(bool ta, const double *A, int64_t lda, const double *B, int64_t l
     return JSVD_OK;
 }
 
+// Workspace carve-up of the QR preprocessing (kept apart from the solve's).
+struct QrLayout {
+    size_t oW, oX, oVx, oVp, oT, oTau, oParts, oY1, oY2, oPart, oProw, oNrm, oPerm, oBar, total;
+};
+
+QrLayout qr_plan(int64_t m, int64_t n) {
+    constexpr int NB = kQrPanel;
+    const int64_t npan = (n + NB - 1) / NB;
+    QrLayout q;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off += align_up(bytes, 256); return at; };
+    q.oW = take((size_t)m * n * 8);
+    q.oX = take((size_t)n * n * 8);
+    q.oVx = take((size_t)n * n * 8);
+    q.oVp = take((size_t)m * NB * 8);
+    q.oT = take((size_t)npan * NB * NB * 8);
+    q.oTau = take((size_t)n * 8);
+    q.oParts = take((size_t)32 * NB * n * 8);
+    q.oY1 = take((size_t)NB * n * 8);
+    q.oY2 = take((size_t)NB * n * 8);
+    q.oPart = take((size_t)2 * 64 * NB * 8);
+    q.oProw = take((size_t)2 * NB * 8);
+    q.oNrm = take((size_t)n * 8);
+    q.oPerm = take((size_t)n * 4);
+    q.oBar = take(128);
+    q.total = off;
+    return q;
+}
+
 int gesvd_qr(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double *S,
              double *V, int64_t ldv, const jsvd_opts &o, jsvd_info *info) {
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = h->stream;
     constexpr int NB = kQrPanel;
     const int64_t npan = (n + NB - 1) / NB;
-    // workspace
-    size_t off = 0;
-    auto take = [&](size_t bytes) { size_t at = off; off += align_up(bytes, 256); return at; };
-    const size_t oW = take((size_t)m * n * 8), oX = take((size_t)n * n * 8),
-                 oVx = take((size_t)n * n * 8), oVp = take((size_t)m * NB * 8),
-                 oT = take((size_t)npan * NB * NB * 8), oTau = take((size_t)n * 8),
-                 oParts = take((size_t)32 * NB * n * 8), oY1 = take((size_t)NB * n * 8),
-                 oY2 = take((size_t)NB * n * 8), oPart = take((size_t)2 * 64 * NB * 8),
-                 oProw = take((size_t)2 * NB * 8), oNrm = take((size_t)n * 8),
-                 oPerm = take((size_t)n * 4), oBar = take(128);
+    const QrLayout q = qr_plan(m, n);
+    const size_t off = q.total;
+    const size_t oW = q.oW, oX = q.oX, oVx = q.oVx, oVp = q.oVp, oT = q.oT, oTau = q.oTau,
+                 oParts = q.oParts, oY1 = q.oY1, oY2 = q.oY2, oPart = q.oPart, oProw = q.oProw,
+                 oNrm = q.oNrm, oPerm = q.oPerm, oBar = q.oBar;
     if (off > h->qr_ws_bytes) {
         if (h->qr_ws) (void)hipFree(h->qr_ws);
         h->qr_ws = nullptr;
@@ -512,21 +588,22 @@ int gesvd_qr(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, dou
                 return rc;
         }
     }
-    int hab = 0;
-    HIP_TRY(hipMemcpyAsync(&hab, abort_flag, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (hab) return JSVD_HIP_ERROR;
-
-    // R numerically singular (dependent columns): solve G directly, so that V
-    // stays orthogonal and zero singular values stay exact
+    // A grid barrier of the panel kernel that did not complete (some panel
+    // workgroups could not start beside other work on the device), or R
+    // numerically singular (dependent columns): solve G directly, so that V
+    // stays orthogonal and zero singular values stay exact.  G itself is
+    // untouched so far (the factorization works on the copy W).  The abort
+    // flag and R's diagonal range are read through the handle's pinned words.
     {
-        double range[2] = {0.0, 0.0};
         double *d_range = reinterpret_cast<double *>(ws + oBar + 64);
         HIP_TRY(launch_diag_range(W, m, n, d_range, st));
-        HIP_TRY(hipMemcpyAsync(range, d_range, sizeof range, hipMemcpyDeviceToHost, st));
+        int *hab = reinterpret_cast<int *>(h->host_counters + kSlotFlag);
+        double *range = reinterpret_cast<double *>(h->host_counters + kSlotRange);
+        HIP_TRY(hipMemcpyAsync(hab, abort_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(range, d_range, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         const double dmin = range[0], dmax = range[1];
-        if (!(dmin > (double)n * 0x1p-53 * dmax)) {
+        if (*hab != 0 || !(dmin > (double)n * 0x1p-53 * dmax)) {
             jsvd_opts od = o;
             od.qr = 1;
             return solve(h, m, n, A, lda, S, V, ldv, n, od, info, false, nullptr);
@@ -567,6 +644,101 @@ int gesvd_qr(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, dou
     return status;
 }
 
+// Strategy tables of every supported order <= strategy_order(kBatchMaxN)
+// (R-reverse) for the batched kernels, and the LDS they may take.
+int ensure_batch_tables(jsvd_handle_s *h) {
+    if (h->batch_tables) return JSVD_OK;
+    std::vector<unsigned char> flat;
+    std::vector<int> tbl_order(kBatchMaxN + 1, 2);
+    const int top = strategy_order(kBatchMaxN);
+    std::vector<int64_t> tbl_off(top / 2 + 1, 0);
+    for (int N = 2; N <= top; N += 2) {
+        if (strategy_order(N) != N) continue;
+        Table t;
+        if (!make_table(N, JSVD_STRAT_RREV, t)) return JSVD_HIP_ERROR;
+        tbl_off[N / 2] = (int64_t)flat.size();
+        for (const auto &stp : t)
+            for (const auto &pr : stp) {
+                flat.push_back((unsigned char)pr.first);
+                flat.push_back((unsigned char)pr.second);
+            }
+    }
+    for (int k = 1; k <= kBatchMaxN; ++k) tbl_order[k] = strategy_order(k);
+    void *tables = nullptr, *meta = nullptr;
+    const size_t meta_bytes =
+        align_up(tbl_order.size() * sizeof(int), 256) + tbl_off.size() * sizeof(int64_t);
+    if (hipMalloc(&tables, flat.size()) != hipSuccess) return JSVD_NO_MEMORY;
+    if (hipMalloc(&meta, meta_bytes) != hipSuccess) {
+        (void)hipFree(tables);
+        return JSVD_NO_MEMORY;
+    }
+    h->batch_tables = tables;
+    h->batch_meta = meta;
+    HIP_TRY(hipMemcpy(h->batch_tables, flat.data(), flat.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->batch_meta, tbl_order.data(), tbl_order.size() * sizeof(int),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(static_cast<char *>(h->batch_meta) +
+                          align_up(tbl_order.size() * sizeof(int), 256),
+                      tbl_off.data(), tbl_off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, h->device));
+    h->cu_count = prop.multiProcessorCount;
+    // LDS for the working copy of G: what the CU has, less the static part
+    const size_t lds_total = prop.sharedMemPerMultiprocessor ? prop.sharedMemPerMultiprocessor
+                                                             : prop.sharedMemPerBlock;
+    h->batch_lds = (int)std::min<size_t>(lds_total, 160 * 1024) - 12 * 1024;
+    if (h->batch_lds < 0 || batched_set_lds(h->batch_lds) != hipSuccess) h->batch_lds = 0;
+    return JSVD_OK;
+}
+
+// Launch geometry and workspace carve-up of a batched call: the work order
+// histogram, the order itself, the queue counters and one scratch area per
+// workgroup of the larger of the two persistent grids.
+struct BatchPlan {
+    int grid, bgrid;
+    int64_t scratch_per_wg;
+    size_t off_hist, off_order, off_queue, off_scratch, total;
+};
+
+BatchPlan batch_plan(const jsvd_handle_s *h, int64_t batch, int32_t max_m, int32_t max_n) {
+    BatchPlan p;
+    const int cus = std::max(1, h->cu_count);
+    p.grid = (int)std::min<int64_t>(std::max<int64_t>(batch, 1), cus);
+    p.bgrid = (int)std::min<int64_t>(std::max<int64_t>(batch, 1), 2 * (int64_t)cus);
+    p.scratch_per_wg = (int64_t)max_m * max_n + (int64_t)max_n * max_n;
+    p.off_hist = 0;
+    p.off_order = align_up((size_t)(kBatchMaxN + 1) * sizeof(int), 256);
+    p.off_queue = p.off_order + align_up((size_t)batch * sizeof(int32_t), 256);
+    p.off_scratch = p.off_queue + 256;
+    p.total = p.off_scratch +
+              (size_t)std::max(p.grid, p.bgrid) * (size_t)p.scratch_per_wg * sizeof(double);
+    return p;
+}
+
+int check_batched_sizes(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t max_n) {
+    if (!h) return -1;
+    if (batch < 0) return -2;
+    if (max_m < 1 || max_m > (1 << 20)) return -3;
+    if (max_n < 1 || max_n > kBatchMaxN || max_n > max_m) return -4;
+    return JSVD_OK;
+}
+
+int check_opts(const jsvd_opts &o) {
+    if (o.block_w != 0 && o.block_w != 16 && o.block_w != 32) return -1;
+    if (o.strategy < JSVD_STRAT_RREV || o.strategy > JSVD_STRAT_C) return -1;
+    if (o.max_sweeps < 1 || o.max_inner_sweeps < 0) return -1;
+    if (o.qr < 0 || o.qr > 2) return -1;
+    if (o.scaled < 0 || o.scaled > 2) return -1;
+    return JSVD_OK;
+}
+
+// Whether jsvd_gesvd takes the QR path (before the scaling check, which can
+// still send a badly scaled G to the direct method).
+bool wants_qr(const jsvd_handle_s *h, const jsvd_opts &o, int64_t m, int64_t n) {
+    return (o.qr == 2 || (o.qr == 0 && m >= 2 * n)) && m <= 32768 && n >= 1 &&
+           qr_panel_groups(m) <= h->qr_resident;
+}
+
 int check_common(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
                  const jsvd_opts &o) {
     if (!h) return -1;
@@ -574,11 +746,7 @@ int check_common(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
     if (n < 1) return -3;
     if (!A) return -4;
     if (lda < m) return -5;
-    if (o.block_w != 0 && o.block_w != 16 && o.block_w != 32) return -9;
-    if (o.strategy < JSVD_STRAT_RREV || o.strategy > JSVD_STRAT_C) return -9;
-    if (o.max_sweeps < 1 || o.max_inner_sweeps < 0) return -9;
-    if (o.qr < 0 || o.qr > 2) return -9;
-    if (o.scaled < 0 || o.scaled > 2) return -9;
+    if (check_opts(o)) return -9;
     if (m > (int64_t)1 << 31 || n > (int64_t)1 << 20) return -2;
     return JSVD_OK;
 }
@@ -599,14 +767,23 @@ int jsvd_create(jsvd_handle_t *h, void *hip_stream) {
     if (!p) return JSVD_NO_MEMORY;
     if (hipGetDevice(&p->device) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&p->host_counters),
-                      C_COUNT * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+                      kHostSlots * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
         delete p;
         return JSVD_HIP_ERROR;
     }
+    std::memset(p->host_counters, 0, kHostSlots * sizeof(unsigned long long));
     p->stream = static_cast<hipStream_t>(hip_stream);
     if (hipDeviceGetAttribute(&p->cu_count, hipDeviceAttributeMultiprocessorCount, p->device) !=
         hipSuccess)
         p->cu_count = 0;
+    p->qr_resident = qr_panel_resident(p->cu_count);
+    // the batched path's strategy tables, so that its first call need not
+    // allocate them
+    const int rc = ensure_batch_tables(p);
+    if (rc) {
+        jsvd_destroy(p);
+        return rc;
+    }
     *h = p;
     return JSVD_OK;
 }
@@ -639,6 +816,7 @@ int jsvd_destroy(jsvd_handle_t h) {
     if (!h) return -1;
     (void)hipStreamSynchronize(h->stream);
     if (h->ws) (void)hipFree(h->ws);
+    if (h->bws) (void)hipFree(h->bws);
     for (auto &kv : h->block_tables) (void)hipFree(kv.second.ptr);
     for (auto &kv : h->inner_tables) (void)hipFree(kv.second.ptr);
     if (h->batch_tables) (void)hipFree(h->batch_tables);
@@ -660,7 +838,7 @@ int jsvd_gesvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda, do
     if (o.want_v && !V) return -7;
     if (o.want_v && ldv < n) return -8;
     if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
-    bool qr = (o.qr == 2 || (o.qr == 0 && m >= 2 * n)) && m <= 32768 && n >= 1;
+    bool qr = wants_qr(h, o, m, n);
     if (qr && o.scaled != 1) {
         // the Householder norms of the preprocessing are not scaled: a badly
         // scaled G goes to the scaled Jacobi method directly
@@ -740,10 +918,8 @@ int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t ma
                        const int64_t *s_off, const int64_t *v_off, double *A, double *S,
                        double *V, const jsvd_opts *opts, int32_t *status, int32_t *sweeps) {
     const jsvd_opts o = opts ? *opts : defaults();
-    if (!h) return -1;
-    if (batch < 0) return -2;
-    if (max_m < 1 || max_m > (1 << 20)) return -3;
-    if (max_n < 1 || max_n > kBatchMaxN || max_n > max_m) return -4;
+    int rc0 = check_batched_sizes(h, batch, max_m, max_n);
+    if (rc0) return rc0;
     if (!m) return -5;
     if (!n) return -6;
     if (!a_off) return -7;
@@ -756,57 +932,21 @@ int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t ma
     if (batch == 0) return JSVD_OK;
     if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
     hipStream_t st = h->stream;
-
+    const bool capturing = stream_capturing(st);
     if (!h->batch_tables) {
-        // tables of every supported order <= strategy_order(kBatchMaxN), R-reverse
-        std::vector<unsigned char> flat;
-        std::vector<int> tbl_order(kBatchMaxN + 1, 2);
-        const int top = strategy_order(kBatchMaxN);
-        std::vector<int64_t> tbl_off(top / 2 + 1, 0);
-        for (int N = 2; N <= top; N += 2) {
-            if (strategy_order(N) != N) continue;
-            Table t;
-            if (!make_table(N, JSVD_STRAT_RREV, t)) return JSVD_HIP_ERROR;
-            tbl_off[N / 2] = (int64_t)flat.size();
-            for (const auto &stp : t)
-                for (const auto &pr : stp) {
-                    flat.push_back((unsigned char)pr.first);
-                    flat.push_back((unsigned char)pr.second);
-                }
-        }
-        for (int k = 1; k <= kBatchMaxN; ++k) tbl_order[k] = strategy_order(k);
-        HIP_TRY(hipMalloc(&h->batch_tables, flat.size()));
-        HIP_TRY(hipMemcpy(h->batch_tables, flat.data(), flat.size(), hipMemcpyHostToDevice));
-        const size_t meta = align_up(tbl_order.size() * sizeof(int), 256) +
-                            tbl_off.size() * sizeof(int64_t);
-        HIP_TRY(hipMalloc(&h->batch_meta, meta));
-        HIP_TRY(hipMemcpy(h->batch_meta, tbl_order.data(), tbl_order.size() * sizeof(int),
-                          hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(static_cast<char *>(h->batch_meta) +
-                              align_up(tbl_order.size() * sizeof(int), 256),
-                          tbl_off.data(), tbl_off.size() * sizeof(int64_t),
-                          hipMemcpyHostToDevice));
-        hipDeviceProp_t prop;
-        HIP_TRY(hipGetDeviceProperties(&prop, h->device));
-        h->cu_count = prop.multiProcessorCount;
-        // LDS for the working copy of G: what the CU has, less the static part
-        const size_t lds_total = prop.sharedMemPerMultiprocessor ? prop.sharedMemPerMultiprocessor
-                                                                 : prop.sharedMemPerBlock;
-        h->batch_lds = (int)std::min<size_t>(lds_total, 160 * 1024) - 12 * 1024;
-        if (h->batch_lds < 0 || batched_set_lds(h->batch_lds) != hipSuccess) h->batch_lds = 0;
+        if (capturing) return JSVD_NO_MEMORY;
+        int rc = ensure_batch_tables(h);
+        if (rc) return rc;
     }
-    const int grid = (int)std::min<int64_t>(batch, std::max(1, h->cu_count));
-    const int bgrid = (int)std::min<int64_t>(batch, 2 * (int64_t)std::max(1, h->cu_count));
-    const int64_t scratch_per_wg = (int64_t)max_m * max_n + (int64_t)max_n * max_n;
-    const size_t off_hist = 0;
-    const size_t off_order = align_up((size_t)(kBatchMaxN + 1) * sizeof(int), 256);
-    const size_t off_queue = off_order + align_up((size_t)batch * sizeof(int32_t), 256);
-    const size_t off_scratch = off_queue + 256;
-    const size_t total =
-        off_scratch + (size_t)std::max(grid, bgrid) * scratch_per_wg * sizeof(double);
-    int rc = ensure_workspace(h, total);
+    const BatchPlan bp = batch_plan(h, batch, max_m, max_n);
+    const int grid = bp.grid, bgrid = bp.bgrid;
+    const int64_t scratch_per_wg = bp.scratch_per_wg;
+    const size_t off_hist = bp.off_hist, off_order = bp.off_order, off_queue = bp.off_queue,
+                 off_scratch = bp.off_scratch;
+    int rc = ensure_batch_workspace(h, bp.total, capturing);
     if (rc) return rc;
-    char *ws = static_cast<char *>(h->ws);
+    if (capturing) h->bws_captured = true;
+    char *ws = static_cast<char *>(h->bws);
 
     BatchArgs b;
     b.count = batch;
@@ -909,10 +1049,10 @@ int jsvd_svd_backward(jsvd_handle_t h, int64_t batch, int64_t m, int64_t n, cons
     g.B = V; g.ldb = n; g.sb = (int64_t)nn;
     g.C = dA; g.ldc = m; g.sc = m * n;
     HIP_TRY(launch_gemm(g, st));
-    int hflag = 0;
-    HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    int *hflag = reinterpret_cast<int *>(h->host_counters + kSlotFlag);
+    HIP_TRY(hipMemcpyAsync(hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    return hflag ? JSVD_DEGENERATE : JSVD_OK;
+    return *hflag ? JSVD_DEGENERATE : JSVD_OK;
 }
 
 int jsvd_kernel_timing(jsvd_handle_t h, int enable) {
@@ -942,11 +1082,11 @@ const char *jsvd_error_string(int code) {
     switch (code) {
     case JSVD_OK: return "success";
     case JSVD_NOT_CONVERGED: return "not converged within the block sweep limit";
-    case JSVD_CHOL_BREAKDOWN: return "Cholesky breakdown in a pivot block Gram matrix";
     case JSVD_NONFINITE: return "non-finite value in the input or the iteration";
     case JSVD_HIP_ERROR: return "HIP runtime error";
-    case JSVD_NO_MEMORY: return "device workspace allocation failed";
     case JSVD_DEGENERATE: return "equal singular values: the adjoint is undefined";
+    case JSVD_NO_MEMORY:
+        return "device workspace allocation failed (or a captured workspace would have to grow)";
     default: return code < 0 ? "invalid argument" : "unknown status";
     }
 }
@@ -961,6 +1101,65 @@ int jsvd_diag_fp64(jsvd_handle_t h, int64_t count, const double *a, const double
     HIP_TRY(launch_diag_fp64(count, a, b, quot, root, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     return JSVD_OK;
+}
+
+int jsvd_diag_refined(jsvd_handle_t h, int64_t count, const double *a, const double *b,
+                      double *out) {
+    if (!h) return -1;
+    if (count < 0) return -2;
+    if (!a || !b || !out) return -3;
+    if (count == 0) return JSVD_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
+    HIP_TRY(launch_diag_refined(count, a, b, out, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return JSVD_OK;
+}
+
+int jsvd_workspace_size(jsvd_handle_t h, int64_t m, int64_t n, const jsvd_opts *opts,
+                        size_t *bytes) {
+    const jsvd_opts o = opts ? *opts : defaults();
+    if (!h) return -1;
+    if (m < 1 || m < n || m > (int64_t)1 << 31) return -2;
+    if (n < 1 || n > (int64_t)1 << 20) return -3;
+    if (check_opts(o)) return -4;
+    if (!bytes) return -5;
+    // the Jacobi solve runs on G (m x n) or, after the QR preprocessing, on
+    // R^T (n x n); the hyperbolic SVD adds the input column permutation
+    auto solve_bytes = [&](int64_t mm, int64_t nn, bool hsvd) {
+        const int w = pick_w(h, o, mm, nn);
+        const int order = strategy_order((int)((nn + w - 1) / w));
+        int64_t rps = 0;
+        const int splits = gram_splits(mm, order / 2, &rps);
+        return plan(mm, nn, 2 * w, order / 2, splits, hsvd).total;
+    };
+    size_t total = std::max(solve_bytes(m, n, false), solve_bytes(m, n, true));
+    if (wants_qr(h, o, m, n)) total = std::max(total, solve_bytes(n, n, false)) + qr_plan(m, n).total;
+    if (o.scaled != 1) total += align_up((size_t)(n + 2) * sizeof(int), 256);
+    *bytes = total;
+    return JSVD_OK;
+}
+
+int jsvd_workspace_size_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t max_n,
+                                const jsvd_opts *opts, size_t *bytes) {
+    const jsvd_opts o = opts ? *opts : defaults();
+    int rc = check_batched_sizes(h, batch, max_m, max_n);
+    if (rc) return rc;
+    if (o.max_sweeps < 1) return -5;
+    if (!bytes) return -6;
+    *bytes = batch_plan(h, batch, max_m, max_n).total;
+    return JSVD_OK;
+}
+
+int jsvd_reserve_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t max_n,
+                         const jsvd_opts *opts) {
+    const jsvd_opts o = opts ? *opts : defaults();
+    int rc = check_batched_sizes(h, batch, max_m, max_n);
+    if (rc) return rc;
+    if (o.max_sweeps < 1) return -5;
+    if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
+    if ((rc = ensure_batch_tables(h))) return rc;
+    return ensure_batch_workspace(h, batch_plan(h, batch, max_m, max_n).total,
+                                  stream_capturing(h->stream));
 }
 
 }  // extern "C"

@@ -145,6 +145,7 @@ struct QrPanelArgs {
 };
 
 int qr_panel_groups(int64_t rows);
+int qr_panel_resident(int cu_count);  // panel workgroups that fit on the device at once
 hipError_t launch_qr_reset(unsigned *bar, int *abort_flag, hipStream_t s);
 hipError_t launch_diag_range(const double *W, int64_t ldw, int64_t n, double *out, hipStream_t s);
 hipError_t launch_qr_panel(const QrPanelArgs &a, hipStream_t s);
@@ -173,5 +174,7 @@ hipError_t launch_scatter_rows(const double *src, int64_t lds, double *dst, int6
                                int64_t rows, int64_t cols, const int *row_of, hipStream_t s);
 hipError_t launch_diag_fp64(int64_t count, const double *a, const double *b, double *q,
                             double *r, hipStream_t s);
+hipError_t launch_diag_refined(int64_t count, const double *a, const double *b, double *out,
+                               hipStream_t s);
 
 }  // namespace jsvd

@@ -288,6 +288,14 @@ int qr_panel_groups(int64_t rows) {
     return (int)((rows + per - 1) / per);
 }
 
+int qr_panel_resident(int cu_count) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(&qr_panel_kernel), kQT, 0) != hipSuccess)
+        return 0;
+    return per_cu * cu_count;
+}
+
 hipError_t launch_diag_range(const double *W, int64_t ldw, int64_t n, double *out, hipStream_t s) {
     hipLaunchKernelGGL(diag_range_kernel, dim3(1), dim3(256), 0, s, W, ldw, n, out);
     return hipGetLastError();
@@ -299,10 +307,12 @@ hipError_t launch_qr_reset(unsigned *bar, int *abort_flag, hipStream_t s) {
 }
 
 // The abort flag is left as it is: once a barrier has failed, the later
-// panels fall through at their first barrier and the caller reports it.
-// An ordinary launch in stream order: nwg <= 64 workgroups of 68 kB LDS,
-// one per CU, are all resident on the 256 CUs (a barrier that waited for
-// one that is not would end at its spin bound and report the failure).
+// panels fall through at their first barrier and the caller falls back to
+// the direct method.  An ordinary launch in stream order: the caller checks
+// that the nwg <= 64 workgroups of 68 kB LDS can all be resident
+// (qr_panel_resident); work of other streams or processes on the device can
+// still keep some from starting, and then a barrier ends at its spin bound
+// (about 1 s) instead of hanging.
 hipError_t launch_qr_panel(const QrPanelArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(qr_reset_kernel, dim3(1), dim3(64), 0, s, a.bar, (int *)nullptr);
     hipLaunchKernelGGL(qr_panel_kernel, dim3((unsigned)a.nwg), dim3(kQT), 0, s, a);

@@ -103,3 +103,19 @@ def test_bad_orders_rejected():
     assert L.jsvd_strategy_table(26, 0, buf.ctypes.data) == -1
     assert L.jsvd_strategy_table(8, 9, buf.ctypes.data) == -2
     assert L.jsvd_strategy_table(8, 0, None) == -3
+
+
+def test_workspace_and_diagnostic_calls_validate_arguments():
+    """The workspace queries, the reservation and the refined-arithmetic
+    diagnostic reject a NULL handle before touching a device, and the status
+    codes have their documented meaning (2 is not used)."""
+    L = jsvd.lib()
+    o = jsvd._binding.make_opts()
+    out = ctypes.c_size_t(0)
+    assert L.jsvd_workspace_size(None, 64, 64, ctypes.byref(o), ctypes.byref(out)) == -1
+    assert L.jsvd_workspace_size_batched(None, 10, 64, 64, ctypes.byref(o), ctypes.byref(out)) == -1
+    assert L.jsvd_reserve_batched(None, 10, 64, 64, ctypes.byref(o)) == -1
+    assert L.jsvd_diag_refined(None, 4, None, None, None) == -1
+    assert L.jsvd_error_string(5) == b"equal singular values: the adjoint is undefined"
+    assert L.jsvd_error_string(6).startswith(b"device workspace allocation failed")
+    assert L.jsvd_error_string(2) == b"unknown status"

@@ -109,3 +109,25 @@ def test_large_single_backward_fd():
     L, grad = _grad(A, w, W, d["k"])
     assert np.isfinite(L)
     _fd_check(A, w, W, d["k"], grad, seed=5, ndir=2)
+
+
+def test_differentiable_workload_256x64x64():
+    """The differentiable workload's batch itself: 256 matrices 64 x 64 with
+    sigma_i = 1 + 0.01 i (seed 6), every gradient against the oracle adjoint,
+    the batch loss against central differences."""
+    torch = _torch()
+    d = inputs.differentiable_set()
+    print("backward 256 x 64x64", flush=True)
+    A, w, W, k = d["small"], d["w_small"], d["W_small"], d["k"]
+    At = torch.from_numpy(A).cuda()
+    wt, Wt = torch.from_numpy(w).cuda(), torch.from_numpy(W).cuda()
+    _, grad = _grad(At, wt, Wt, k)
+    gh = grad.cpu().numpy()
+    worst = 0.0
+    for i in range(A.shape[0]):
+        ref = _oracle_grad(A[i], w[i], W[i], k)
+        rel = np.linalg.norm(gh[i] - ref) / np.linalg.norm(ref)
+        worst = max(worst, rel)
+        assert rel <= 1e-9, (i, rel)
+    print(f"  worst relative gradient error {worst:.2e}", flush=True)
+    _fd_check(At, wt, Wt, k, grad, seed=256, ndir=2)

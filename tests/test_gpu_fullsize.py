@@ -94,3 +94,54 @@ def test_hyperbolic_2048():
     lam = np.linalg.eigvalsh((G * J) @ G.T)
     got = np.sort(Jout * S.cpu().numpy() ** 2)
     assert np.max(np.abs(got - np.sort(lam))) <= 1e-12 * np.max(np.abs(lam)) * vmax
+
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    return np.loadtxt(path, comments="#")
+
+
+def _sigma_gate(s, ref, strict_from=1e-3):
+    """The sigma bars: |s - s_orc| <= 1e-12 s_orc + 1e-13 s_orc[0] for every
+    i, and relative 1e-12 outright for s_orc >= 1e-3 s_orc.max()."""
+    err = np.abs(s - ref)
+    assert np.all(err <= 1e-12 * ref + 1e-13 * ref.max()), float(np.max(err / ref))
+    big = ref >= strict_from * ref.max()
+    rel = float(np.max(err[big] / ref[big]))
+    assert rel <= 1e-12, rel
+    return rel
+
+
+def test_square_gaussian_4096_sigma_against_oracle():
+    """The benchmark workload's singular values against the oracle's
+    (round-robin order run to convergence, tests/golden/make_sigma_golden.py),
+    elementwise, in the launch configuration the benchmark times."""
+    torch = _torch()
+    import paper_1401_2720_amd as jsvd
+    print("4096 x 4096 N(0,1): sigma against the oracle", flush=True)
+    ref = _golden("sigma_gaussian4096_seed2.txt")
+    A = torch.from_numpy(inputs.square_gaussian()).cuda()
+    _, S, _, info = jsvd.gesvd(A)
+    torch.cuda.synchronize()
+    assert info["status"] == 0
+    rel = _sigma_gate(S.cpu().numpy(), ref)
+    print(f"  max rel sigma err {rel:.2e}", flush=True)
+
+
+def test_hyperbolic_2048_sigma_against_oracle():
+    torch = _torch()
+    import paper_1401_2720_amd as jsvd
+    print("hyperbolic 2048 x 2048: sigma against the oracle", flush=True)
+    ref = _golden("sigma_hsvd2048_p1280_seed4.txt")
+    G, J = inputs.hyperbolic_gaussian()
+    _, S, _, Jout, info = jsvd.hsvd(torch.from_numpy(G).cuda(), J)
+    torch.cuda.synchronize()
+    assert info["status"] == 0
+    assert np.array_equal(Jout, J)
+    s = S.cpu().numpy()
+    # each part in its own order (positive part non-increasing, negative
+    # part non-decreasing): compare part by part
+    rel_p = _sigma_gate(s[:1280], ref[:1280])
+    rel_m = _sigma_gate(s[1280:], ref[1280:])
+    print(f"  max rel sigma err +part {rel_p:.2e} -part {rel_m:.2e}", flush=True)

@@ -99,6 +99,15 @@ CASES = [
     ("odd_blocks_w16", 160, 144, dict(block_w=16), "gauss"),  # 9 block-columns
     ("block_oriented_ms1", 200, 192, dict(block_w=16, max_inner_sweeps=1), "gauss"),
     ("tall513x300_w32", 513, 300, dict(block_w=32), "graded"),
+    # the full block variant of Section 4.3: up to M_s = 30 inner sweeps per
+    # pivot block-pair (the inner stop on a sweep without rotation, the
+    # published rotations' double buffer across inner sweep boundaries and
+    # the counters summed over inner sweeps)
+    ("full_block_graded256_w16_rrev", 256, 256,
+     dict(block_w=16, strategy="rrev", max_inner_sweeps=30), "graded"),
+    ("full_block_ragged300x231_w32", 300, 231, dict(block_w=32, max_inner_sweeps=30), "gauss"),
+    ("full_block_ragged170x150_w16_c", 170, 150,
+     dict(block_w=16, strategy="c", max_inner_sweeps=30), "gauss"),
 ]
 
 
@@ -120,11 +129,18 @@ def test_gesvd_matches_oracle(name, m, n, kw, kind):
     _say(f"  sweeps={info['sweeps']} rotations={info['rotations']} w={info['block_w']}")
 
 
-def test_small_graded_workload():
-    """256 x 256, sigma 1 .. 1e-6, Haar factors, w = 16, cyclic parallel order."""
+@pytest.mark.parametrize("inner", [0, 30], ids=["library_choice", "full_block_30"])
+def test_small_graded_workload(inner):
+    """256 x 256, sigma 1 .. 1e-6, Haar factors, w = 16, Rrev (the cyclic
+    parallel order), the library's inner sweep choice and the full block
+    variant with M_s = 30 (Section 4.3)."""
     A = inputs.small_graded()
-    U, S, V, info = _run_gesvd(A, block_w=16)
+    U, S, V, info = _run_gesvd(A, block_w=16, strategy="rrev", max_inner_sweeps=inner)
     assert info["status"] == 0 and info["converged"] == 1
+    if inner == 30:
+        # more than one inner sweep per pivot pair on average: the repeated
+        # inner sweep did run
+        assert info["inner_sweeps"] > info["pair_updates"]
     ref = oracle.gesvj(A)
     _check_sigma(S, ref["S"])
     _check_svd(A, U, S, V, 256)
@@ -201,6 +217,10 @@ def _run_hsvd(G, J, **kw):
 
 HCASES = [
     ("hsvd96x80_p48", 96, 80, 48, False, dict(block_w=16)),
+    ("hsvd150x120_random_J_full_block", 150, 120, None, True,
+     dict(block_w=16, max_inner_sweeps=30)),
+    ("hsvd200x160_p100_w32_full_block", 200, 160, 100, False,
+     dict(block_w=32, max_inner_sweeps=30)),
     ("hsvd130x100_random_J", 130, 100, None, True, dict(block_w=16)),
     ("hsvd128x128_p64_w32", 128, 128, 64, False, dict(block_w=32)),
     ("hsvd70x50_p17_ragged", 70, 50, 17, False, dict(block_w=16)),

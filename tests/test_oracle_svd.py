@@ -201,3 +201,24 @@ def test_many_matches_single():
         r = oracle.gesvj(A)
         assert np.array_equal(o["S"], r["S"])
         assert np.array_equal(o["V"], r["V"])
+
+
+def test_threshold_uses_column_length():
+    """Section 4.3, subphase 2: a pair is left alone when |h_pq| <= c(eps)
+    sqrt(h_pp) sqrt(h_qq) with c(eps) = eps sqrt(nhat).  Reading used: nhat
+    is the length of the columns being orthogonalised (m), not their count.
+    Two columns of length m = 10000 with cosine 1e-15, between eps sqrt(2)
+    (1.6e-16) and eps sqrt(m) (1.1e-14), are therefore already orthogonal:
+    no rotation, V = I exactly, sigma = the column norms.  The dot products
+    are exact here (one nonzero product each), so rounding cannot decide."""
+    m, c = 10000, 1e-15
+    A = np.zeros((m, 2))
+    A[0, 0] = 1.0
+    A[0, 1] = c
+    A[1, 1] = 1.0
+    r = oracle.gesvj(A)
+    assert r["rotations"] == 0 and r["sweeps"] == 1
+    assert np.array_equal(r["V"], np.eye(2))
+    # the same pair with only its 2 nonzero rows (eps sqrt 2 < c) rotates
+    r2 = oracle.gesvj(A[:2].copy())
+    assert r2["rotations"] >= 1
