@@ -50,8 +50,8 @@ extern "C" {
 #define JSVD_NONFINITE 3       /* a NaN or infinity appeared in the input or the iteration */
 #define JSVD_HIP_ERROR 4       /* a HIP runtime call failed */
 #define JSVD_DEGENERATE 5      /* equal singular values: the adjoint of U and V is undefined */
-#define JSVD_NO_MEMORY 6       /* workspace allocation failed, or a workspace that a captured
-                                  graph uses would have to grow */
+#define JSVD_NO_MEMORY 6       /* workspace allocation failed, or a workspace would have to
+                                  grow while the stream is being captured */
 
 /* Parallel pivot strategies of Section 3, used at both levels. */
 #define JSVD_STRAT_RREV 0 /* reverse of the p-strategy closest to row-cyclic (default) */
@@ -223,11 +223,12 @@ int jsvd_hsvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
  * problems must not overlap in A, S or V.
  * Workspace: the batched call has a device workspace of its own (apart from
  * the one of jsvd_gesvd, jsvd_hsvd and jsvd_svd_backward, which therefore
- * never free it).  It grows when a call needs more, unless the stream is
- * being captured or a capture has used it: a graph holds its address, so
- * from then on a call that would need more returns JSVD_NO_MEMORY instead
- * (nothing enqueued).  To capture the first call, size the workspace with
- * jsvd_reserve_batched beforehand.
+ * never free it).  It grows when a call needs more, except while the stream
+ * is being captured: such a call returns JSVD_NO_MEMORY (nothing enqueued);
+ * to capture a call, size the workspace first with jsvd_reserve_batched or
+ * an eager call of at least that size.  A workspace that a capture used is
+ * never freed before jsvd_destroy (the graph holds its address): a later,
+ * larger call allocates a new one, and the graph still replays correctly.
  * Returns JSVD_OK, a negative argument index, JSVD_HIP_ERROR or
  * JSVD_NO_MEMORY.
  */
@@ -266,8 +267,8 @@ int jsvd_workspace_size_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, i
  * bounds allocates nothing and can be captured into a HIP graph even as the
  * first call.  Synchronises the handle's stream if the workspace grows.
  * Returns JSVD_OK, the argument errors of jsvd_workspace_size_batched (-6
- * does not occur), JSVD_HIP_ERROR or JSVD_NO_MEMORY (also when a captured
- * graph already uses a smaller workspace).
+ * does not occur), JSVD_HIP_ERROR or JSVD_NO_MEMORY (also when called while
+ * the stream is being captured and the workspace would have to grow).
  */
 int jsvd_reserve_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t max_n,
                          const jsvd_opts *opts);

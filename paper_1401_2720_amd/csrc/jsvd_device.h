@@ -34,34 +34,82 @@ __device__ __forceinline__ int64_t pair_col(int c, int w, int2 pq) {
 }
 
 // ----------------------------------------------------- FP64 building blocks
-// Division and square roots by the hardware reciprocal (v_rcp_f64) and
-// reciprocal-square-root (v_rsq_f64) seeds, good to about 26 bits, refined by
-// Newton steps and a final residual correction.  For positive normal
-// operands these agree with the correctly rounded IEEE results (checked on
-// 10^6 random operands over 2^+-40); they are used where the operands are
-// known to lie well inside the normal range, and the IEEE operations
-// everywhere else.
-__device__ __forceinline__ double nrcp(double b) {
+// Correctly rounded division, reciprocal and square root for the inner
+// rotations, built from the hardware reciprocal (v_rcp_f64) and reciprocal
+// square root (v_rsq_f64) seeds: Newton steps and a residual correction with
+// fused multiply-adds (Markstein's scheme) bring the result within one ulp,
+// and a final exact rounding test picks between it and its neighbour.  Valid
+// for positive normal operands whose results and residuals stay in the
+// normal range (the kernels use them only inside [2^-900, 2^900]); the IEEE
+// operations are used everywhere else.
+//
+// The rounding test.  Let x be within one ulp of the exact result z.  For
+// the reciprocal and the quotient the residual e = 1 - b x (a - b x) is an
+// integer multiple of the product grain of b and x that is smaller in
+// magnitude than b ulp(x), i.e. it has at most 53 significant bits, so the
+// fma computes it exactly; so does it for the neighbour x' of x on z's side,
+// which lies on the other side of z or on it.  The nearer of x and x' is the
+// one with the smaller |residual|, and neither z = 1/b nor z = a/b is ever
+// the exact midpoint of two doubles (it would need 54 significant bits in a
+// or in 1), so the choice is the correctly rounded result.
+
+__device__ __forceinline__ double step_bits(double x, bool up) {
+    return __builtin_bit_cast(double, __builtin_bit_cast(long long, x) + (up ? 1LL : -1LL));
+}
+
+// Reciprocal of a positive b within one ulp: two Newton steps from the seed.
+__device__ __forceinline__ double nrcp_1ulp(double b) {
     double y = __builtin_amdgcn_rcp(b);
     double e = fma(-b, y, 1.0);
     y = fma(y, e, y);
     e = fma(-b, y, 1.0);
     return fma(y, e, y);
 }
-__device__ __forceinline__ double ndiv(double a, double b) {
-    const double y = nrcp(b);
-    const double q = a * y;
-    const double r = fma(-b, q, a);
-    return fma(r, y, q);
+// Correctly rounded 1/b for a positive b.
+__device__ __forceinline__ double nrcp(double b) {
+    const double y = nrcp_1ulp(b);
+    const double e = fma(-b, y, 1.0);
+    const double yn = step_bits(y, e > 0.0);
+    const double en = fma(-b, yn, 1.0);
+    return fabs(en) < fabs(e) ? yn : y;
 }
+// Correctly rounded a/b (any signs): the quotient of the magnitudes by the
+// reciprocal and one residual correction, the rounding test, then the sign.
+__device__ __forceinline__ double ndiv(double a, double b) {
+    const double aa = fabs(a), bb = fabs(b);
+    const double y = nrcp_1ulp(bb);
+    double q = aa * y;
+    double r = fma(-bb, q, aa);
+    q = fma(r, y, q);
+    r = fma(-bb, q, aa);
+    const double qn = step_bits(q, r > 0.0);
+    const double rn = fma(-bb, qn, aa);
+    q = fabs(rn) < fabs(r) ? qn : q;
+    const long long sign =
+        (__builtin_bit_cast(long long, a) ^ __builtin_bit_cast(long long, b)) & (1LL << 63);
+    return __builtin_bit_cast(double, __builtin_bit_cast(long long, q) | sign);
+}
+// Correctly rounded sqrt(u) for a positive u.  The coupled iteration for the
+// root s and half its reciprocal h and a residual correction give s within
+// one ulp.  Rounding test: with s+ and s- the neighbours of s, sqrt(u) lies
+// above the midpoint of s and s+ iff d = u - s^2 > s (s+ - s), and below the
+// midpoint of s- and s iff d <= -s (s - s-) (the squared half ulps are
+// below the grain of d; s (s+ - s) is exact and has fewer than 53
+// significant bits of that grain, so comparing the fma-rounded d with it
+// decides the same way as the exact d).
 __device__ __forceinline__ double nsqrt(double u) {
     const double y = __builtin_amdgcn_rsq(u);
     double s = u * y, h = 0.5 * y;
     const double r = fma(-s, h, 0.5);
     s = fma(s, r, s);
     h = fma(h, r, h);
-    const double d = fma(-s, s, u);
-    return fma(d, h, s);
+    double d = fma(-s, s, u);
+    s = fma(d, h, s);
+    const double su = step_bits(s, true), sd = step_bits(s, false);
+    d = fma(-s, s, u);
+    const double up = s * (su - s), dn = s * (s - sd);
+    const double t = d > up ? su : s;
+    return d <= -dn ? sd : t;
 }
 
 // 1/sqrt(u) and sqrt(u) for a positive finite u, normal or subnormal: u is

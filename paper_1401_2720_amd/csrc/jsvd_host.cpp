@@ -36,9 +36,11 @@ struct jsvd_handle_s {
     hipStream_t stream = nullptr;
     void *ws = nullptr;          // device workspace of gesvd / hsvd / backward
     size_t ws_bytes = 0;
-    void *bws = nullptr;         // device workspace of the batched call, never freed
-    size_t bws_bytes = 0;        // while the handle lives except to grow it
-    bool bws_captured = false;   // a graph capture used bws: it must not move
+    void *bws = nullptr;         // device workspace of the batched call
+    size_t bws_bytes = 0;
+    bool bws_captured = false;   // a graph capture used bws: it must not be freed
+    std::vector<void *> bws_retired;  // captured workspaces replaced by larger ones,
+                                      // kept for their graphs until jsvd_destroy
     unsigned long long *host_counters = nullptr;  // pinned, kHostSlots words
     std::map<std::pair<int, int>, DeviceTable> block_tables;  // (order, kind) -> int2[]
     std::map<std::pair<int, int>, DeviceTable> inner_tables;  // (bw, kind) -> uchar[]
@@ -71,17 +73,24 @@ namespace {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// The batched call's workspace: grows like the other one, except while the
-// stream is being captured or after a capture used it (the graph holds its
-// address), when a call that needs more gets JSVD_NO_MEMORY.
+// The batched call's workspace grows when a call needs more.  While the
+// stream is being captured it cannot (no allocation there): such a call gets
+// JSVD_NO_MEMORY.  A workspace that a capture used is never freed before
+// jsvd_destroy, since the graph holds its address: growing then allocates a
+// new one and keeps the old one aside.
 int ensure_batch_workspace(jsvd_handle_s *h, size_t bytes, bool capturing) {
     if (bytes <= h->bws_bytes) return JSVD_OK;
-    if (capturing || h->bws_captured) return JSVD_NO_MEMORY;
+    if (capturing) return JSVD_NO_MEMORY;
     if (h->bws) {
-        if (hipStreamSynchronize(h->stream) != hipSuccess) return JSVD_HIP_ERROR;
-        (void)hipFree(h->bws);
+        if (h->bws_captured) {
+            h->bws_retired.push_back(h->bws);
+        } else {
+            if (hipStreamSynchronize(h->stream) != hipSuccess) return JSVD_HIP_ERROR;
+            (void)hipFree(h->bws);
+        }
         h->bws = nullptr;
         h->bws_bytes = 0;
+        h->bws_captured = false;
     }
     if (hipMalloc(&h->bws, bytes) != hipSuccess) {
         h->bws = nullptr;
@@ -817,6 +826,7 @@ int jsvd_destroy(jsvd_handle_t h) {
     (void)hipStreamSynchronize(h->stream);
     if (h->ws) (void)hipFree(h->ws);
     if (h->bws) (void)hipFree(h->bws);
+    for (void *p : h->bws_retired) (void)hipFree(p);
     for (auto &kv : h->block_tables) (void)hipFree(kv.second.ptr);
     for (auto &kv : h->inner_tables) (void)hipFree(kv.second.ptr);
     if (h->batch_tables) (void)hipFree(h->batch_tables);

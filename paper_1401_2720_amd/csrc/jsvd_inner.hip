@@ -86,7 +86,7 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
         if (a.prev_pair_rot[vpair] == 0) return;
         const int64_t r0 = (int64_t)chunk * a.prev_rows;
         const int64_t r1 = min(a.n, r0 + (int64_t)a.prev_rows);
-        update_rows<BW, NWAVES, 1>(a.V, a.ldv, r0, r1, a.prev_pairs[vpair], a.w, a.n,
+        update_rows<BW, NWAVES, 1, true>(a.V, a.ldv, r0, r1, a.prev_pairs[vpair], a.w, a.n,
                                 a.prev_vprime + (size_t)vpair * BW * BW, R);
         return;
     }

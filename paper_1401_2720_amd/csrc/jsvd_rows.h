@@ -19,8 +19,11 @@ namespace {
 // are w consecutive columns of block P, then w of block Q; local columns
 // past n (padding) are neither loaded nor stored.  JB of the BW/16 result
 // tiles are accumulated at a time (fewer live registers for smaller JB).
+// NTV: non-temporal loads and stores, for V, which is not read again before
+// the next block sweep, so that it does not push G (read by the next Gram
+// and update kernels) out of the caches.
 // All 64 NW threads of the workgroup must call it (it contains a barrier).
-template <int BW, int NW, int JB>
+template <int BW, int NW, int JB, bool NTV = false>
 __device__ __forceinline__ void update_rows(double *X, int64_t ldx, int64_t r0, int64_t r1,
                                             int2 pq, int w, int64_t n, const double *vpr,
                                             double *vs) {
@@ -46,7 +49,10 @@ __device__ __forceinline__ void update_rows(double *X, int64_t ldx, int64_t r0, 
             const int c = 4 * ks + grp;
             const bool in_p = c < w;
             const int lc = in_p ? c : c - w;
-            b[ks] = (rv && lc < (in_p ? np : nq)) ? (in_p ? XP : XQ)[(int64_t)lc * ldx + row] : 0.0;
+            const double *src = (in_p ? XP : XQ) + (int64_t)lc * ldx + row;
+            b[ks] = (rv && lc < (in_p ? np : nq))
+                        ? (NTV ? __builtin_nontemporal_load(src) : *src)
+                        : 0.0;
         }
 #pragma unroll
         for (int j0 = 0; j0 < JT; j0 += JB) {
@@ -65,8 +71,13 @@ __device__ __forceinline__ void update_rows(double *X, int64_t ldx, int64_t r0, 
                     const int c = (j0 + jb) * 16 + grp + 4 * v;
                     const bool in_p = c < w;
                     const int lc = in_p ? c : c - w;
-                    if (rv && lc < (in_p ? np : nq))
-                        (in_p ? XP : XQ)[(int64_t)lc * ldx + row] = acc[jb][v];
+                    if (rv && lc < (in_p ? np : nq)) {
+                        double *dst = (in_p ? XP : XQ) + (int64_t)lc * ldx + row;
+                        if (NTV)
+                            __builtin_nontemporal_store(acc[jb][v], dst);
+                        else
+                            *dst = acc[jb][v];
+                    }
                 }
         }
     }

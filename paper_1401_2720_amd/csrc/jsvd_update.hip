@@ -22,8 +22,11 @@ __global__ __launch_bounds__(256) void update_kernel(StepArgs a) {
     const int64_t rows = isV ? a.n : a.m;
     const int64_t r0 = (int64_t)chunk * a.upd_rows;
     const int64_t r1 = min(rows, r0 + (int64_t)a.upd_rows);
-    update_rows<BW, 4, BW / 16>(isV ? a.V : a.G, isV ? a.ldv : a.ldg, r0, r1, a.pairs[pair], a.w, a.n,
-                       a.vprime + (size_t)pair * BW * BW, vs);
+    const double *vpr = a.vprime + (size_t)pair * BW * BW;
+    if (isV)
+        update_rows<BW, 4, BW / 16, true>(a.V, a.ldv, r0, r1, a.pairs[pair], a.w, a.n, vpr, vs);
+    else
+        update_rows<BW, 4, BW / 16>(a.G, a.ldg, r0, r1, a.pairs[pair], a.w, a.n, vpr, vs);
 }
 
 }  // namespace

@@ -5,9 +5,11 @@ graph capture, and the differentiable form's status handling.
     with the problem, and jsvd_reserve_batched lets the very first batched
     call be captured (it then allocates nothing);
   * a captured batched call keeps its workspace: a larger jsvd_gesvd, a
-    larger backward and a larger batched call after the capture do not move
-    it (the larger batched call is refused with JSVD_NO_MEMORY), and every
-    replay gives the same bits;
+    larger backward and a larger batched call after the capture do not free
+    it (the larger batched call runs in a new workspace), and every replay
+    gives the same bits;
+  * a batched call captured on a workspace too small for it is refused with
+    JSVD_NO_MEMORY (no allocation during capture);
   * the differentiable SVD raises when its forward does not converge.
 """
 import numpy as np
@@ -103,13 +105,42 @@ def test_capture_survives_larger_calls_on_the_same_handle():
     dA = jsvd.svd_backward(U, S, V, dS=torch.ones_like(S))
     torch.cuda.synchronize()
     assert bool(torch.isfinite(dA).all())
-    # a larger batched call would have to grow the captured workspace: refused
+    # a larger batched call grows the workspace into a new allocation; the
+    # captured one stays valid for its graph
     bigger = jsvd.Batch(_mats(400, 100, 200, 6))
-    with pytest.raises(jsvd.JsvdError) as e:
-        jsvd.gesvd_batched(bigger)
-    assert e.value.code == 6
+    jsvd.gesvd_batched(bigger)
+    torch.cuda.synchronize()
+    assert int(bigger.status.abs().sum()) == 0
     second = _replay(torch, batch, graph)
     assert all(torch.equal(x, y) for x, y in zip(first, second))
+    # and the larger batch gives the same bits as on a fresh handle
+    got = (bigger.A.clone(), bigger.S.clone(), bigger.V.clone())
+    from paper_1401_2720_amd import _binding as B
+    B._HANDLES.clear()
+    jsvd.gesvd_batched(bigger)
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(got, (bigger.A, bigger.S, bigger.V)))
+
+
+def test_capture_of_a_call_that_needs_more_workspace_is_refused():
+    torch = _torch()
+    import paper_1401_2720_amd as jsvd
+    small = jsvd.Batch(_mats(10, 8, 30, 9))
+    jsvd.gesvd_batched(small)
+    torch.cuda.synchronize()
+    bigger = jsvd.Batch(_mats(80, 100, 200, 10))
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    code = None
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            try:
+                jsvd.gesvd_batched(bigger, restore=False)
+            except jsvd.JsvdError as e:
+                code = e.code
+    torch.cuda.current_stream().wait_stream(side)
+    assert code == 6
 
 
 def test_differentiable_forward_raises_when_not_converged():

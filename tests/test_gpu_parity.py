@@ -243,9 +243,15 @@ def test_hsvd_matches_oracle(name, m, n, n_plus, shuffle, kw):
     # oracle on the column-permuted (partitioned) problem
     perm = np.concatenate([np.nonzero(J == 1)[0], np.nonzero(J == -1)[0]])
     ref = oracle.gesvj(G[:, perm], n_plus=npl)
+    # kappa_2(V) = ||V||_2 ||V^-1||_2 = ||V||_2^2 (V^-1 = J V^T J): the
+    # J-orthogonal transformations amplify rounding errors by up to that
+    # factor, on both sides; the measured ratio to the plain bar is printed
     vn2 = max(1.0, np.linalg.norm(V, 2) ** 2)
-    tol = vn2 * (1e-12 * ref["S"] + 1e-13 * ref["S"].max())
-    assert np.all(np.abs(S - ref["S"]) <= tol)
+    bar = 1e-12 * ref["S"] + 1e-13 * ref["S"].max()
+    ratio = float(np.max(np.abs(S - ref["S"]) / bar))
+    rel = float(np.max(np.abs(S - ref["S"]) / ref["S"]))
+    _say(f"  sigma: max rel err {rel:.2e}, err / plain bar {ratio:.3f}, ||V||_2^2 {vn2:.2f}")
+    assert ratio <= vn2
     jv = Jout.astype(np.float64)
     jin = J.astype(np.float64)
     vmax = max(1.0, np.max(np.abs(V)) ** 2)
