@@ -253,8 +253,9 @@ int jsvd_workspace_size(jsvd_handle_t h, int64_t m, int64_t n, const jsvd_opts *
 /*
  * Device workspace, in bytes, of jsvd_gesvd_batched for a batch of `batch`
  * problems within the bounds max_m, max_n (arguments as for that call;
- * opts may be NULL): the work order, the queue counters and one area of
- * max_m max_n + max_n^2 doubles per workgroup of the persistent launches.
+ * opts may be NULL): the work order and the queue counters (about 4 bytes
+ * per problem; the end of each problem permutes its columns in place
+ * through LDS).
  * Returns JSVD_OK, -1 if h is NULL, -2..-4 as jsvd_gesvd_batched, -5 for
  * invalid options, -6 if bytes is NULL.
  */

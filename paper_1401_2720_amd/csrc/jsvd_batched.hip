@@ -23,7 +23,7 @@
 // their global buffers.  A workgroup barrier separates p-steps.  At the end
 // of a problem the column norms give sigma, the workgroup ranks them
 // (non-increasing, ties by index) and gathers U = G Sigma^{-1} and V in that
-// order (through a per-workgroup scratch area for what is in global memory).
+// order (what is in global memory is permuted in place through LDS).
 #include "jsvd_device.h"
 
 namespace jsvd {
@@ -584,13 +584,42 @@ __device__ __forceinline__ int blocked_sweeps(double *G, double *V, int m, int n
 // The end of a problem: sigma_j = ||g_j||, the output order (non-increasing,
 // ties by index, NaN last), U = G Sigma^{-1} and V in that order, status
 // and sweeps.  Gw / Vw are the working copies (LDS or the global buffers;
-// in_lds / v_lds say which), G / V the global buffers.
+// in_lds / v_lds say which), G / V the global buffers.  A working copy in
+// global memory is permuted in place through LDS (lds, lds_cap doubles,
+// free at this point except for LDS working copies), a band of rows of all
+// columns at a time.
+template <int NT>
+__device__ __forceinline__ void permute_columns(double *X, int rows, int n, const int *perm,
+                                                const double *sig, double *lds, int64_t lds_cap) {
+    const int tid = threadIdx.x;
+    const int band = (int)min<int64_t>(rows, lds_cap / n);
+    for (int i0 = 0; i0 < rows; i0 += band) {
+        const int nr = min(band, rows - i0);
+        for (int e = tid; e < nr * n; e += NT) {
+            const int k = e / nr, i = e % nr;
+            lds[e] = X[(size_t)k * rows + i0 + i];
+        }
+        __syncthreads();
+        for (int e = tid; e < nr * n; e += NT) {
+            const int k = e / nr, i = e % nr, c = perm[k];
+            const double v = lds[(size_t)c * nr + i];
+            if (sig) {
+                const double sg = sig[c];
+                X[(size_t)k * rows + i0 + i] = sg > 0.0 ? v / sg : 0.0;
+            } else {
+                X[(size_t)k * rows + i0 + i] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <int NT>
 __device__ __forceinline__ void finish_problem(const BatchArgs &b, int id, int m, int n, double *G,
                                                double *V, const double *Gw, const double *Vw,
-                                               bool in_lds, bool v_lds, double *scratch,
-                                               int sweeps, int status, double *s_sig,
-                                               int *s_perm) {
+                                               bool in_lds, bool v_lds, double *lds,
+                                               int64_t lds_cap, int sweeps, int status,
+                                               double *s_sig, int *s_perm) {
     const int tid = threadIdx.x, x = tid & 31, group = tid >> 5;
     for (int j = group; j < n; j += NT / 32) {
         const double *g = Gw + (size_t)j * m;
@@ -609,28 +638,23 @@ __device__ __forceinline__ void finish_problem(const BatchArgs &b, int id, int m
         }
         s_perm[r] = j;
     }
-    const double *src = Gw;
-    if (!in_lds) {
-        for (int e = tid; e < m * n; e += NT) scratch[e] = G[e];
-        src = scratch;
-    }
-    const double *vsrc = Vw;
-    if (V && !v_lds) {
-        for (int e = tid; e < n * n; e += NT) scratch[(size_t)m * n + e] = V[e];
-        vsrc = scratch + (size_t)m * n;
-    }
     __syncthreads();
-    double *S = b.S + b.s_off[id];
-    for (int e = tid; e < m * n; e += NT) {
-        const int k = e / m, i = e % m, c = s_perm[k];
-        const double sg = s_sig[c];
-        G[e] = sg > 0.0 ? src[(size_t)c * m + i] / sg : 0.0;
-    }
-    if (V)
+    // working copies in LDS are written out directly; the LDS is then free
+    if (in_lds)
+        for (int e = tid; e < m * n; e += NT) {
+            const int k = e / m, i = e % m, c = s_perm[k];
+            const double sg = s_sig[c];
+            G[e] = sg > 0.0 ? Gw[(size_t)c * m + i] / sg : 0.0;
+        }
+    if (V && v_lds)
         for (int e = tid; e < n * n; e += NT) {
             const int k = e / n, i = e % n;
-            V[e] = vsrc[(size_t)s_perm[k] * n + i];
+            V[e] = Vw[(size_t)s_perm[k] * n + i];
         }
+    __syncthreads();
+    if (!in_lds) permute_columns<NT>(G, m, n, s_perm, s_sig, lds, lds_cap);
+    if (V && !v_lds) permute_columns<NT>(V, n, n, s_perm, nullptr, lds, lds_cap);
+    double *S = b.S + b.s_off[id];
     for (int k = tid; k < n; k += NT) S[k] = s_sig[s_perm[k]];
     if (tid == 0) {
         if (b.status) b.status[id] = status;
@@ -650,7 +674,6 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs b) {
     __shared__ double s_tn[2][kBatchMaxN / 2];  // published rotations, by p-step parity
     __shared__ double s_cs[2][kBatchMaxN / 2];
     const int tid = threadIdx.x;
-    double *scratch = b.scratch + (size_t)blockIdx.x * b.scratch_per_wg;
 
     for (;;) {
         if (tid == 0) s_item = atomicAdd(&b.queue[1], 1);
@@ -689,8 +712,9 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs b) {
             sweeps = pointwise_sweeps<6, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged);
         else
             sweeps = pointwise_sweeps<0, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged);
-        finish_problem<kBatchThreads>(b, id, m, n, G, V, Gw, Vw, in_lds, v_lds, scratch, sweeps,
-                       converged ? 0 : JSVD_NOT_CONVERGED, s_sig, s_perm);
+        finish_problem<kBatchThreads>(b, id, m, n, G, V, Gw, Vw, in_lds, v_lds, lds_g,
+                                      b.lds_doubles, sweeps, converged ? 0 : JSVD_NOT_CONVERGED,
+                                      s_sig, s_perm);
     }
 }
 
@@ -705,7 +729,6 @@ void batched_blocked_kernel(BatchArgs b) {
     __shared__ double s_sig[kBatchMaxN];
     __shared__ int s_perm[kBatchMaxN];
     const int tid = threadIdx.x;
-    double *scratch = b.scratch + (size_t)blockIdx.x * b.scratch_per_wg;
     const int nblk = b.queue[2];
 
     for (;;) {
@@ -725,8 +748,8 @@ void batched_blocked_kernel(BatchArgs b) {
                                      b.tbl_off, b.tbls, lds_g);
         const int status = (r & kBlkNonfinite) ? JSVD_NONFINITE
                            : (r & kBlkConverged) ? 0 : JSVD_NOT_CONVERGED;
-        finish_problem<kBlkThreads>(b, id, m, n, G, V, G, V, false, false, scratch, r & 0xffff,
-                                    status, s_sig, s_perm);
+        finish_problem<kBlkThreads>(b, id, m, n, G, V, G, V, false, false, lds_g, kBlkLdsDoubles,
+                                    r & 0xffff, status, s_sig, s_perm);
     }
 }
 

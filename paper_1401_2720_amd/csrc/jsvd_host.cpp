@@ -701,26 +701,21 @@ int ensure_batch_tables(jsvd_handle_s *h) {
 }
 
 // Launch geometry and workspace carve-up of a batched call: the work order
-// histogram, the order itself, the queue counters and one scratch area per
-// workgroup of the larger of the two persistent grids.
+// histogram, the order itself and the queue counters.
 struct BatchPlan {
     int grid, bgrid;
-    int64_t scratch_per_wg;
-    size_t off_hist, off_order, off_queue, off_scratch, total;
+    size_t off_hist, off_order, off_queue, total;
 };
 
-BatchPlan batch_plan(const jsvd_handle_s *h, int64_t batch, int32_t max_m, int32_t max_n) {
+BatchPlan batch_plan(const jsvd_handle_s *h, int64_t batch) {
     BatchPlan p;
     const int cus = std::max(1, h->cu_count);
     p.grid = (int)std::min<int64_t>(std::max<int64_t>(batch, 1), cus);
     p.bgrid = (int)std::min<int64_t>(std::max<int64_t>(batch, 1), 2 * (int64_t)cus);
-    p.scratch_per_wg = (int64_t)max_m * max_n + (int64_t)max_n * max_n;
     p.off_hist = 0;
     p.off_order = align_up((size_t)(kBatchMaxN + 1) * sizeof(int), 256);
     p.off_queue = p.off_order + align_up((size_t)batch * sizeof(int32_t), 256);
-    p.off_scratch = p.off_queue + 256;
-    p.total = p.off_scratch +
-              (size_t)std::max(p.grid, p.bgrid) * (size_t)p.scratch_per_wg * sizeof(double);
+    p.total = p.off_queue + 256;
     return p;
 }
 
@@ -923,11 +918,15 @@ int32_t jsvd_batched_block_min_n(jsvd_handle_t h) {
     return h->tuning.batch_block_min_n ? h->tuning.batch_block_min_n : kBatchBlockMinN;
 }
 
-int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t max_n,
+}  // extern "C"
+
+namespace {
+
+// Arguments of a batched call (jsvd_gesvd_batched's numbering).
+int check_batched_args(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t max_n,
                        const int32_t *m, const int32_t *n, const int64_t *a_off,
-                       const int64_t *s_off, const int64_t *v_off, double *A, double *S,
-                       double *V, const jsvd_opts *opts, int32_t *status, int32_t *sweeps) {
-    const jsvd_opts o = opts ? *opts : defaults();
+                       const int64_t *s_off, const int64_t *v_off, const double *A,
+                       const double *S, const double *V, const jsvd_opts &o) {
     int rc0 = check_batched_sizes(h, batch, max_m, max_n);
     if (rc0) return rc0;
     if (!m) return -5;
@@ -939,25 +938,17 @@ int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t ma
     if (!S) return -11;
     if (o.want_v && !V) return -12;
     if (o.max_sweeps < 1) return -13;
-    if (batch == 0) return JSVD_OK;
-    if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
-    hipStream_t st = h->stream;
-    const bool capturing = stream_capturing(st);
-    if (!h->batch_tables) {
-        if (capturing) return JSVD_NO_MEMORY;
-        int rc = ensure_batch_tables(h);
-        if (rc) return rc;
-    }
-    const BatchPlan bp = batch_plan(h, batch, max_m, max_n);
-    const int grid = bp.grid, bgrid = bp.bgrid;
-    const int64_t scratch_per_wg = bp.scratch_per_wg;
-    const size_t off_hist = bp.off_hist, off_order = bp.off_order, off_queue = bp.off_queue,
-                 off_scratch = bp.off_scratch;
-    int rc = ensure_batch_workspace(h, bp.total, capturing);
-    if (rc) return rc;
-    if (capturing) h->bws_captured = true;
-    char *ws = static_cast<char *>(h->bws);
+    return JSVD_OK;
+}
 
+// Enqueue the batched solve with its workspace at ws (batch_plan(h,
+// batch).total bytes): the work-order kernels, then the two persistent
+// launches.  Allocates nothing.
+int launch_batched_solve(jsvd_handle_s *h, int64_t batch, int32_t max_n, const int32_t *m,
+                         const int32_t *n, const int64_t *a_off, const int64_t *s_off,
+                         const int64_t *v_off, double *A, double *S, double *V,
+                         const jsvd_opts &o, int32_t *status, int32_t *sweeps, char *ws) {
+    const BatchPlan bp = batch_plan(h, batch);
     BatchArgs b;
     b.count = batch;
     b.m = m;
@@ -968,18 +959,19 @@ int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t ma
     b.A = A;
     b.S = S;
     b.V = o.want_v ? V : nullptr;
-    b.order = reinterpret_cast<int32_t *>(ws + off_order);
-    b.queue = reinterpret_cast<int *>(ws + off_queue);
+    b.order = reinterpret_cast<int32_t *>(ws + bp.off_order);
+    b.queue = reinterpret_cast<int *>(ws + bp.off_queue);
     b.tbl_order = static_cast<const int *>(h->batch_meta);
     b.tbl_off = reinterpret_cast<const int64_t *>(
         static_cast<char *>(h->batch_meta) + align_up((kBatchMaxN + 1) * sizeof(int), 256));
     b.tbls = static_cast<const unsigned char *>(h->batch_tables);
-    b.scratch = reinterpret_cast<double *>(ws + off_scratch);
-    b.scratch_per_wg = scratch_per_wg;
     b.max_sweeps = o.max_sweeps;
     b.status = status;
     b.sweeps = sweeps;
     b.lds_doubles = h->batch_lds / (int64_t)sizeof(double);
+    // the end of a problem permutes its columns through LDS, a band of rows
+    // of all columns at a time
+    if (b.lds_doubles < kBatchMaxN) return JSVD_HIP_ERROR;
     b.g_groups = h->tuning.batch_g_groups ? h->tuning.batch_g_groups : 16;
     {
         const int mn = h->tuning.batch_block_min_n ? h->tuning.batch_block_min_n
@@ -987,9 +979,36 @@ int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t ma
         const bool room = b.lds_doubles >= kBatchBlockLds;
         b.blk_min_n = (room && mn <= kBatchMaxN) ? mn : 0;
     }
-    HIP_TRY(launch_batched(b, grid, bgrid, max_n, reinterpret_cast<int *>(ws + off_hist),
-                           reinterpret_cast<int32_t *>(ws + off_order), st));
+    HIP_TRY(launch_batched(b, bp.grid, bp.bgrid, max_n, reinterpret_cast<int *>(ws + bp.off_hist),
+                           reinterpret_cast<int32_t *>(ws + bp.off_order), h->stream));
     return JSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t max_n,
+                       const int32_t *m, const int32_t *n, const int64_t *a_off,
+                       const int64_t *s_off, const int64_t *v_off, double *A, double *S,
+                       double *V, const jsvd_opts *opts, int32_t *status, int32_t *sweeps) {
+    const jsvd_opts o = opts ? *opts : defaults();
+    const int rc0 = check_batched_args(h, batch, max_m, max_n, m, n, a_off, s_off, v_off, A, S,
+                                       V, o);
+    if (rc0) return rc0;
+    if (batch == 0) return JSVD_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
+    const bool capturing = stream_capturing(h->stream);
+    if (!h->batch_tables) {
+        if (capturing) return JSVD_NO_MEMORY;
+        int rc = ensure_batch_tables(h);
+        if (rc) return rc;
+    }
+    int rc = ensure_batch_workspace(h, batch_plan(h, batch).total, capturing);
+    if (rc) return rc;
+    if (capturing) h->bws_captured = true;
+    return launch_batched_solve(h, batch, max_n, m, n, a_off, s_off, v_off, A, S, V, o, status,
+                                sweeps, static_cast<char *>(h->bws));
 }
 
 int jsvd_svd_backward(jsvd_handle_t h, int64_t batch, int64_t m, int64_t n, const double *U,
@@ -1156,7 +1175,7 @@ int jsvd_workspace_size_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, i
     if (rc) return rc;
     if (o.max_sweeps < 1) return -5;
     if (!bytes) return -6;
-    *bytes = batch_plan(h, batch, max_m, max_n).total;
+    *bytes = batch_plan(h, batch).total;
     return JSVD_OK;
 }
 
@@ -1168,7 +1187,7 @@ int jsvd_reserve_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t 
     if (o.max_sweeps < 1) return -5;
     if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
     if ((rc = ensure_batch_tables(h))) return rc;
-    return ensure_batch_workspace(h, batch_plan(h, batch, max_m, max_n).total,
+    return ensure_batch_workspace(h, batch_plan(h, batch).total,
                                   stream_capturing(h->stream));
 }
 

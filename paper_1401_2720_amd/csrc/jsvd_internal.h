@@ -89,8 +89,6 @@ struct BatchArgs {
     const int *tbl_order;                       // device [kBatchMaxN + 1]: strategy order for n
     const int64_t *tbl_off;                     // device: offset of the order-N table at [N/2]
     const unsigned char *tbls;                  // device: concatenated zero-based pair tables
-    double *scratch;                            // device, per workgroup
-    int64_t scratch_per_wg;                     // doubles
     int max_sweeps;
     int32_t *status, *sweeps;                   // device, per problem (may be null)
     int64_t lds_doubles;                        // problems with m n <= this work in LDS
@@ -101,7 +99,7 @@ struct BatchArgs {
 hipError_t batched_set_lds(int bytes);
 
 // grid: workgroups of the pointwise kernel; bgrid: of the blocked kernel
-// (two fit on a CU); the scratch holds max(grid, bgrid) areas.
+// (two fit on a CU).
 hipError_t launch_batched(const BatchArgs &b, int grid, int bgrid, int max_n, int *hist,
                           int32_t *order, hipStream_t s);
 
