@@ -238,6 +238,28 @@ int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t ma
                        double *V, const jsvd_opts *opts, int32_t *status, int32_t *sweeps);
 
 /*
+ * The batched SVD of jsvd_gesvd_batched for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc): the same kernels and results, bit for bit, with
+ * the work order and queue counters in a fixed device array of the library
+ * instead of the handle's workspace, so that the call allocates nothing, not
+ * even on its first use.  The array holds JSVD_NOALLOC_MAX_BATCH problems
+ * (about 4 MiB; each device the library runs on keeps one until the process
+ * ends).  Arguments, ownership and return codes as for jsvd_gesvd_batched,
+ * except that batch > JSVD_NOALLOC_MAX_BATCH returns -2 (nothing enqueued)
+ * and JSVD_NO_MEMORY does not occur.  All calls on one device share its
+ * array, whose counters every call re-initialises with kernels on its own
+ * stream: two calls whose work can overlap on the same device (other
+ * streams, other handles, other threads) race; keep them on one stream.
+ */
+#define JSVD_NOALLOC_MAX_BATCH 1048576
+int jsvd_gesvd_batched_noalloc(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t max_n,
+                               const int32_t *m, const int32_t *n, const int64_t *a_off,
+                               const int64_t *s_off, const int64_t *v_off, double *A, double *S,
+                               double *V, const jsvd_opts *opts, int32_t *status,
+                               int32_t *sweeps);
+
+/*
  * Device workspace, in bytes, that jsvd_gesvd (or, for a J with both signs,
  * jsvd_hsvd) needs for an m x n problem with these options (NULL: defaults):
  * the pivot Gram partials, V'_pq slots and counters of the block sweeps

@@ -58,7 +58,7 @@ EXPORTS = ["jsvd_default_opts", "jsvd_create", "jsvd_set_stream", "jsvd_destroy"
            "jsvd_diag_fp64", "jsvd_kernel_timing", "jsvd_kernel_times", "jsvd_gesvd_batched",
            "jsvd_svd_backward", "jsvd_set_tuning", "jsvd_batched_block_min_n",
            "jsvd_workspace_size", "jsvd_workspace_size_batched", "jsvd_reserve_batched",
-           "jsvd_diag_refined"]
+           "jsvd_diag_refined", "jsvd_gesvd_batched_noalloc"]
 
 
 def lib():
@@ -88,6 +88,7 @@ def lib():
     L.jsvd_diag_fp64.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp]
     L.jsvd_gesvd_batched.argtypes = [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                      _vp, ctypes.POINTER(Opts), _vp, _vp]
+    L.jsvd_gesvd_batched_noalloc.argtypes = L.jsvd_gesvd_batched.argtypes
     L.jsvd_svd_backward.argtypes = [_vp, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.jsvd_set_tuning.argtypes = [_vp, ctypes.POINTER(Tuning)]
     L.jsvd_workspace_size.argtypes = [_vp, _i64, _i64, ctypes.POINTER(Opts),
@@ -102,7 +103,7 @@ def lib():
               "jsvd_gesvd", "jsvd_hsvd", "jsvd_strategy_table", "jsvd_diag_fp64",
               "jsvd_kernel_timing", "jsvd_kernel_times", "jsvd_gesvd_batched",
               "jsvd_svd_backward", "jsvd_workspace_size", "jsvd_workspace_size_batched",
-              "jsvd_reserve_batched", "jsvd_diag_refined"):
+              "jsvd_reserve_batched", "jsvd_diag_refined", "jsvd_gesvd_batched_noalloc"):
         getattr(L, f).restype = ctypes.c_int
     _LIB = L
     return L
@@ -477,8 +478,9 @@ class Batch:
         return U, S, V
 
 
-def gesvd_batched(batch, max_sweeps=30, restore=True):
-    """Run jsvd_gesvd_batched on a Batch on the current stream (asynchronous).
+def gesvd_batched(batch, max_sweeps=30, restore=True, noalloc=False):
+    """Run jsvd_gesvd_batched (noalloc=True: jsvd_gesvd_batched_noalloc) on a
+    Batch on the current stream (asynchronous).
 
     restore=True first copies the original inputs back into batch.A.
     """
@@ -490,14 +492,15 @@ def gesvd_batched(batch, max_sweeps=30, restore=True):
     if restore:
         batch.A.copy_(batch.A0)
     o = make_opts(max_sweeps=max_sweeps, want_v=batch.want_v)
-    rc = lib().jsvd_gesvd_batched(
+    name = "jsvd_gesvd_batched_noalloc" if noalloc else "jsvd_gesvd_batched"
+    rc = getattr(lib(), name)(
         h, batch.count, batch.max_m, batch.max_n, _vp(batch.m.data_ptr()),
         _vp(batch.n.data_ptr()), _vp(batch.a_off.data_ptr()), _vp(batch.s_off.data_ptr()),
         _vp(batch.v_off.data_ptr()) if batch.want_v else None, _vp(batch.A.data_ptr()),
         _vp(batch.S.data_ptr()), _vp(batch.V.data_ptr()) if batch.want_v else None,
         ctypes.byref(o), _vp(batch.status.data_ptr()), _vp(batch.sweeps.data_ptr()))
     if rc:
-        raise JsvdError(rc, "jsvd_gesvd_batched")
+        raise JsvdError(rc, name)
 
 
 def svd_backward(U, S, V, dU=None, dS=None, dV=None):

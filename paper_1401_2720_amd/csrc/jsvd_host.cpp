@@ -55,6 +55,7 @@ struct jsvd_handle_s {
     void *qr_ws = nullptr;          // QR preprocessing workspace (kept apart from ws,
     size_t qr_ws_bytes = 0;         // which the Jacobi solve of R^T may reallocate)
     int qr_resident = 0;            // QR panel workgroups that can be resident at once
+    void *noalloc_scratch = nullptr;  // device address of this device's fixed scratch
     // per-kernel timing (measurement aid): 4 events per p-step
     bool timing = false;
     int timing_stride = 1;          // time every timing_stride-th p-step
@@ -707,16 +708,45 @@ struct BatchPlan {
     size_t off_hist, off_order, off_queue, total;
 };
 
+constexpr size_t batch_off_order() { return ((kBatchMaxN + 1) * sizeof(int) + 255) / 256 * 256; }
+constexpr size_t batch_off_queue(int64_t batch) {
+    return batch_off_order() + ((size_t)batch * sizeof(int32_t) + 255) / 256 * 256;
+}
+constexpr size_t batch_ws_bytes(int64_t batch) { return batch_off_queue(batch) + 256; }
+
 BatchPlan batch_plan(const jsvd_handle_s *h, int64_t batch) {
     BatchPlan p;
     const int cus = std::max(1, h->cu_count);
     p.grid = (int)std::min<int64_t>(std::max<int64_t>(batch, 1), cus);
     p.bgrid = (int)std::min<int64_t>(std::max<int64_t>(batch, 1), 2 * (int64_t)cus);
     p.off_hist = 0;
-    p.off_order = align_up((size_t)(kBatchMaxN + 1) * sizeof(int), 256);
-    p.off_queue = p.off_order + align_up((size_t)batch * sizeof(int32_t), 256);
-    p.total = p.off_queue + 256;
+    p.off_order = batch_off_order();
+    p.off_queue = batch_off_queue(batch);
+    p.total = batch_ws_bytes(batch);
     return p;
+}
+
+// ------------------------------------------- allocation-free batched call
+// The work order and queue counters of jsvd_gesvd_batched_noalloc live in
+// this fixed device array (each device the library runs on holds its own
+// copy until the process ends).  In host code `scratch` only names the
+// symbol: its device address comes from hipGetSymbolAddress, taken once per
+// device when a handle is created there, and only that address is passed on.
+constexpr size_t kNoAllocScratchBytes = batch_ws_bytes(JSVD_NOALLOC_MAX_BATCH);
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mutex;
+std::map<int, void *> g_scratch_ptr;  // device -> address of its scratch
+
+// With `device` current: the device address of its scratch (null on error).
+void *device_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) return it->second;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) ptr = nullptr;
+    if (ptr) g_scratch_ptr.emplace(device, ptr);
+    return ptr;
 }
 
 int check_batched_sizes(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t max_n) {
@@ -781,6 +811,8 @@ int jsvd_create(jsvd_handle_t *h, void *hip_stream) {
         hipSuccess)
         p->cu_count = 0;
     p->qr_resident = qr_panel_resident(p->cu_count);
+    // the fixed scratch of the allocation-free batched call on this device
+    p->noalloc_scratch = device_scratch(p->device);
     // the batched path's strategy tables, so that its first call need not
     // allocate them
     const int rc = ensure_batch_tables(p);
@@ -1009,6 +1041,24 @@ int jsvd_gesvd_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t ma
     if (capturing) h->bws_captured = true;
     return launch_batched_solve(h, batch, max_n, m, n, a_off, s_off, v_off, A, S, V, o, status,
                                 sweeps, static_cast<char *>(h->bws));
+}
+
+int jsvd_gesvd_batched_noalloc(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t max_n,
+                               const int32_t *m, const int32_t *n, const int64_t *a_off,
+                               const int64_t *s_off, const int64_t *v_off, double *A, double *S,
+                               double *V, const jsvd_opts *opts, int32_t *status,
+                               int32_t *sweeps) {
+    const jsvd_opts o = opts ? *opts : defaults();
+    const int rc0 = check_batched_args(h, batch, max_m, max_n, m, n, a_off, s_off, v_off, A, S,
+                                       V, o);
+    if (rc0) return rc0;
+    if (batch > JSVD_NOALLOC_MAX_BATCH) return -2;
+    if (batch == 0) return JSVD_OK;
+    if (!h->noalloc_scratch || !h->batch_tables) return JSVD_HIP_ERROR;
+    if (batch_plan(h, batch).total > kNoAllocScratchBytes) return -2;
+    if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
+    return launch_batched_solve(h, batch, max_n, m, n, a_off, s_off, v_off, A, S, V, o, status,
+                                sweeps, static_cast<char *>(h->noalloc_scratch));
 }
 
 int jsvd_svd_backward(jsvd_handle_t h, int64_t batch, int64_t m, int64_t n, const double *U,
