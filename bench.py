@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--max-inner-sweeps", type=int, default=0, help="0 = library's choice")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the oracle sample (0 = skip)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="leave the batched and differentiable forms out of the svd4096 line")
     ap.add_argument("--workload", default="svd4096", choices=["svd4096", "batched", "backward"],
                     help="svd4096: the benchmark line; batched / backward: the other forms")
     return ap.parse_args()
@@ -53,10 +55,16 @@ def kernel_roofline(name, avg_ms, per_launch):
     of dependent FP64 vector operations, against the FP64 vector peak."""
     sec = avg_ms * 1e-3
     if name == "inner":
-        achieved = per_launch["inner_flops"] / sec / 1e12
+        # achieved: the inner Jacobi's algorithmic cost per launch, 36 w n^2
+        # s_in flops per block sweep over the nb - 1 launches of a sweep;
+        # achieved_actual: the same work counted from the run's rotations,
+        # inner sweeps and Cholesky factorizations
+        achieved = per_launch["inner_flops_model"] / sec / 1e12
+        actual = per_launch["inner_flops"] / sec / 1e12
         return {"kernel": "inner", "bound": "alu", "achieved": achieved,
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                "traffic": None,
+                "traffic": None, "achieved_actual": actual,
+                "frac_actual": actual / PEAK_FP64_TFLOPS,
                 "v_stream_gbs": per_launch["inner_v_bytes"] / sec / 1e9}
     flops = per_launch[name + "_flops"]
     bytes_ = per_launch[name + "_bytes"]
@@ -88,9 +96,24 @@ def measured_traffic(kernel_name, w):
     return entry["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(A, sweeps, target_s):
+def oracle_sweeps(default):
+    """Sweeps the oracle takes to converge on the benchmark matrix (recorded
+    by tests/golden/make_sigma_golden.py in the header of its output)."""
+    path = os.path.join(ROOT, "tests", "golden", "sigma_gaussian4096_seed2.txt")
+    try:
+        with open(path) as f:
+            for line in f:
+                if line.startswith("# oracle:") and " sweeps," in line:
+                    return int(line.split(" sweeps,")[0].split()[-1]), "oracle's own"
+    except OSError:
+        pass
+    return default, "the GPU run's"
+
+
+def cpu_baseline(A, gpu_sweeps, target_s):
     """The oracle (round-robin OpenMP ordering) on the first rounds of the
-    first sweep of the same matrix, scaled to seconds per SVD."""
+    first sweep of the same matrix, scaled to seconds per SVD with the
+    number of sweeps the oracle needs on it."""
     import numpy as np
     import oracle
     n = A.shape[1]
@@ -105,16 +128,19 @@ def cpu_baseline(A, sweeps, target_s):
     t = time.perf_counter() - t0
     per_sweep = t / rounds * rounds_per_sweep
     del np
+    sweeps, whose = oracle_sweeps(gpu_sweeps) if n == 4096 else (gpu_sweeps, "the GPU run's")
     return {"value": per_sweep * sweeps, "unit": "s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": (f"round-robin oracle, first {rounds} of {rounds_per_sweep} rounds of "
                        f"sweep 1 on the same {A.shape[0]}x{n} input ({t:.1f} s); per-sweep "
-                       f"time x {sweeps} sweeps (the GPU run's sweep count)")}
+                       f"time x {sweeps} sweeps ({whose} sweep count on this matrix)")}
 
 
-def bench_batched(args):
-    """10,000 uneven problems (n ~ U{8..128}, m = n + U{0..64}, 20 % graded),
-    one persistent launch captured in a HIP graph and replayed."""
+def measure_batched(steps, warmup, cpu_seconds, plain_sample=200):
+    """10,000 uneven problems (n ~ U{8..128}, m = n + U{0..64}, 20 % graded)
+    in the two persistent launches, captured in a HIP graph and replayed;
+    beside it the plain form (one jsvd_gesvd per problem, synchronising per
+    sweep) on a fixed seeded sample of the same problems."""
     import numpy as np
     import torch
 
@@ -126,24 +152,20 @@ def bench_batched(args):
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        for _ in range(max(1, args.warmup)):
+        for _ in range(max(1, warmup)):
             jsvd.gesvd_batched(b)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         jsvd.gesvd_batched(b)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         graph.replay()
-    stop.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms = (t1 - t0) / args.steps * 1e3
+    ms = (t1 - t0) / steps * 1e3
     sw = b.sweeps.cpu().numpy().astype(np.float64)
     m = b.m_host.astype(np.float64)
     n = b.n_host.astype(np.float64)
@@ -163,13 +185,30 @@ def bench_batched(args):
     flops = float(np.sum(sw * np.where(blk, f_blk, f_pt)))
     achieved = flops / (ms * 1e-3) / 1e12
     status = int(b.status.abs().sum())
+    del graph
+
+    # the plain form on a seeded sample of the same problems, one call each
+    mats = data["mats"]
+    pick = np.sort(inputs.rng(55).choice(len(mats), size=min(plain_sample, len(mats)),
+                                         replace=False))
+    dev_mats = [torch.from_numpy(mats[i]).cuda() for i in pick]
+    for A in dev_mats[:4]:
+        jsvd.gesvd(A)
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for A in dev_mats:
+        jsvd.gesvd(A)
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - p0) / len(dev_mats)
+    plain = {"svds_per_s": 1.0 / plain_s, "sample": f"{len(dev_mats)} seeded problems of the "
+             "10000, one jsvd_gesvd each (synchronises once per sweep)",
+             "batched_over_plain": (10000 / (ms * 1e-3)) * plain_s}
     cpu = None
-    if args.cpu_seconds > 0:
+    if cpu_seconds > 0:
         # oracle on the problems in index order (one per OpenMP thread) until
         # the sample reaches the target time, scaled to problems per second
-        mats = data["mats"]
         done, t_cpu, k = 0, 0.0, 64
-        while t_cpu < args.cpu_seconds and done < len(mats):
+        while t_cpu < cpu_seconds and done < len(mats):
             chunk = mats[done:done + k]
             c0 = time.perf_counter()
             oracle.gesvj_many(chunk)
@@ -178,24 +217,35 @@ def bench_batched(args):
             k *= 2
         cpu = {"value": done / t_cpu, "unit": "SVDs/s", "cores": oracle.num_threads(),
                "kind": "oracle", "sample": f"first {done} of the 10000 problems ({t_cpu:.1f} s)"}
-    out = {"metric": "batched small SVDs/s", "value": 10000 / (ms * 1e-3), "unit": "SVDs/s",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+    return {"svds_per_s": 10000 / (ms * 1e-3), "ms_per_batch": ms, "steps": steps,
+            "sweeps_mean": float(sw.mean()), "sweeps_max": int(sw.max()),
+            "not_converged": status,
+            "roofline": {"kernel": "batched", "bound": "alu", "achieved": achieved,
+                         "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                         "algorithmic_flops_per_launch": flops},
+            "plain_form": plain, "cpu_baseline": cpu}
+
+
+def bench_batched(args):
+    r = measure_batched(args.steps, args.warmup, args.cpu_seconds)
+    out = {"metric": "batched small SVDs/s", "value": r["svds_per_s"], "unit": "SVDs/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_batch"],
            "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": "batched_10000_ragged_n8-128", "seed": 5, "graph": True,
-                      "sweeps_mean": float(sw.mean()), "sweeps_max": int(sw.max()),
-                      "not_converged": status},
-           "roofline": {"kernel": "batched", "bound": "alu", "achieved": achieved,
-                        "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                        "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                        "algorithmic_flops_per_launch": flops},
-           "cpu_baseline": cpu}
+                      "sweeps_mean": r["sweeps_mean"], "sweeps_max": r["sweeps_max"],
+                      "not_converged": r["not_converged"]},
+           "roofline": r["roofline"], "plain_form": r["plain_form"],
+           "cpu_baseline": r["cpu_baseline"]}
     print(json.dumps(out), flush=True)
 
 
-def bench_backward(args):
+def measure_backward(steps, warmup):
     """Forward + backward of the differentiable SVD: 256 x (64 x 64) and one
-    1024 x 1024, loss sum w_i s_i + ||U_k V_k^T o W||_F^2, k = 8."""
+    1024 x 1024, loss sum w_i s_i + ||U_k V_k^T o W||_F^2, k = 8; beside it
+    the plain forward (jsvd_gesvd_batched / jsvd_gesvd through the binding,
+    no autograd) on the same matrices."""
     import torch
 
     import paper_1401_2720_amd as jsvd
@@ -207,8 +257,8 @@ def bench_backward(args):
         A = torch.from_numpy(A).cuda()
         w = torch.from_numpy(w).cuda()
         W = torch.from_numpy(W).cuda()
-        fwd, bwd = [], []
-        for it in range(args.warmup + args.steps):
+        fwd, bwd, plain = [], [], []
+        for it in range(warmup + steps):
             X = A.clone().requires_grad_(True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -220,21 +270,39 @@ def bench_backward(args):
             L.backward()
             torch.cuda.synchronize()
             t2 = time.perf_counter()
-            if it >= args.warmup:
+            if A.dim() == 3:
+                batch = jsvd.Batch.from_uniform(A)
+                torch.cuda.synchronize()
+                t3 = time.perf_counter()
+                jsvd.gesvd_batched(batch, restore=False)
+            else:
+                torch.cuda.synchronize()
+                t3 = time.perf_counter()
+                jsvd.gesvd(A)
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            if it >= warmup:
                 fwd.append(t1 - t0)
                 bwd.append(t2 - t1)
+                plain.append(t4 - t3)
         b = A.shape[0] if A.dim() == 3 else 1
         n = A.shape[-1]
-        res[name] = {"forward_ms": 1e3 * sum(fwd) / len(fwd),
-                     "loss_backward_ms": 1e3 * sum(bwd) / len(bwd),
+        f, g, p = (1e3 * sum(x) / len(x) for x in (fwd, bwd, plain))
+        res[name] = {"forward_ms": f, "loss_backward_ms": g, "plain_forward_ms": p,
+                     "forward_backward_over_plain": (f + g) / p,
                      "backward_gemm_flops": b * 8.0 * n ** 3}
     total_ms = sum(v["forward_ms"] + v["loss_backward_ms"] for v in res.values())
-    out = {"metric": "differentiable SVD forward+backward time", "value": total_ms / 1e3,
+    return {"forward_backward_s": total_ms / 1e3, "parts": res}
+
+
+def bench_backward(args):
+    r = measure_backward(args.steps, args.warmup)
+    out = {"metric": "differentiable SVD forward+backward time", "value": r["forward_backward_s"],
            "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": total_ms, "higher_is_better": False, "scaling": "strong",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "ms_per_step": r["forward_backward_s"] * 1e3, "higher_is_better": False,
+           "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "svd_backward_256x64x64_and_1024x1024", "seed": 6, "k": 8,
-                      "parts": res},
+                      "parts": r["parts"]},
            "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
@@ -328,6 +396,9 @@ def main():
         "update_bytes": upd_per_launch * m * bw * 8.0 * 2,
         "inner_flops": (isw_per_launch * (bw - 1) * (bw // 2) * 6.0 * bw
                         + rot_per_launch * 12.0 * bw + npairs * bw ** 3 / 3.0),
+        # the survey's model of the inner Jacobi: 36 w n^2 s_in flops per
+        # block sweep (s_in inner sweeps per pivot pair), nb - 1 launches
+        "inner_flops_model": 36.0 * w * n * n * (isw_per_launch / npairs) / steps_per_sweep,
         "inner_v_flops": upd_per_launch * 2.0 * n * bw * bw,
         "inner_v_bytes": upd_per_launch * n * bw * 8.0 * 2,
     }
@@ -369,6 +440,19 @@ def main():
     if args.cpu_seconds > 0:
         cpu = cpu_baseline(A_host, int(np.median(sweeps)), args.cpu_seconds)
 
+    # the two other forms, measured in the same process after the timed
+    # region: the batched solve (graph replay) against the plain form on a
+    # sample of its problems, and the differentiable SVD against the plain
+    # forward
+    forms = None
+    if not args.no_forms:
+        torch.cuda.synchronize()
+        bat = measure_batched(steps=5, warmup=1, cpu_seconds=0)
+        bwd = measure_backward(steps=3, warmup=1)
+        forms = {"batched_svds_per_s": bat["svds_per_s"], "batched": bat,
+                 "differentiable_forward_backward_s": bwd["forward_backward_s"],
+                 "differentiable": bwd["parts"]}
+
     out = {
         "metric": "FP64 SVD time (s) at n=4096",
         "value": ms_per_step / 1e3,
@@ -389,6 +473,9 @@ def main():
         "roofline": roof,
         "rooflines": rooflines,
         "mfma": mfma,
+        "gram_update_mfma_frac": (gram_exec + per_launch["update_flops"])
+        / ((avg["gram"] + avg["update"]) * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+        "forms": forms,
         "kernels_avg_us": {k: avg[k] * 1e3 for k in avg},
         "kernels_share": {k: kt[k][0] / max(sum(v[0] for v in kt.values()), 1e-9) for k in kt},
         "accuracy": {"fro2_rel": abs(sum_s2 - fro2) / fro2, "orth_u": orth_u, "orth_v": orth_v},

@@ -58,6 +58,10 @@ extern "C" {
 #define JSVD_STRAT_R 1    /* p-strategy closest to row-cyclic, Definition 3.1 */
 #define JSVD_STRAT_CREV 2 /* reverse of the p-strategy closest to column-cyclic */
 #define JSVD_STRAT_C 3    /* p-strategy closest to column-cyclic */
+#define JSVD_STRAT_RR 4   /* round-robin (tournament) ordering, one of the comparison
+                             strategies of Section 6: pairs (1,2),(3,4),... first, then
+                             every index but the first moves one place round the ring
+                             (Brent and Luk's parallel ordering) */
 
 typedef struct jsvd_handle_s *jsvd_handle_t;
 

@@ -16,6 +16,9 @@ Definitions followed:
     last pair of the last p-step first).
   * R_n is the row-cyclic order (1,2),(1,3),...,(1,n),(2,3),...;
     C_n is the column-cyclic order (1,2),(1,3),(2,3),(1,4),(2,4),(3,4),...
+  * The round-robin ordering (a comparison strategy of Section 6; Brent and
+    Luk's parallel ordering): index 1 stays put, the others sit on a ring
+    that turns by one place per p-step; see round_robin().
 
 Pairs are one-based (i, j) with i < j, as in the paper.
 """
@@ -128,3 +131,28 @@ def is_pstrategy(steps, n):
                 return False
             seen.add((i, j))
     return len(seen) == n * (n - 1) // 2
+
+
+def round_robin(n):
+    """Round-robin ordering of even order n as p-steps of one-based pairs.
+
+    Index 1 is fixed; the other n - 1 indices sit on a ring, initially
+    3, 5, ..., n - 1, n, n - 2, ..., 2, which turns by one place per step
+    (entry i of step s is entry i - s of the initial ring, cyclically).
+    Step s pairs 1 with the ring's last entry and, for k = 1 .. n/2 - 1,
+    ring entry k - 1 with ring entry n - 2 - k (zero-based ring positions),
+    in that order; pairs are written (min, max).  Step 0 is (1,2), (3,4), ...
+    """
+    if n < 2 or n % 2:
+        raise ValueError("even order >= 2")
+    h = n // 2
+    ring0 = list(range(3, n, 2)) + list(range(n, 1, -2))
+    L = n - 1
+    out = []
+    for s in range(n - 1):
+        ring = [ring0[(i - s) % L] for i in range(L)]
+        step = [tuple(sorted((1, ring[L - 1])))]
+        for k in range(1, h):
+            step.append(tuple(sorted((ring[k - 1], ring[n - 2 - k]))))
+        out.append(step)
+    return out

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "libjsvd.so")
 
 _i32, _i64, _dbl, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 
-STRATEGIES = {"rrev": 0, "r": 1, "crev": 2, "c": 3}
+STRATEGIES = {"rrev": 0, "r": 1, "crev": 2, "c": 3, "rr": 4}
 STATUS = {0: "ok", 1: "not converged", 3: "non-finite value", 4: "HIP error",
           5: "equal singular values", 6: "out of device memory"}
 

@@ -759,7 +759,7 @@ int check_batched_sizes(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t m
 
 int check_opts(const jsvd_opts &o) {
     if (o.block_w != 0 && o.block_w != 16 && o.block_w != 32) return -1;
-    if (o.strategy < JSVD_STRAT_RREV || o.strategy > JSVD_STRAT_C) return -1;
+    if (o.strategy < JSVD_STRAT_RREV || o.strategy > JSVD_STRAT_RR) return -1;
     if (o.max_sweeps < 1 || o.max_inner_sweeps < 0) return -1;
     if (o.qr < 0 || o.qr > 2) return -1;
     if (o.scaled < 0 || o.scaled > 2) return -1;
@@ -929,7 +929,7 @@ int jsvd_hsvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda, con
 }
 
 int jsvd_strategy_table(int32_t order, int32_t kind, int32_t *pairs) {
-    if (kind < JSVD_STRAT_RREV || kind > JSVD_STRAT_C) return -2;
+    if (kind < JSVD_STRAT_RREV || kind > JSVD_STRAT_RR) return -2;
     if (!pairs) return -3;
     if (order < 2 || order % 2 || strategy_order(order) != order || order > 4096) return -1;
     Table t;

@@ -6,13 +6,16 @@
 // whose pairs, read step by step, have the lexicographically smallest
 // sequence of positions in O.  Algorithm 3.1 builds it by taking the
 // lexicographically first set of N/2 disjoint unused pairs that still lets
-// the remaining pairs be completed, backtracking otherwise.  It is only
+// the remaining pairs be completed, backtracking otherwise.  The round-robin
+// ordering, one of the strategies Section 6 compares against, is built
+// directly.  It is only
 // affordable for small orders, so (following Section 3) a table of order
 // 2^k * o is built from order 2o by k-1 expansions of Algorithm 3.2, which
 // turns every p-step of order N into two p-steps of order 2N.  The reverse
 // strategies list the pairs in the opposite order.
 #include "jsvd_internal.h"
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -136,6 +139,38 @@ Table expand(const Table &in, bool row_cyclic) {
     return out;
 }
 
+// Round-robin ordering of order N in Brent and Luk's layout: two rows of
+// N/2 places, pair k of a p-step joins top[k] and bot[k]; the first step
+// pairs (0,1), (2,3), ...; between steps top[0] stays and every other index
+// moves one place round the ring top[1] -> top[2] -> ... -> top[N/2-1] ->
+// bot[N/2-1] -> ... -> bot[0] -> top[1].  After N - 1 steps every pair has
+// met once.
+Table round_robin(int order) {
+    const int h = order / 2;
+    std::vector<int> top(h), bot(h);
+    for (int k = 0; k < h; ++k) {
+        top[k] = 2 * k;
+        bot[k] = 2 * k + 1;
+    }
+    Table t;
+    for (int s = 0; s + 1 < order; ++s) {
+        Step st;
+        for (int k = 0; k < h; ++k) st.push_back({std::min(top[k], bot[k]), std::max(top[k], bot[k])});
+        t.push_back(st);
+        if (h > 1) {
+            std::vector<int> nt(h), nb(h);
+            nt[0] = top[0];
+            nt[1] = bot[0];
+            for (int k = 2; k < h; ++k) nt[k] = top[k - 1];
+            for (int k = 0; k + 1 < h; ++k) nb[k] = bot[k + 1];
+            nb[h - 1] = top[h - 1];
+            top.swap(nt);
+            bot.swap(nb);
+        }
+    }
+    return t;
+}
+
 bool split_order(int order, int &k, int &o) {
     if (order < 2 || order % 2) return false;
     k = 0;
@@ -162,11 +197,16 @@ bool make_table(int order, int kind, Table &out) {
     static std::map<std::pair<int, int>, Table> cache;
     int k, o;
     if (!split_order(order, k, o) || order > 4096) return false;
-    if (kind < JSVD_STRAT_RREV || kind > JSVD_STRAT_C) return false;
+    if (kind < JSVD_STRAT_RREV || kind > JSVD_STRAT_RR) return false;
     std::lock_guard<std::mutex> lock(mu);
     auto it = cache.find({order, kind});
     if (it != cache.end()) {
         out = it->second;
+        return true;
+    }
+    if (kind == JSVD_STRAT_RR) {
+        cache[{order, kind}] = round_robin(order);
+        out = cache[{order, kind}];
         return true;
     }
     const bool row = (kind == JSVD_STRAT_R || kind == JSVD_STRAT_RREV);

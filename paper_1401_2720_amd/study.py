@@ -2,7 +2,8 @@
 
     python -m paper_1401_2720_amd.study [--quick] [--json OUT]
 
-For each input it runs every parallel strategy (R, Rrev, C, Crev; Section 3)
+For each input it runs every parallel strategy (R, Rrev, C, Crev; Section 3,
+and the round-robin ordering RR that Section 6 compares against)
 in the block-oriented (one inner sweep, M_s = 1) and the full-block (inner
 sweeps to convergence, at most 30) variant, and for the 4096 matrix both
 block widths, and prints sweeps, rotations, inner sweeps, the library's own
@@ -19,7 +20,7 @@ import numpy as np
 
 from . import inputs
 
-STRATEGIES = ("rrev", "r", "crev", "c")
+STRATEGIES = ("rrev", "r", "crev", "c", "rr")
 
 
 def _cases(quick):

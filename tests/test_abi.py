@@ -76,6 +76,12 @@ def test_tables_are_pstrategies(kind, order):
         assert [tuple(p) for p in t[-1].tolist()] == first[::-1]
 
 
+@pytest.mark.parametrize("order", [2, 4, 6, 8, 12, 16, 32, 64, 96, 128, 256, 4096])
+def test_round_robin_table_matches_oracle(order):
+    got = [[tuple(p) for p in st] for st in jsvd.strategy_table(order, "rr").tolist()]
+    assert got == ost.round_robin(order)
+
+
 def test_power_of_two_matches_oracle_64():
     got = [[tuple(p) for p in st] for st in jsvd.strategy_table(64, "r").tolist()]
     assert got == _closest(64, "R")
@@ -102,6 +108,7 @@ def test_bad_orders_rejected():
     assert L.jsvd_strategy_table(7, 0, buf.ctypes.data) == -1
     assert L.jsvd_strategy_table(26, 0, buf.ctypes.data) == -1
     assert L.jsvd_strategy_table(8, 9, buf.ctypes.data) == -2
+    assert L.jsvd_strategy_table(8, 5, buf.ctypes.data) == -2
     assert L.jsvd_strategy_table(8, 0, None) == -3
 
 

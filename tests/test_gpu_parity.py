@@ -108,6 +108,11 @@ CASES = [
     ("full_block_ragged300x231_w32", 300, 231, dict(block_w=32, max_inner_sweeps=30), "gauss"),
     ("full_block_ragged170x150_w16_c", 170, 150,
      dict(block_w=16, strategy="c", max_inner_sweeps=30), "gauss"),
+    # the round-robin ordering (a comparison strategy of Section 6) at both
+    # levels
+    ("round_robin_ragged300x200_w16", 300, 200, dict(block_w=16, strategy="rr"), "gauss"),
+    ("round_robin_full_block_graded256_w32", 256, 256,
+     dict(block_w=32, strategy="rr", max_inner_sweeps=30), "graded"),
 ]
 
 
@@ -224,6 +229,7 @@ HCASES = [
     ("hsvd130x100_random_J", 130, 100, None, True, dict(block_w=16)),
     ("hsvd128x128_p64_w32", 128, 128, 64, False, dict(block_w=32)),
     ("hsvd70x50_p17_ragged", 70, 50, 17, False, dict(block_w=16)),
+    ("hsvd180x150_round_robin_w32", 180, 150, None, True, dict(block_w=32, strategy="rr")),
 ]
 
 

@@ -83,3 +83,16 @@ def test_invalid_detected():
     bad[1][0], bad[2][0] = bad[2][0], bad[1][0]
     assert st.is_pstrategy(s, 6)
     assert not st.is_pstrategy([s[0]] * 5, 6)
+
+
+@pytest.mark.parametrize("name", ["RR4", "RR6"])
+def test_round_robin_golden(name):
+    tabs = _golden()
+    assert st.round_robin(int(name[2:])) == tabs[name]
+
+
+@pytest.mark.parametrize("n", [2, 4, 6, 8, 10, 16, 22, 64, 128, 130])
+def test_round_robin_is_pstrategy(n):
+    s = st.round_robin(n)
+    assert st.is_pstrategy(s, n)
+    assert s[0] == [(2 * k - 1, 2 * k) for k in range(1, n // 2 + 1)]
