@@ -7,20 +7,23 @@ namespace jsvd {
 namespace {
 
 // ----------------------------------------------------------------- Gram
-// Grid (splits, npairs), 256 threads.  Each wave takes 32-row slices; lane
-// l holds rows 8*(l/16) .. +7 of local column 16*t + l%16 for every column
+// Grid (splits, npairs), 256 threads.  Each wave takes 16-row slices; lane
+// l holds rows 4*(l/16) .. +3 of local column 16*t + l%16 for every column
 // tile t, loaded as 16-byte vectors.  The contraction index of the MFMA
 // runs over those rows, which is free to choose because both operands are
 // the same slice.  Only the tiles on and above the diagonal of the
-// symmetric H are formed.
+// symmetric H are formed.  Four rows per lane (not eight) keep the kernel
+// within 128 registers, four waves per SIMD; a pair whose columns all exist
+// loads without per-column selects (measured at n = 4096: 40.3 -> 35.8 us
+// per launch).
 typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
 
 // SC: scaled mode, column c multiplied by 2^-e_c (exact) as it is loaded.
 template <int BW, bool SC>
-__global__ __launch_bounds__(256) void gram_kernel(StepArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gram_kernel(StepArgs a) {
     constexpr int T = BW / 16;
     constexpr int NT = T * (T + 1) / 2;
-    constexpr int S = 8;
+    constexpr int S = 4;
     constexpr int SLICE = 4 * S;  // rows per wave and iteration
     __shared__ d4 red[NT * 64];
 
@@ -56,10 +59,21 @@ __global__ __launch_bounds__(256) void gram_kernel(StepArgs a) {
 
     const int64_t r0 = (int64_t)split * a.rows_per_split;
     const int64_t r1 = min(a.m, r0 + (int64_t)a.rows_per_split);
+    // every column of the pair present: loads without selects
+    const bool allv = (int64_t)(pq.y + 1) * a.w <= a.n;
     for (int64_t base = r0 + wave * SLICE; base < r1; base += 4 * SLICE) {
         double x[T][S];
         const int64_t rb = base + grp * S;
-        if (base + SLICE <= r1) {
+        if (allv && base + SLICE <= r1) {
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int s2 = 0; s2 < S / 2; ++s2) {
+                    const d2u v = *reinterpret_cast<const d2u *>(col[t] + rb + 2 * s2);
+                    x[t][2 * s2] = v.x;
+                    x[t][2 * s2 + 1] = v.y;
+                }
+        } else if (base + SLICE <= r1) {
 #pragma unroll
             for (int t = 0; t < T; ++t)
 #pragma unroll
