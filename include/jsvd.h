@@ -113,6 +113,13 @@ typedef struct {
  *   n_upper[i]     : strictly increasing; a problem takes the block_w of the
  *                    first entry with n <= n_upper[i], or of the last entry.
  *   block_w[i]     : 16 or 32.
+ *   gram_wg[i]     : tile shape of the Gram kernel for that entry: about this
+ *                    many workgroups per launch (the rows are split into
+ *                    gram_wg / (pivot pairs) ranges, 1..16); 0 = built-in
+ *                    (512), else 64..8192.
+ *   update_wg[i]   : tile shape of the update kernel: about this many
+ *                    workgroups per launch (row chunks per pivot pair =
+ *                    update_wg / pairs); 0 = built-in (1024), else 64..8192.
  *   batch_g_groups : of the 32 half waves of a batched workgroup, those that
  *                    rotate G when V is wanted (the others apply the
  *                    rotations to V); 0 = built-in (16), else 4..28.
@@ -124,13 +131,16 @@ typedef struct {
     int32_t count;
     int64_t n_upper[8];
     int32_t block_w[8];
+    int32_t gram_wg[8];
+    int32_t update_wg[8];
     int32_t batch_g_groups;
     int32_t batch_block_min_n;
 } jsvd_tuning;
 
 /* Install (tuning != NULL, copied) or remove (NULL) the tuned choices of a
- * handle: they decide w when opts->block_w == 0, the batched kernel's
- * split and which batched problems are blocked.  Returns JSVD_OK, -1 if h is NULL, -2 for an invalid table. */
+ * handle: they decide w when opts->block_w == 0, the tile shapes of the
+ * Gram and update kernels, the batched kernel's split and which batched
+ * problems are blocked.  Returns JSVD_OK, -1 if h is NULL, -2 for an invalid table. */
 int jsvd_set_tuning(jsvd_handle_t h, const jsvd_tuning *tuning);
 
 /* Fill *opts with the defaults listed above.  Returns JSVD_OK, or -1 if

@@ -40,6 +40,7 @@ class Info(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("count", _i32), ("n_upper", _i64 * 8), ("block_w", _i32 * 8),
+                ("gram_wg", _i32 * 8), ("update_wg", _i32 * 8),
                 ("batch_g_groups", _i32), ("batch_block_min_n", _i32)]
 
 
@@ -136,16 +137,22 @@ def _handle(device_index, stream_ptr):
 
 def tuning_struct(table):
     """The jsvd_tuning of a table {"n_upper": [...], "block_w": [...],
+    "gram_wg": [...], "update_wg": [...] (optional, 0 = built-in),
     "batch_g_groups": int, "batch_block_min_n": int} (raises ValueError if it
     cannot be one)."""
     nu, bw = list(table.get("n_upper", [])), list(table.get("block_w", []))
-    if len(nu) != len(bw) or len(nu) > 8:
-        raise ValueError("n_upper and block_w must have the same length, at most 8")
+    gw = list(table.get("gram_wg", [0] * len(nu)))
+    uw = list(table.get("update_wg", [0] * len(nu)))
+    if len(nu) != len(bw) or len(nu) > 8 or len(gw) != len(nu) or len(uw) != len(nu):
+        raise ValueError("n_upper, block_w, gram_wg and update_wg must have the same length, "
+                         "at most 8")
     t = Tuning()
     t.count = len(nu)
     for i, (a, b) in enumerate(zip(nu, bw)):
         t.n_upper[i] = int(a)
         t.block_w[i] = int(b)
+        t.gram_wg[i] = int(gw[i])
+        t.update_wg[i] = int(uw[i])
     t.batch_g_groups = int(table.get("batch_g_groups", 0))
     t.batch_block_min_n = int(table.get("batch_block_min_n", 0))
     return t

@@ -9,6 +9,9 @@ Tuned:
     N(0,1) square matrices of several orders n: the table maps each measured
     n to the fastest w (a problem takes the entry of the first measured n
     that is >= its n, or the last one);
+  * for that w and n, the tile shapes of the p-step kernels: the number of
+    workgroups of a Gram launch (its row splits) and of an update launch
+    (its row chunks per pivot pair), over a small grid;
   * the split of the batched kernel's 32 half waves between rotating G and
     applying the rotations to V, on the 10000-problem ragged batch (n 8..128,
     m = n + 0..64, the synthetic stand-in of the batched workload), with
@@ -32,6 +35,8 @@ from . import inputs
 
 DENSE_ORDERS = (256, 512, 1024, 2048, 3072, 4096)
 WIDTHS = (16, 32)
+GRAM_WG = (256, 512, 1024)
+UPDATE_WG = (512, 1024, 2048)
 G_GROUPS = (8, 12, 16, 20, 24)
 BLOCK_MIN_N = (33, 49, 65, 81, 97, 257)  # 257: no problem blocked
 
@@ -48,15 +53,30 @@ def _time_dense(B, A, w, reps=2):
     return best
 
 
-def tune_dense(orders=DENSE_ORDERS, widths=WIDTHS, seed=11):
+def tune_dense(orders=DENSE_ORDERS, widths=WIDTHS, gram_wg=GRAM_WG, update_wg=UPDATE_WG,
+               seed=11):
+    """Per order n: the fastest w with the built-in tile shapes, then for
+    that w the fastest (Gram, update) workgroup counts."""
     import torch
     from . import _binding as B
+    dev = torch.cuda.current_device()
     rows = []
     for n in orders:
         A = torch.from_numpy(inputs.gaussian(n, n, inputs.rng(seed + n))).cuda()
+        B.set_tuning(dev, None)
         times = {w: _time_dense(B, A, w) for w in widths}
         best = min(times, key=times.get)
-        rows.append({"n": n, "times_s": {str(w): t for w, t in times.items()}, "block_w": best})
+        shapes = {}
+        for g in gram_wg:
+            for u in update_wg:
+                B.set_tuning(dev, {"n_upper": [n], "block_w": [best], "gram_wg": [g],
+                                   "update_wg": [u]})
+                shapes[(g, u)] = _time_dense(B, A, best)
+        B.set_tuning(dev, None)
+        g_best, u_best = min(shapes, key=shapes.get)
+        rows.append({"n": n, "times_s": {str(w): t for w, t in times.items()}, "block_w": best,
+                     "shape_times_s": {f"{g}/{u}": t for (g, u), t in shapes.items()},
+                     "gram_wg": g_best, "update_wg": u_best})
         print(json.dumps(rows[-1]), flush=True)
     return rows
 
@@ -101,14 +121,18 @@ def tune_batched(groups=G_GROUPS, block_min=BLOCK_MIN_N, count=10000):
 
 def table_from(dense_rows, batched_times, block_times=None):
     dense_rows = sorted(dense_rows, key=lambda r: r["n"])
-    n_upper, block_w = [], []
+    n_upper, block_w, gram_wg, update_wg = [], [], [], []
     for r in dense_rows:
-        if block_w and block_w[-1] == r["block_w"]:
-            n_upper[-1] = r["n"]          # extend the run of the same w
+        key = (r["block_w"], r.get("gram_wg", 0), r.get("update_wg", 0))
+        if block_w and (block_w[-1], gram_wg[-1], update_wg[-1]) == key:
+            n_upper[-1] = r["n"]          # extend the run of the same choices
         else:
             n_upper.append(r["n"])
-            block_w.append(r["block_w"])
-    table = {"n_upper": n_upper, "block_w": block_w}
+            block_w.append(key[0])
+            gram_wg.append(key[1])
+            update_wg.append(key[2])
+    table = {"n_upper": n_upper, "block_w": block_w, "gram_wg": gram_wg,
+             "update_wg": update_wg}
     if batched_times:
         table["batch_g_groups"] = int(min(batched_times, key=batched_times.get))
     if block_times:

@@ -192,23 +192,37 @@ int choose_inner_sweeps(int64_t m, int64_t n) {
     return 1;
 }
 
-// Block width of a solve: the caller's, else the handle's tuning table,
-// else the built-in size rule.
-int pick_w(const jsvd_handle_s *h, const jsvd_opts &o, int64_t m, int64_t n) {
-    int w = o.block_w;
-    if (!w && h->tuning.count > 0) {
+// Block width and kernel tile shapes of a solve: w is the caller's, else
+// the handle's tuning table, else the built-in size rule; the shapes
+// (workgroups per Gram and update launch) come from the tuning entry of the
+// problem's size, else the built-in 512 and 1024.
+struct Shapes {
+    int w, gram_wg, update_wg;
+};
+
+Shapes pick_shapes(const jsvd_handle_s *h, const jsvd_opts &o, int64_t m, int64_t n) {
+    Shapes sh{o.block_w, 0, 0};
+    if (h->tuning.count > 0) {
         int i = 0;
         while (i + 1 < h->tuning.count && n > h->tuning.n_upper[i]) ++i;
-        w = h->tuning.block_w[i];
+        if (!sh.w) sh.w = h->tuning.block_w[i];
+        sh.gram_wg = h->tuning.gram_wg[i];
+        sh.update_wg = h->tuning.update_wg[i];
     }
-    if (!w) w = choose_w(m, n);
-    return w;
+    if (!sh.w) sh.w = choose_w(m, n);
+    if (!sh.gram_wg) sh.gram_wg = 512;
+    if (!sh.update_wg) sh.update_wg = 1024;
+    return sh;
+}
+
+int pick_w(const jsvd_handle_s *h, const jsvd_opts &o, int64_t m, int64_t n) {
+    return pick_shapes(h, o, m, n).w;
 }
 
 // Gram row splits of a solve (at most 16, rows per split a multiple of 64),
-// aiming at a few workgroups per CU.
-int gram_splits(int64_t m, int npairs, int64_t *rows_per_split) {
-    int splits = std::min(16, std::max(1, 512 / npairs));
+// aiming at gram_wg workgroups per launch.
+int gram_splits(int64_t m, int npairs, int gram_wg, int64_t *rows_per_split) {
+    int splits = std::min(16, std::max(1, gram_wg / npairs));
     const int64_t rps = (int64_t)align_up((size_t)((m + splits - 1) / splits), 64);
     *rows_per_split = rps;
     return (int)((m + rps - 1) / rps);
@@ -279,7 +293,8 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
           const int *perm_in_host) {
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = h->stream;
-    const int w = pick_w(h, o, m, n);
+    const Shapes shp = pick_shapes(h, o, m, n);
+    const int w = shp.w;
     const int bw = 2 * w;
     const int nb_real = (int)((n + w - 1) / w);
     const int order = strategy_order(nb_real);
@@ -291,9 +306,9 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     // workgroups per CU.  The V update of a p-step is done by the next
     // p-step's inner launch, in about two workgroups per CU that the pivot
     // pairs leave free (a workgroup there has 16 * 2w threads).
-    const int target_wg = 1024;
+    const int target_wg = shp.update_wg;
     int64_t rps = 0;
-    const int splits = gram_splits(m, npairs, &rps);
+    const int splits = gram_splits(m, npairs, shp.gram_wg, &rps);
     const int per_pair = std::max(1, target_wg / npairs);
     const int64_t upd_rows_g = align_up((size_t)((m + per_pair - 1) / per_pair), 64);
     const int64_t upd_rows_v = align_up((size_t)((n + per_pair - 1) / per_pair), 64);
@@ -840,6 +855,8 @@ int jsvd_set_tuning(jsvd_handle_t h, const jsvd_tuning *t) {
     for (int i = 0; i < t->count; ++i) {
         if (t->block_w[i] != 16 && t->block_w[i] != 32) return -2;
         if (i > 0 && t->n_upper[i] <= t->n_upper[i - 1]) return -2;
+        if (t->gram_wg[i] != 0 && (t->gram_wg[i] < 64 || t->gram_wg[i] > 8192)) return -2;
+        if (t->update_wg[i] != 0 && (t->update_wg[i] < 64 || t->update_wg[i] > 8192)) return -2;
     }
     if (t->batch_g_groups != 0 && (t->batch_g_groups < 4 || t->batch_g_groups > 28)) return -2;
     if (t->batch_block_min_n != 0 && (t->batch_block_min_n < 33 || t->batch_block_min_n > 257))
@@ -1205,10 +1222,11 @@ int jsvd_workspace_size(jsvd_handle_t h, int64_t m, int64_t n, const jsvd_opts *
     // the Jacobi solve runs on G (m x n) or, after the QR preprocessing, on
     // R^T (n x n); the hyperbolic SVD adds the input column permutation
     auto solve_bytes = [&](int64_t mm, int64_t nn, bool hsvd) {
-        const int w = pick_w(h, o, mm, nn);
+        const Shapes shp = pick_shapes(h, o, mm, nn);
+        const int w = shp.w;
         const int order = strategy_order((int)((nn + w - 1) / w));
         int64_t rps = 0;
-        const int splits = gram_splits(mm, order / 2, &rps);
+        const int splits = gram_splits(mm, order / 2, shp.gram_wg, &rps);
         return plan(mm, nn, 2 * w, order / 2, splits, hsvd).total;
     };
     size_t total = std::max(solve_bytes(m, n, false), solve_bytes(m, n, true));

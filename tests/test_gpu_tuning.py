@@ -40,13 +40,41 @@ def test_width_table_decides_block_w(dev):
     assert np.max(np.abs(out[16] - out[32])) <= 1e-13 * out[16][0]
 
 
+def test_tile_shapes_follow_the_table(dev):
+    """The Gram and update tile shapes of a tuning entry change the launch
+    geometry (the Gram partial sums' workspace follows the row splits) and
+    the result only within the rounding of a different summation order."""
+    torch = _torch()
+    import oracle
+    from paper_1401_2720_amd import _binding as B
+    import paper_1401_2720_amd as jsvd
+    print("tuning: tile shapes", flush=True)
+    A_np = inputs.gaussian(700, 640, inputs.rng(22))
+    A = torch.from_numpy(A_np).cuda()
+    ref = oracle.gesvj(A_np)["S"]
+    sizes = {}
+    for g, u in ((64, 64), (512, 1024), (4096, 8192)):
+        B.set_tuning(dev, {"n_upper": [10 ** 6], "block_w": [32], "gram_wg": [g],
+                           "update_wg": [u]})
+        sizes[g] = jsvd.workspace_size(700, 640)
+        _, S, V, info = B.gesvd(A)
+        assert info["status"] == 0 and info["block_w"] == 32
+        s = S.cpu().numpy()
+        assert np.max(np.abs(s - ref) / ref) <= 1e-12
+        Vh = V.cpu().numpy()
+        assert np.max(np.abs(Vh.T @ Vh - np.eye(640))) <= 1e-13 * 640
+    assert sizes[64] < sizes[512] <= sizes[4096]
+
+
 def test_invalid_table_refused(dev):
     from paper_1401_2720_amd import _binding as B
     for bad in ({"n_upper": [10], "block_w": [24]},
                 {"n_upper": [10, 5], "block_w": [16, 32]},
                 {"n_upper": [], "block_w": [], "batch_g_groups": 2},
                 {"n_upper": [], "block_w": [], "batch_block_min_n": 20},
-                {"n_upper": [], "block_w": [], "batch_block_min_n": 300}):
+                {"n_upper": [], "block_w": [], "batch_block_min_n": 300},
+                {"n_upper": [10], "block_w": [16], "gram_wg": [32], "update_wg": [0]},
+                {"n_upper": [10], "block_w": [16], "gram_wg": [0], "update_wg": [9000]}):
         with pytest.raises(B.JsvdError):
             B.set_tuning(dev, bad)
 
