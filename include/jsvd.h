@@ -185,6 +185,27 @@ int jsvd_gesvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda, do
                double *V, int64_t ldv, const jsvd_opts *opts, jsvd_info *info);
 
 /*
+ * Full SVD, G = U [Sigma; 0] V^T with U of order m (the form of eq. (2.1)'s
+ * G = Q [R_0; 0] carried through to U): jsvd_gesvd (QR preprocessing and
+ * all options as there; the output is always sorted), then the last m - k
+ * columns of U, k the number of positive singular values, are completed to
+ * an orthonormal basis: a Householder QR of the economy U (zero columns
+ * last) and Q applied to the identity's columns k .. m-1.
+ *   A      : device, m x n (lda >= m).  In: G.  Out: the economy U.
+ *   U      : device, m x m, leading dimension ldu >= m (argument 7).  Out:
+ *            columns 0 .. k-1 equal to A's, the rest orthonormal to them.
+ *   S, V, opts, info : as for jsvd_gesvd (arguments 8, 9, 10, 11, 12).
+ * Needs m <= 32768 (the completion holds a QR workspace of about
+ * 8 (m n + 256 m) bytes beside U).
+ * Returns JSVD_OK, a negative argument index, JSVD_NOT_CONVERGED,
+ * JSVD_NONFINITE, JSVD_HIP_ERROR (also when the completion's QR panel could
+ * not run its workgroups together) or JSVD_NO_MEMORY.
+ */
+int jsvd_gesvd_full(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda, double *U,
+                    int64_t ldu, double *S, double *V, int64_t ldv, const jsvd_opts *opts,
+                    jsvd_info *info);
+
+/*
  * Hyperbolic SVD, G = U Sigma V^{-1} with V^T J V = J (eq. (2.10); Section
  * 4.3, subphases 4-5).  J = diag(j_1..j_n), j_i = +1 or -1, given on the host.
  * Pairs of columns with opposite signs are orthogonalised by hyperbolic

@@ -59,7 +59,7 @@ EXPORTS = ["jsvd_default_opts", "jsvd_create", "jsvd_set_stream", "jsvd_destroy"
            "jsvd_diag_fp64", "jsvd_kernel_timing", "jsvd_kernel_times", "jsvd_gesvd_batched",
            "jsvd_svd_backward", "jsvd_set_tuning", "jsvd_batched_block_min_n",
            "jsvd_workspace_size", "jsvd_workspace_size_batched", "jsvd_reserve_batched",
-           "jsvd_diag_refined", "jsvd_gesvd_batched_noalloc"]
+           "jsvd_diag_refined", "jsvd_gesvd_batched_noalloc", "jsvd_gesvd_full"]
 
 
 def lib():
@@ -77,6 +77,8 @@ def lib():
     L.jsvd_destroy.argtypes = [_vp]
     L.jsvd_gesvd.argtypes = [_vp, _i64, _i64, _vp, _i64, _vp, _vp, _i64, ctypes.POINTER(Opts),
                              ctypes.POINTER(Info)]
+    L.jsvd_gesvd_full.argtypes = [_vp, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64,
+                                  ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     L.jsvd_hsvd.argtypes = [_vp, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _i64,
                             ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     L.jsvd_strategy_table.argtypes = [_i32, _i32, _vp]
@@ -104,7 +106,8 @@ def lib():
               "jsvd_gesvd", "jsvd_hsvd", "jsvd_strategy_table", "jsvd_diag_fp64",
               "jsvd_kernel_timing", "jsvd_kernel_times", "jsvd_gesvd_batched",
               "jsvd_svd_backward", "jsvd_workspace_size", "jsvd_workspace_size_batched",
-              "jsvd_reserve_batched", "jsvd_diag_refined", "jsvd_gesvd_batched_noalloc"):
+              "jsvd_reserve_batched", "jsvd_diag_refined", "jsvd_gesvd_batched_noalloc",
+              "jsvd_gesvd_full"):
         getattr(L, f).restype = ctypes.c_int
     _LIB = L
     return L
@@ -244,6 +247,32 @@ def gesvd(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want
     d = info.as_dict()
     d["status"] = rc
     return work.t(), S, (Vb.t() if want_v else None), d
+
+
+def gesvd_full(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,
+               allow=(1,), qr="auto", scaled="auto"):
+    """Full SVD A = U [diag(S); 0] V^T of a float64 CUDA tensor (m >= n) with
+    U of order m.  Returns (U, S, V, info): U (m x m) and V (n x n) views of
+    column-major buffers."""
+    import torch
+    m, n = A.shape
+    work = _colmajor_copy(A)
+    dev = A.device
+    Ub = torch.empty((m, m), dtype=torch.float64, device=dev)
+    S = torch.empty(n, dtype=torch.float64, device=dev)
+    Vb = torch.empty((n, n), dtype=torch.float64, device=dev) if want_v else None
+    stream = torch.cuda.current_stream(dev)
+    h = _handle(dev.index if dev.index is not None else torch.cuda.current_device(),
+                stream.cuda_stream)
+    o = make_opts(block_w, strategy, max_inner_sweeps, max_sweeps, want_v, True, qr, scaled)
+    info = Info()
+    rc = lib().jsvd_gesvd_full(h, m, n, _vp(work.data_ptr()), m, _vp(Ub.data_ptr()), m,
+                               _vp(S.data_ptr()), _vp(Vb.data_ptr()) if want_v else None, n,
+                               ctypes.byref(o), ctypes.byref(info))
+    _raise_on(rc, "jsvd_gesvd_full", allow)
+    d = info.as_dict()
+    d["status"] = rc
+    return Ub.t(), S, (Vb.t() if want_v else None), d
 
 
 def hsvd(G, J, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,

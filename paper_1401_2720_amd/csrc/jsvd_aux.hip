@@ -194,11 +194,48 @@ hipError_t launch_colnorms(const double *G, int64_t ldg, int64_t m, int64_t n, d
     return hipGetLastError();
 }
 
+// B (rows x cols, ld ldb) = columns first .. first + cols - 1 of the
+// identity of order rows.
+__global__ void identity_cols_kernel(double *B, int64_t ldb, int64_t rows, int64_t first) {
+    const int64_t c = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * blockDim.x)
+        B[i + c * ldb] = (i == first + c) ? 1.0 : 0.0;
+}
+
+// out[0] = the number of entries of S (n of them) that are > 0.
+__global__ void count_positive_kernel(const double *S, int64_t n, int *out) {
+    __shared__ int part[256];
+    int c = 0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) c += S[i] > 0.0 ? 1 : 0;
+    part[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = part[0];
+}
+
 __global__ void range_init_kernel(int *range) {
     if (threadIdx.x == 0) {
         range[0] = 0x7fffffff;
         range[1] = -0x7fffffff - 1;
     }
+}
+
+hipError_t launch_identity_cols(double *B, int64_t ldb, int64_t rows, int64_t cols, int64_t first,
+                                hipStream_t s) {
+    if (cols <= 0) return hipSuccess;
+    const int64_t bx = std::min<int64_t>((rows + 255) / 256, 64);
+    hipLaunchKernelGGL(identity_cols_kernel, dim3((unsigned)bx, (unsigned)cols), dim3(256), 0, s, B,
+                       ldb, rows, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_positive(const double *S, int64_t n, int *out, hipStream_t s) {
+    hipLaunchKernelGGL(count_positive_kernel, dim3(1), dim3(256), 0, s, S, n, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_range_init(int *range, hipStream_t s) {

@@ -521,13 +521,16 @@ int gemm_plain(bool ta, const double *A, int64_t lda, const double *B, int64_t l
 }
 
 // Workspace carve-up of the QR preprocessing (kept apart from the solve's).
+// ncols: the widest block Q is applied to (n for U = Q [V_x; 0], up to m for
+// the full U).
 struct QrLayout {
     size_t oW, oX, oVx, oVp, oT, oTau, oParts, oY1, oY2, oPart, oProw, oNrm, oPerm, oBar, total;
 };
 
-QrLayout qr_plan(int64_t m, int64_t n) {
+QrLayout qr_plan(int64_t m, int64_t n, int64_t ncols = 0) {
     constexpr int NB = kQrPanel;
     const int64_t npan = (n + NB - 1) / NB;
+    const int64_t nc = std::max(n, ncols);
     QrLayout q;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t at = off; off += align_up(bytes, 256); return at; };
@@ -537,9 +540,9 @@ QrLayout qr_plan(int64_t m, int64_t n) {
     q.oVp = take((size_t)m * NB * 8);
     q.oT = take((size_t)npan * NB * NB * 8);
     q.oTau = take((size_t)n * 8);
-    q.oParts = take((size_t)32 * NB * n * 8);
-    q.oY1 = take((size_t)NB * n * 8);
-    q.oY2 = take((size_t)NB * n * 8);
+    q.oParts = take((size_t)32 * NB * nc * 8);
+    q.oY1 = take((size_t)NB * nc * 8);
+    q.oY2 = take((size_t)NB * nc * 8);
     q.oPart = take((size_t)2 * 64 * NB * 8);
     q.oProw = take((size_t)2 * NB * 8);
     q.oNrm = take((size_t)n * 8);
@@ -549,119 +552,159 @@ QrLayout qr_plan(int64_t m, int64_t n) {
     return q;
 }
 
-int gesvd_qr(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double *S,
-             double *V, int64_t ldv, const jsvd_opts &o, jsvd_info *info) {
-    const auto t0 = std::chrono::steady_clock::now();
-    hipStream_t st = h->stream;
-    constexpr int NB = kQrPanel;
-    const int64_t npan = (n + NB - 1) / NB;
-    const QrLayout q = qr_plan(m, n);
-    const size_t off = q.total;
-    const size_t oW = q.oW, oX = q.oX, oVx = q.oVx, oVp = q.oVp, oT = q.oT, oTau = q.oTau,
-                 oParts = q.oParts, oY1 = q.oY1, oY2 = q.oY2, oPart = q.oPart, oProw = q.oProw,
-                 oNrm = q.oNrm, oPerm = q.oPerm, oBar = q.oBar;
-    if (off > h->qr_ws_bytes) {
-        if (h->qr_ws) (void)hipFree(h->qr_ws);
+// Pointers into the QR workspace of a layout.
+struct QrWork {
+    double *W, *X, *Vx, *Vp, *T, *tau, *parts, *Y1, *Y2, *part, *prow, *nrm, *d_range;
+    int *perm, *abort_flag;
+    unsigned *bar;
+};
+
+int qr_workspace(jsvd_handle_s *h, const QrLayout &q, QrWork *w) {
+    if (q.total > h->qr_ws_bytes) {
+        if (h->qr_ws) {
+            if (hipStreamSynchronize(h->stream) != hipSuccess) return JSVD_HIP_ERROR;
+            (void)hipFree(h->qr_ws);
+        }
         h->qr_ws = nullptr;
         h->qr_ws_bytes = 0;
-        if (hipMalloc(&h->qr_ws, off) != hipSuccess) {
+        if (hipMalloc(&h->qr_ws, q.total) != hipSuccess) {
             h->qr_ws = nullptr;
             return JSVD_NO_MEMORY;
         }
-        h->qr_ws_bytes = off;
+        h->qr_ws_bytes = q.total;
     }
     char *ws = static_cast<char *>(h->qr_ws);
-    double *W = reinterpret_cast<double *>(ws + oW), *X = reinterpret_cast<double *>(ws + oX),
-           *Vx = reinterpret_cast<double *>(ws + oVx), *Vp = reinterpret_cast<double *>(ws + oVp),
-           *T = reinterpret_cast<double *>(ws + oT), *tau = reinterpret_cast<double *>(ws + oTau),
-           *parts = reinterpret_cast<double *>(ws + oParts), *Y1 = reinterpret_cast<double *>(ws + oY1),
-           *Y2 = reinterpret_cast<double *>(ws + oY2), *part = reinterpret_cast<double *>(ws + oPart),
-           *prow = reinterpret_cast<double *>(ws + oProw), *nrm = reinterpret_cast<double *>(ws + oNrm);
-    int *perm = reinterpret_cast<int *>(ws + oPerm);
-    unsigned *bar = reinterpret_cast<unsigned *>(ws + oBar);
-    int *abort_flag = reinterpret_cast<int *>(ws + oBar + 8);
+    auto d = [&](size_t o) { return reinterpret_cast<double *>(ws + o); };
+    w->W = d(q.oW); w->X = d(q.oX); w->Vx = d(q.oVx); w->Vp = d(q.oVp); w->T = d(q.oT);
+    w->tau = d(q.oTau); w->parts = d(q.oParts); w->Y1 = d(q.oY1); w->Y2 = d(q.oY2);
+    w->part = d(q.oPart); w->prow = d(q.oProw); w->nrm = d(q.oNrm);
+    w->perm = reinterpret_cast<int *>(ws + q.oPerm);
+    w->bar = reinterpret_cast<unsigned *>(ws + q.oBar);
+    w->abort_flag = reinterpret_cast<int *>(ws + q.oBar + 8);
+    w->d_range = d(q.oBar + 64);
+    return JSVD_OK;
+}
 
-    // presort: W = G P, columns by non-increasing norm (ties by index)
-    HIP_TRY(launch_colnorms(A, lda, m, n, nrm, st));
-    HIP_TRY(launch_rank(nrm, n, n, perm, st));
-    HIP_TRY(launch_gather_cols(A, lda, W, m, m, n, perm, nullptr, nullptr, st));
-    HIP_TRY(launch_qr_reset(bar, abort_flag, st));
-
-    // Householder QR, panel by panel
+// Blocked Householder QR of w.W (m x n, ld m) in place (eq. (2.1) without
+// the column permutation): reflectors below the diagonal (LAPACK's
+// convention, v(k) = 1 implicit), R on and above it, T of each panel's
+// compact WY form in w.T.  A panel barrier that cannot complete sets
+// w.abort_flag (read by the caller).
+int hh_factor(jsvd_handle_s *h, const QrWork &w, int64_t m, int64_t n) {
+    hipStream_t st = h->stream;
+    constexpr int NB = kQrPanel;
+    const int64_t npan = (n + NB - 1) / NB;
+    HIP_TRY(launch_qr_reset(w.bar, w.abort_flag, st));
     for (int64_t p = 0; p < npan; ++p) {
         const int64_t j = p * NB;
         const int nb = (int)std::min<int64_t>(NB, n - j);
         const int64_t rows = m - j;
         QrPanelArgs qa;
-        qa.W = W; qa.ldw = m; qa.m = m; qa.n = n; qa.j = j; qa.nb = nb;
-        qa.tau = tau; qa.Vp = Vp; qa.ldvp = m; qa.partials = part; qa.prow = prow;
-        qa.bar = bar; qa.abort_flag = abort_flag; qa.nwg = qr_panel_groups(rows);
+        qa.W = w.W; qa.ldw = m; qa.m = m; qa.n = n; qa.j = j; qa.nb = nb;
+        qa.tau = w.tau; qa.Vp = w.Vp; qa.ldvp = m; qa.partials = w.part; qa.prow = w.prow;
+        qa.bar = w.bar; qa.abort_flag = w.abort_flag; qa.nwg = qr_panel_groups(rows);
         HIP_TRY(launch_qr_panel(qa, st));
         // T of the panel from V^T V
-        int rc = gemm_splitk(Vp, m, Vp, m, NB, NB, rows, parts, Y1, st);
+        int rc = gemm_splitk(w.Vp, m, w.Vp, m, NB, NB, rows, w.parts, w.Y1, st);
         if (rc) return rc;
-        HIP_TRY(launch_qr_t(Y1, tau + j, nb, T + p * NB * NB, st));
+        HIP_TRY(launch_qr_t(w.Y1, w.tau + j, nb, w.T + p * NB * NB, st));
         if (j + nb < n) {
             // trailing columns: C <- C - V T^T (V^T C)
             const int nc = (int)(n - j - nb);
-            double *C = W + j + (j + nb) * m;
-            if ((rc = gemm_splitk(Vp, m, C, m, NB, nc, rows, parts, Y1, st))) return rc;
-            if ((rc = gemm_plain(true, T + p * NB * NB, NB, Y1, NB, Y2, NB, NB, nc, NB, 1.0, 0.0,
-                                 st)))
+            double *C = w.W + j + (j + nb) * m;
+            if ((rc = gemm_splitk(w.Vp, m, C, m, NB, nc, rows, w.parts, w.Y1, st))) return rc;
+            if ((rc = gemm_plain(true, w.T + p * NB * NB, NB, w.Y1, NB, w.Y2, NB, NB, nc, NB, 1.0,
+                                 0.0, st)))
                 return rc;
-            if ((rc = gemm_plain(false, Vp, m, Y2, NB, C, m, (int)rows, nc, NB, -1.0, 1.0, st)))
+            if ((rc = gemm_plain(false, w.Vp, m, w.Y2, NB, C, m, (int)rows, nc, NB, -1.0, 1.0, st)))
                 return rc;
         }
     }
-    // A grid barrier of the panel kernel that did not complete (some panel
-    // workgroups could not start beside other work on the device), or R
-    // numerically singular (dependent columns): solve G directly, so that V
-    // stays orthogonal and zero singular values stay exact.  G itself is
-    // untouched so far (the factorization works on the copy W).  The abort
-    // flag and R's diagonal range are read through the handle's pinned words.
-    {
-        double *d_range = reinterpret_cast<double *>(ws + oBar + 64);
-        HIP_TRY(launch_diag_range(W, m, n, d_range, st));
-        int *hab = reinterpret_cast<int *>(h->host_counters + kSlotFlag);
-        double *range = reinterpret_cast<double *>(h->host_counters + kSlotRange);
-        HIP_TRY(hipMemcpyAsync(hab, abort_flag, sizeof(int), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(range, d_range, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        const double dmin = range[0], dmax = range[1];
-        if (*hab != 0 || !(dmin > (double)n * 0x1p-53 * dmax)) {
-            jsvd_opts od = o;
-            od.qr = 1;
-            return solve(h, m, n, A, lda, S, V, ldv, n, od, info, false, nullptr);
-        }
-    }
+    return JSVD_OK;
+}
 
-    // Jacobi on X = R^T: X V_x = U_x Sigma
-    HIP_TRY(launch_r_transpose(W, m, n, X, n, st));
-    jsvd_opts oj = o;
-    oj.want_v = 1;
-    oj.qr = 1;
-    jsvd_info inf{};
-    int status = solve(h, n, n, X, n, S, Vx, n, n, oj, &inf, false, nullptr);
-    if (status != JSVD_OK && status != JSVD_NOT_CONVERGED) return status;
-
-    // U = Q [V_x; 0]: the reflectors applied to [V_x; 0] in reverse panel order
-    HIP_TRY(launch_embed(Vx, n, n, A, lda, m, n, st));
+// B <- Q B for B m x ncols (ld ldb), Q the product of the reflectors that
+// hh_factor left in w.W: the panels applied in reverse order.
+int hh_apply_q(jsvd_handle_s *h, const QrWork &w, int64_t m, int64_t n, double *B, int64_t ldb,
+               int64_t ncols) {
+    hipStream_t st = h->stream;
+    constexpr int NB = kQrPanel;
+    const int64_t npan = (n + NB - 1) / NB;
     for (int64_t p = npan - 1; p >= 0; --p) {
         const int64_t j = p * NB;
         const int nb = (int)std::min<int64_t>(NB, n - j);
         const int64_t rows = m - j;
-        HIP_TRY(launch_qr_extract_v(W, m, m, j, nb, Vp, m, st));
-        double *B = A + j;
-        int rc = gemm_splitk(Vp, m, B, lda, NB, (int)n, rows, parts, Y1, st);
+        HIP_TRY(launch_qr_extract_v(w.W, m, m, j, nb, w.Vp, m, st));
+        double *Bj = B + j;
+        int rc = gemm_splitk(w.Vp, m, Bj, ldb, NB, (int)ncols, rows, w.parts, w.Y1, st);
         if (rc) return rc;
-        if ((rc = gemm_plain(false, T + p * NB * NB, NB, Y1, NB, Y2, NB, NB, (int)n, NB, 1.0, 0.0,
-                             st)))
+        if ((rc = gemm_plain(false, w.T + p * NB * NB, NB, w.Y1, NB, w.Y2, NB, NB, (int)ncols, NB,
+                             1.0, 0.0, st)))
             return rc;
-        if ((rc = gemm_plain(false, Vp, m, Y2, NB, B, lda, (int)rows, (int)n, NB, -1.0, 1.0, st)))
+        if ((rc = gemm_plain(false, w.Vp, m, w.Y2, NB, Bj, ldb, (int)rows, (int)ncols, NB, -1.0,
+                             1.0, st)))
             return rc;
     }
+    return JSVD_OK;
+}
+
+// Whether hh_factor completed and R (in w.W) is numerically nonsingular
+// (min |r_ii| > n 2^-53 max |r_jj|); one stream synchronisation, the values
+// read through the handle's pinned words.
+int qr_check(jsvd_handle_s *h, const QrWork &w, int64_t m, int64_t n, bool *aborted,
+             bool *singular) {
+    hipStream_t st = h->stream;
+    HIP_TRY(launch_diag_range(w.W, m, n, w.d_range, st));
+    int *hab = reinterpret_cast<int *>(h->host_counters + kSlotFlag);
+    double *range = reinterpret_cast<double *>(h->host_counters + kSlotRange);
+    HIP_TRY(hipMemcpyAsync(hab, w.abort_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(range, w.d_range, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *aborted = *hab != 0;
+    *singular = !(range[0] > (double)n * 0x1p-53 * range[1]);
+    return JSVD_OK;
+}
+
+int gesvd_qr(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double *S,
+             double *V, int64_t ldv, const jsvd_opts &o, jsvd_info *info) {
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = h->stream;
+    QrWork w;
+    int rc = qr_workspace(h, qr_plan(m, n), &w);
+    if (rc) return rc;
+
+    // presort: W = G P, columns by non-increasing norm (ties by index)
+    HIP_TRY(launch_colnorms(A, lda, m, n, w.nrm, st));
+    HIP_TRY(launch_rank(w.nrm, n, n, w.perm, st));
+    HIP_TRY(launch_gather_cols(A, lda, w.W, m, m, n, w.perm, nullptr, nullptr, st));
+    if ((rc = hh_factor(h, w, m, n))) return rc;
+    // A grid barrier of the panel kernel that did not complete (some panel
+    // workgroups could not start beside other work on the device), or R
+    // numerically singular (dependent columns): solve G directly, so that V
+    // stays orthogonal and zero singular values stay exact.  G itself is
+    // untouched so far (the factorization works on the copy W).
+    bool aborted = false, singular = false;
+    if ((rc = qr_check(h, w, m, n, &aborted, &singular))) return rc;
+    if (aborted || singular) {
+        jsvd_opts od = o;
+        od.qr = 1;
+        return solve(h, m, n, A, lda, S, V, ldv, n, od, info, false, nullptr);
+    }
+
+    // Jacobi on X = R^T: X V_x = U_x Sigma
+    HIP_TRY(launch_r_transpose(w.W, m, n, w.X, n, st));
+    jsvd_opts oj = o;
+    oj.want_v = 1;
+    oj.qr = 1;
+    jsvd_info inf{};
+    int status = solve(h, n, n, w.X, n, S, w.Vx, n, n, oj, &inf, false, nullptr);
+    if (status != JSVD_OK && status != JSVD_NOT_CONVERGED) return status;
+
+    // U = Q [V_x; 0]
+    HIP_TRY(launch_embed(w.Vx, n, n, A, lda, m, n, st));
+    if ((rc = hh_apply_q(h, w, m, n, A, lda, n))) return rc;
     // V = P U_x: row i of U_x is row perm[i] of V
-    if (o.want_v) HIP_TRY(launch_scatter_rows(X, n, V, ldv, n, n, perm, st));
+    if (o.want_v) HIP_TRY(launch_scatter_rows(w.X, n, V, ldv, n, n, w.perm, st));
     HIP_TRY(hipStreamSynchronize(st));
     inf.preprocessed = 1;
     inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -902,6 +945,56 @@ int jsvd_gesvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda, do
     }
     if (qr) return gesvd_qr(h, m, n, A, lda, S, V, ldv, o, info);
     return solve(h, m, n, A, lda, S, V, ldv, n, o, info, false, nullptr);
+}
+
+int jsvd_gesvd_full(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda, double *U,
+                    int64_t ldu, double *S, double *V, int64_t ldv, const jsvd_opts *opts,
+                    jsvd_info *info) {
+    jsvd_opts o = opts ? *opts : defaults();
+    int rc = check_common(h, m, n, A, lda, o);
+    if (rc) return rc == -9 ? -11 : rc;
+    if (m > 32768) return -2;
+    if (!U) return -6;
+    if (ldu < m) return -7;
+    if (!S) return -8;
+    if (o.want_v && !V) return -9;
+    if (o.want_v && ldv < n) return -10;
+    o.sort = 1;  // the completion relies on the zero singular values coming last
+    if ((rc = jsvd_gesvd(h, m, n, A, lda, S, V, ldv, &o, info)) != JSVD_OK &&
+        rc != JSVD_NOT_CONVERGED)
+        return rc;
+    const int status = rc;
+    hipStream_t st = h->stream;
+    // k = number of positive singular values; U's columns k .. n-1 are zero
+    int *hk = reinterpret_cast<int *>(h->host_counters + kSlotFlag);
+    {
+        QrWork w;
+        if ((rc = qr_workspace(h, qr_plan(m, n, m), &w))) return rc;
+        HIP_TRY(launch_count_positive(S, n, w.perm, st));
+        HIP_TRY(hipMemcpyAsync(hk, w.perm, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const int64_t k = *hk;
+        // Q R = U (Householder); Q's columns k .. m-1 are orthogonal to the
+        // first k columns of U, which Q spans
+        HIP_TRY(hipMemcpy2DAsync(w.W, (size_t)m * sizeof(double), A, (size_t)lda * sizeof(double),
+                                 (size_t)m * sizeof(double), (size_t)n, hipMemcpyDeviceToDevice,
+                                 st));
+        if ((rc = hh_factor(h, w, m, n))) return rc;
+        bool aborted = false, singular = false;
+        if ((rc = qr_check(h, w, m, n, &aborted, &singular))) return rc;
+        if (aborted) return JSVD_HIP_ERROR;
+        if (k > 0)
+            HIP_TRY(hipMemcpy2DAsync(U, (size_t)ldu * sizeof(double), A,
+                                     (size_t)lda * sizeof(double), (size_t)m * sizeof(double),
+                                     (size_t)k, hipMemcpyDeviceToDevice, st));
+        if (k < m) {
+            double *Ck = U + k * ldu;
+            HIP_TRY(launch_identity_cols(Ck, ldu, m, m - k, k, st));
+            if ((rc = hh_apply_q(h, w, m, n, Ck, ldu, m - k))) return rc;
+        }
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    return status;
 }
 
 int jsvd_hsvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda, const int8_t *J,

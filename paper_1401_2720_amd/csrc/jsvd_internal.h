@@ -165,6 +165,9 @@ hipError_t launch_range_init(int *range, hipStream_t s);
 hipError_t launch_colexp(const double *G, int64_t ldg, int64_t m, int64_t n, double *s_out,
                          int *ex, int *range, hipStream_t s);
 hipError_t launch_rank(const double *s, int64_t n, int64_t n_plus, int *perm, hipStream_t st);
+hipError_t launch_identity_cols(double *B, int64_t ldb, int64_t rows, int64_t cols, int64_t first,
+                                hipStream_t s);
+hipError_t launch_count_positive(const double *S, int64_t n, int *out, hipStream_t s);
 hipError_t launch_gather_cols(const double *src, int64_t lds, double *dst, int64_t ldd,
                               int64_t rows, int64_t cols, const int *perm, const double *scale,
                               double *s_out, hipStream_t s);
