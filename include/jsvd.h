@@ -67,7 +67,11 @@ typedef struct jsvd_handle_s *jsvd_handle_t;
 
 typedef struct {
     int32_t block_w;          /* block-column width w: 0 = choose (tuning table of the handle,
-                                 else by size), else 16 or 32 */
+                                 else by size), else 16, 32 or 64.  64 is the third blocking
+                                 level: the inner problem of a 128-column pivot pair is
+                                 itself solved by the block method with 16-column
+                                 sub-blocks (ordinary unscaled SVD only: the hyperbolic
+                                 SVD and the scaled mode take 32 instead) */
     int32_t strategy;         /* JSVD_STRAT_* (default JSVD_STRAT_RREV) */
     int32_t max_inner_sweeps; /* M_s of Section 4.3: 0 = choose (default: 1), 1 = block-oriented,
                                  > 1 = full block (the paper's setting is 30) */
@@ -112,7 +116,7 @@ typedef struct {
  *   count          : entries used in n_upper and block_w, 1..8 (0: no w table).
  *   n_upper[i]     : strictly increasing; a problem takes the block_w of the
  *                    first entry with n <= n_upper[i], or of the last entry.
- *   block_w[i]     : 16 or 32.
+ *   block_w[i]     : 16, 32 or 64.
  *   gram_wg[i]     : tile shape of the Gram kernel for that entry: about this
  *                    many workgroups per launch (the rows are split into
  *                    gram_wg / (pivot pairs) ranges, 1..16); 0 = built-in

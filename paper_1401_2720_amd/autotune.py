@@ -5,7 +5,7 @@ for every new handle (jsvd_set_tuning).
     python -m paper_1401_2720_amd.autotune [--quick] [--out PATH]
 
 Tuned:
-  * the block width w of the dense SVD / HSVD, over w in {16, 32}, on seeded
+  * the block width w of the dense SVD / HSVD, over w in {16, 32, 64}, on seeded
     N(0,1) square matrices of several orders n: the table maps each measured
     n to the fastest w (a problem takes the entry of the first measured n
     that is >= its n, or the last one);
@@ -33,8 +33,8 @@ import numpy as np
 
 from . import inputs
 
-DENSE_ORDERS = (256, 512, 1024, 2048, 3072, 4096)
-WIDTHS = (16, 32)
+DENSE_ORDERS = (256, 512, 1024, 2048, 3072, 4096, 8192)
+WIDTHS = (16, 32, 64)
 GRAM_WG = (256, 512, 1024)
 UPDATE_WG = (512, 1024, 2048)
 G_GROUPS = (8, 12, 16, 20, 24)

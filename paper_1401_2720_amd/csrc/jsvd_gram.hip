@@ -130,9 +130,128 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
     }
 }
 
+// ------------------------------------------------------------- Gram, 2w = 128
+// The 8 x 8 column tiles of a 128-column pivot pair give 36 tiles on and
+// above the diagonal of H, too many accumulators for one wave.  Each of the
+// four waves forms its own share over all rows of the split, so no partial
+// sums cross waves: with super-tiles of two column tiles, wave 0 takes the
+// super-tile pairs (0,0) (0,1) (1,1), wave 1 (2,2) (2,3) (3,3), wave 2
+// (0,2) (0,3) and wave 3 (1,2) (1,3) -- 10, 10, 8 and 8 tiles, loading 4,
+// 4, 6 and 6 column tiles of each 16-row slice (the waves read the same
+// rows, so HBM sees each row once).
+template <int ROLE>
+struct Gram128Role;
+template <>
+struct Gram128Role<0> {
+    static constexpr int NTL = 4, NP = 10;
+    static constexpr int tl[NTL] = {0, 1, 2, 3};
+    static constexpr int pa[NP] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+    static constexpr int pb[NP] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+};
+template <>
+struct Gram128Role<1> {
+    static constexpr int NTL = 4, NP = 10;
+    static constexpr int tl[NTL] = {4, 5, 6, 7};
+    static constexpr int pa[NP] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+    static constexpr int pb[NP] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+};
+template <>
+struct Gram128Role<2> {
+    static constexpr int NTL = 6, NP = 8;
+    static constexpr int tl[NTL] = {0, 1, 4, 5, 6, 7};
+    static constexpr int pa[NP] = {0, 0, 0, 0, 1, 1, 1, 1};
+    static constexpr int pb[NP] = {2, 3, 4, 5, 2, 3, 4, 5};
+};
+template <>
+struct Gram128Role<3> {
+    static constexpr int NTL = 6, NP = 8;
+    static constexpr int tl[NTL] = {2, 3, 4, 5, 6, 7};
+    static constexpr int pa[NP] = {0, 0, 0, 0, 1, 1, 1, 1};
+    static constexpr int pb[NP] = {2, 3, 4, 5, 2, 3, 4, 5};
+};
+
+template <int ROLE>
+__device__ __forceinline__ void gram128_role(const StepArgs &a, int2 pq, int64_t r0, int64_t r1,
+                                             double *out) {
+    using Rl = Gram128Role<ROLE>;
+    constexpr int NTL = Rl::NTL, NP = Rl::NP, S = 4, SLICE = 4 * S, BW = 128;
+    const int lane = threadIdx.x & 63, i16 = lane & 15, grp = lane >> 4;
+    const double *col[NTL];
+    bool valid[NTL];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) {
+        const int64_t gc = pair_col(Rl::tl[t] * 16 + i16, a.w, pq);
+        valid[t] = gc < a.n;
+        col[t] = a.G + (valid[t] ? gc : 0) * a.ldg;
+    }
+    d4 acc[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = d4{0.0, 0.0, 0.0, 0.0};
+    const bool allv = (int64_t)(pq.y + 1) * a.w <= a.n;
+    for (int64_t base = r0; base < r1; base += SLICE) {
+        double x[NTL][S];
+        const int64_t rb = base + grp * S;
+        if (allv && base + SLICE <= r1) {
+#pragma unroll
+            for (int t = 0; t < NTL; ++t)
+#pragma unroll
+                for (int s2 = 0; s2 < S / 2; ++s2) {
+                    const d2u v = *reinterpret_cast<const d2u *>(col[t] + rb + 2 * s2);
+                    x[t][2 * s2] = v.x;
+                    x[t][2 * s2 + 1] = v.y;
+                }
+        } else {
+#pragma unroll
+            for (int t = 0; t < NTL; ++t)
+#pragma unroll
+                for (int s2 = 0; s2 < S; ++s2)
+                    x[t][s2] = (valid[t] && rb + s2 < r1) ? col[t][rb + s2] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+            for (int s2 = 0; s2 < S; ++s2)
+                acc[k] = mfma16(x[Rl::pa[k]][s2], x[Rl::pb[k]][s2], acc[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int ta = Rl::tl[Rl::pa[k]], tb = Rl::tl[Rl::pb[k]];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            out[(ta * 16 + grp + 4 * v) * BW + tb * 16 + i16] = acc[k][v];
+    }
+}
+
+__global__ __launch_bounds__(256) void gram128_kernel(StepArgs a) {
+    constexpr int BW = 128;
+    int pair = blockIdx.y, split = blockIdx.x;
+    if (a.npairs % 8 == 0) {
+        const int lin = blockIdx.x + gridDim.x * blockIdx.y;
+        const int xcd = lin % 8, s = lin / 8;
+        pair = xcd + 8 * (s / a.splits);
+        split = s % a.splits;
+    }
+    const int2 pq = a.pairs[pair];
+    if ((int64_t)pq.x * a.w >= a.n) return;  // both block-columns are padding
+    const int64_t r0 = (int64_t)split * a.rows_per_split;
+    const int64_t r1 = min(a.m, r0 + (int64_t)a.rows_per_split);
+    double *out = a.hpart + ((size_t)pair * a.splits + split) * BW * BW;
+    switch (threadIdx.x >> 6) {
+    case 0: gram128_role<0>(a, pq, r0, r1, out); break;
+    case 1: gram128_role<1>(a, pq, r0, r1, out); break;
+    case 2: gram128_role<2>(a, pq, r0, r1, out); break;
+    default: gram128_role<3>(a, pq, r0, r1, out); break;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_gram(int bw, const StepArgs &a, hipStream_t s) {
+    if (bw == 128) {
+        // the third blocking level runs unscaled only (the host checks)
+        hipLaunchKernelGGL(gram128_kernel, dim3(a.splits, a.npairs), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     dim3 grid(a.splits, a.npairs);
     if (a.colexp) {
         if (bw == 32)

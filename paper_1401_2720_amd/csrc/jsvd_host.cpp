@@ -230,7 +230,7 @@ int gram_splits(int64_t m, int npairs, int gram_wg, int64_t *rows_per_split) {
 
 // Workspace carve-up for one solve.
 struct Layout {
-    size_t hpart, vprime, pair_rot, counters, perm, s_tmp, tmp, perm_in, total;
+    size_t hpart, vprime, pair_rot, counters, perm, s_tmp, tmp, perm_in, rscratch, total;
 };
 
 Layout plan(int64_t m, int64_t n, int bw, int npairs, int splits, bool hsvd) {
@@ -250,6 +250,8 @@ Layout plan(int64_t m, int64_t n, int bw, int npairs, int splits, bool hsvd) {
     L.s_tmp = take((size_t)n * sizeof(double));
     L.tmp = take((size_t)std::max(m * n, n * n) * sizeof(double));
     L.perm_in = take(hsvd ? (size_t)n * sizeof(int) : 0);
+    // 2w = 128: the Cholesky factors of the pivot pairs (the inner block method)
+    L.rscratch = take(bw == 128 ? (size_t)npairs * bw * bw * sizeof(double) : 0);
     L.total = off;
     return L;
 }
@@ -293,8 +295,18 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
           const int *perm_in_host) {
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = h->stream;
+    int rc = 0;
+    // scaled mode (opts.scaled: 2 on, 1 off, 0 when G is badly scaled)
+    bool scaled = o.scaled == 2;
+    if (o.scaled != 1) {
+        bool bad = false;
+        if ((rc = column_exponents(h, m, n, A, lda, o.scaled == 0 ? &bad : nullptr))) return rc;
+        scaled = scaled || bad;
+    }
     const Shapes shp = pick_shapes(h, o, m, n);
-    const int w = shp.w;
+    // w = 64 (the third blocking level) runs the ordinary, unscaled SVD; the
+    // hyperbolic SVD and the scaled mode take w = 32 instead
+    const int w = (shp.w == 64 && (n_plus < n || scaled)) ? 32 : shp.w;
     const int bw = 2 * w;
     const int nb_real = (int)((n + w - 1) / w);
     const int order = strategy_order(nb_real);
@@ -314,12 +326,13 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     const int64_t upd_rows_v = align_up((size_t)((n + per_pair - 1) / per_pair), 64);
     const int free_cu = std::max(h->cu_count - npairs, std::max(1, h->cu_count / 4));
     const int v_per_pair = std::max(1, 2 * free_cu / npairs);
-    const int inner_waves = 16 * bw / 64;  // 16-row slices per pass of such a workgroup
+    // 16-row slices per pass of such a workgroup (16 * 2w threads; 512 at 2w = 128)
+    const int inner_waves = bw == 128 ? 8 : 16 * bw / 64;
     const int64_t prev_rows =
         align_up((size_t)((n + v_per_pair - 1) / v_per_pair), (size_t)16 * inner_waves);
 
     Layout L = plan(m, n, bw, npairs, splits, hsvd);
-    int rc = ensure_workspace(h, L.total);
+    rc = ensure_workspace(h, L.total);
     if (rc) return rc;
     char *ws = static_cast<char *>(h->ws);
 
@@ -348,14 +361,13 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     a.pair_rot = pair_rot0;
     a.counters = reinterpret_cast<unsigned long long *>(ws + L.counters);
     a.inner_tbl = inner;
-    // scaled mode (opts.scaled: 2 on, 1 off, 0 when G is badly scaled)
-    bool scaled = o.scaled == 2;
-    if (o.scaled != 1) {
-        bool bad = false;
-        if ((rc = column_exponents(h, m, n, A, lda, o.scaled == 0 ? &bad : nullptr))) return rc;
-        scaled = scaled || bad;
-    }
     a.colexp = scaled ? h->colexp : nullptr;
+    a.rscratch = bw == 128 ? reinterpret_cast<double *>(ws + L.rscratch) : nullptr;
+    a.btbl_order = static_cast<const int *>(h->batch_meta);
+    a.btbl_off = reinterpret_cast<const int64_t *>(
+        static_cast<char *>(h->batch_meta) + align_up((kBatchMaxN + 1) * sizeof(int), 256));
+    a.btbls = static_cast<const unsigned char *>(h->batch_tables);
+    if (bw == 128 && !h->batch_tables) return JSVD_HIP_ERROR;
     a.max_inner_sweeps = o.max_inner_sweeps > 0 ? o.max_inner_sweeps : choose_inner_sweeps(m, n);
     a.upd_rows = (int)upd_rows_g;
     a.upd_chunks_g = (int)((m + upd_rows_g - 1) / upd_rows_g);
@@ -816,7 +828,7 @@ int check_batched_sizes(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t m
 }
 
 int check_opts(const jsvd_opts &o) {
-    if (o.block_w != 0 && o.block_w != 16 && o.block_w != 32) return -1;
+    if (o.block_w != 0 && o.block_w != 16 && o.block_w != 32 && o.block_w != 64) return -1;
     if (o.strategy < JSVD_STRAT_RREV || o.strategy > JSVD_STRAT_RR) return -1;
     if (o.max_sweeps < 1 || o.max_inner_sweeps < 0) return -1;
     if (o.qr < 0 || o.qr > 2) return -1;
@@ -896,7 +908,7 @@ int jsvd_set_tuning(jsvd_handle_t h, const jsvd_tuning *t) {
     }
     if (t->count < 0 || t->count > 8) return -2;
     for (int i = 0; i < t->count; ++i) {
-        if (t->block_w[i] != 16 && t->block_w[i] != 32) return -2;
+        if (t->block_w[i] != 16 && t->block_w[i] != 32 && t->block_w[i] != 64) return -2;
         if (i > 0 && t->n_upper[i] <= t->n_upper[i - 1]) return -2;
         if (t->gram_wg[i] != 0 && (t->gram_wg[i] < 64 || t->gram_wg[i] > 8192)) return -2;
         if (t->update_wg[i] != 0 && (t->update_wg[i] < 64 || t->update_wg[i] > 8192)) return -2;
@@ -1316,11 +1328,15 @@ int jsvd_workspace_size(jsvd_handle_t h, int64_t m, int64_t n, const jsvd_opts *
     // R^T (n x n); the hyperbolic SVD adds the input column permutation
     auto solve_bytes = [&](int64_t mm, int64_t nn, bool hsvd) {
         const Shapes shp = pick_shapes(h, o, mm, nn);
-        const int w = shp.w;
-        const int order = strategy_order((int)((nn + w - 1) / w));
-        int64_t rps = 0;
-        const int splits = gram_splits(mm, order / 2, shp.gram_wg, &rps);
-        return plan(mm, nn, 2 * w, order / 2, splits, hsvd).total;
+        auto bytes_at = [&](int w) {
+            const int order = strategy_order((int)((nn + w - 1) / w));
+            int64_t rps = 0;
+            const int splits = gram_splits(mm, order / 2, shp.gram_wg, &rps);
+            return plan(mm, nn, 2 * w, order / 2, splits, hsvd).total;
+        };
+        // w = 64 falls back to 32 for the hyperbolic SVD and the scaled mode
+        if (shp.w == 64) return hsvd ? bytes_at(32) : std::max(bytes_at(64), bytes_at(32));
+        return bytes_at(shp.w);
     };
     size_t total = std::max(solve_bytes(m, n, false), solve_bytes(m, n, true));
     if (wants_qr(h, o, m, n)) total = std::max(total, solve_bytes(n, n, false)) + qr_plan(m, n).total;

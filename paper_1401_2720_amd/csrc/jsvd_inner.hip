@@ -5,6 +5,7 @@
 // to V (eq. (2.9)): V lies off the path from one p-step's Gram matrices to
 // the next, and these workgroups stream it through HBM on the CUs that the
 // pivot pairs leave idle.
+#include "jsvd_blocked.h"
 #include "jsvd_rows.h"
 
 namespace jsvd {
@@ -462,9 +463,221 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
     }
 }
 
+// ----------------------------------------------------------- inner, 2w = 128
+// The third blocking level.  R and V' of a 128-column pivot pair (128 KiB
+// each) do not both fit in LDS, so, as Section 2 does one level up, the
+// inner problem is itself solved by the block method: the Cholesky factor
+// R of H_pq is written to a global scratch (L2-resident) and a block Jacobi
+// with 16-column sub-blocks runs on it (sub-block Gram matrices, their
+// Cholesky factors, one pointwise sweep each and the sub-updates on FP64
+// MFMA, as the batched path's blocked method: blocked_sweeps), accumulating
+// V' directly in the pair's slot of the V' buffer.  max_inner_sweeps bounds
+// the block sweeps of that inner method (1: block-oriented).  Ordinary SVD,
+// unscaled; the sub-level strategy is the reverse row-cyclic one.
+// 512 threads (kBlkThreads).  Extra workgroups after the pairs' apply the
+// previous p-step's V' to V, as in inner_kernel.
+constexpr int kW128Threads = kBlkThreads;
+
+__global__ __launch_bounds__(kW128Threads) void inner128_kernel(StepArgs a) {
+    constexpr int BW = 128, LD = BW + 1, NT = kW128Threads, NWAVES = NT / 64;
+    constexpr int EPT = BW * BW / NT;  // Gram entries summed per thread
+    __shared__ double L[BW * LD];      // H, then R; then the block method's R'' and V''
+    __shared__ int sflag[2];           // [0] NaN or infinite pivot, [1] zero pivots
+    __shared__ int stats[3];           // rotations, proper rotations, sub-pair updates
+    static_assert(kBlkLdsDoubles <= BW * LD, "the block method's LDS fits in L");
+    static_assert(BW * BW <= BW * LD, "V' of the V workgroups fits in L");
+
+    if (blockIdx.x >= a.npairs) {
+        __builtin_amdgcn_s_sleep(127);
+        __builtin_amdgcn_s_sleep(127);
+        const int idx = blockIdx.x - a.npairs;
+        const int vpair = idx / a.prev_chunks, chunk = idx % a.prev_chunks;
+        if (a.prev_pair_rot[vpair] == 0) return;
+        const int64_t r0 = (int64_t)chunk * a.prev_rows;
+        const int64_t r1 = min(a.n, r0 + (int64_t)a.prev_rows);
+        update_rows<BW, NWAVES, 1, true>(a.V, a.ldv, r0, r1, a.prev_pairs[vpair], a.w, a.n,
+                                         a.prev_vprime + (size_t)vpair * BW * BW, L);
+        return;
+    }
+    const int pair = blockIdx.x;
+    const int2 pq = a.pairs[pair];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if ((int64_t)pq.x * a.w >= a.n) {
+        if (tid == 0) a.pair_rot[pair] = 0;
+        return;
+    }
+
+    // ---- H_pq: the partial Gram matrices summed in split order (upper
+    // triangle); padding columns become unit vectors
+    {
+        const double *hp = a.hpart + (size_t)pair * a.splits * BW * BW;
+        double sacc[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) sacc[u] = 0.0;
+        for (int sp = 0; sp < a.splits; ++sp)
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                const int e = tid + u * NT;
+                if (e / BW <= e % BW) sacc[u] += hp[(size_t)sp * BW * BW + e];
+            }
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + u * NT, i = e / BW, j = e % BW;
+            double h = (i <= j) ? sacc[u] : 0.0;
+            if (i <= j && (pair_col(i, a.w, pq) >= a.n || pair_col(j, a.w, pq) >= a.n))
+                h = (i == j) ? 1.0 : 0.0;
+            L[j * LD + i] = h;
+        }
+    }
+    if (tid < 2) sflag[tid] = 0;
+    if (tid < 3) stats[tid] = 0;
+    __syncthreads();
+
+    // ---- nothing to do when every (i, j) passes the orthogonality test of
+    // the sub-level (c(eps) = eps sqrt(32), the smaller of the two levels')
+    {
+        const double tol = kEps * sqrt((double)kBlkBW);
+        bool need = false;
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + u * NT, i = e / BW, j = e % BW;
+            if (i < j) {
+                const double hij = L[j * LD + i], hii = L[i * LD + i], hjj = L[j * LD + j];
+                need = need || (hij != 0.0 && !(fabs(hij) <= tol * sqrt(hii) * sqrt(hjj)));
+            }
+        }
+        if (!__syncthreads_or(need ? 1 : 0)) {
+            if (tid == 0) a.pair_rot[pair] = 0;
+            return;
+        }
+    }
+
+    // ---- Cholesky H = R^T R (Section 4.1) by block rows of 16: wave 0 factors
+    // a block row, lane j holding columns j and j + 64 (readlane broadcasts the
+    // pivots and multipliers), then the block row's contribution leaves the
+    // trailing part of H on FP64 MFMA, 16 x 16 tiles spread over the waves.
+    // Non-positive pivots make their row zero; NaN or infinite ones stop the
+    // pair (as in inner_kernel).
+#pragma unroll 1
+    for (int kb = 0; kb < BW / 16; ++kb) {
+        if (wave == 0) {
+            double hb[2][16];
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) hb[hh][i] = L[(lane + 64 * hh) * LD + 16 * kb + i];
+            int zero_pivots = 0, nan_met = 0;
+            const int ph = kb >= 4 ? 1 : 0;  // half holding the panel's own columns
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int kk = 16 * kb + k;
+                const double hkk = lane_value(ph ? hb[1][k] : hb[0][k], kk - 64 * ph);
+                const bool bad = !(fabs(hkk) <= 0x1.fffffffffffffp+1023);
+                const bool pos = !bad && hkk > 0.0;
+                nan_met |= bad ? 1 : 0;
+                zero_pivots += (!bad && !pos) ? 1 : 0;
+                double rs, d;
+                rsqrt_sqrt(pos ? hkk : 1.0, rs, d);
+                double rr[2];
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh) {
+                    const int j = lane + 64 * hh;
+                    double r = (j == kk) ? d : hb[hh][k] * rs;
+                    rr[hh] = (pos && j >= kk) ? r : 0.0;
+                    hb[hh][k] = rr[hh];
+                }
+#pragma unroll
+                for (int i = k + 1; i < 16; ++i) {
+                    const double ri = lane_value(ph ? rr[1] : rr[0], 16 * kb + i - 64 * ph);
+#pragma unroll
+                    for (int hh = 0; hh < 2; ++hh) hb[hh][i] = fma(-ri, rr[hh], hb[hh][i]);
+                }
+            }
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const int j = lane + 64 * hh;
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    L[j * LD + 16 * kb + i] = (j >= 16 * kb + i) ? hb[hh][i] : 0.0;
+            }
+            if (lane == 0) {
+                sflag[0] |= nan_met;
+                sflag[1] += zero_pivots;
+            }
+        }
+        __syncthreads();
+        if (kb + 1 < BW / 16) {
+            // H(i, j) -= sum_k R(16 kb + k, i) R(16 kb + k, j), tiles kb < ti <= tj
+            constexpr int TB = BW / 16;
+            const int rest = TB - 1 - kb, ntiles = rest * (rest + 1) / 2;
+            for (int idx = wave; idx < ntiles; idx += NWAVES) {
+                int ti = kb + 1, rem = idx;
+                while (rem >= TB - ti) {
+                    rem -= TB - ti;
+                    ++ti;
+                }
+                const int tj = ti + rem;
+                const int l16 = lane & 15, l4 = lane >> 4;
+                d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int k = 16 * kb + 4 * c + l4;
+                    acc = mfma16(L[(16 * ti + l16) * LD + k], L[(16 * tj + l16) * LD + k], acc);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 16 * ti + l4 + 4 * v, j = 16 * tj + l16;
+                    if (i <= j) L[j * LD + i] -= acc[v];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (sflag[0]) {
+        if (tid == 0) {
+            a.pair_rot[pair] = 0;
+            atomicAdd(&a.counters[C_NONFINITE], 1ull);
+        }
+        return;
+    }
+    if (tid == 0 && sflag[1]) atomicAdd(&a.counters[C_BREAKDOWN], (unsigned long long)sflag[1]);
+
+    // ---- R to the pair's scratch (upper triangle, zeros below), V' := I in
+    // the pair's V' slot, then the block method on R
+    double *Rg = a.rscratch + (size_t)pair * BW * BW;
+    double *Vg = a.vprime + (size_t)pair * BW * BW;
+    for (int e = tid; e < BW * BW; e += NT) {
+        const int i = e % BW, j = e / BW;
+        Rg[e] = (i <= j) ? L[j * LD + i] : 0.0;
+        Vg[e] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int r = blocked_sweeps(Rg, Vg, BW, BW, max(1, min(a.max_inner_sweeps, 0xffff)),
+                                 a.btbl_order, a.btbl_off, a.btbls, L, stats);
+    __syncthreads();
+    if (tid == 0) {
+        if (r & kBlkNonfinite) {
+            a.pair_rot[pair] = 0;
+            atomicAdd(&a.counters[C_NONFINITE], 1ull);
+        } else {
+            const int rot = stats[0];
+            a.pair_rot[pair] = rot;
+            atomicAdd(&a.counters[C_ROT], (unsigned long long)rot);
+            atomicAdd(&a.counters[C_PROPER], (unsigned long long)stats[1]);
+            atomicAdd(&a.counters[C_INNER_SW], (unsigned long long)(r & 0xffff));
+            if (rot) atomicAdd(&a.counters[C_UPDATES], 1ull);
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_inner(int bw, const StepArgs &a, hipStream_t s) {
+    if (bw == 128) {
+        hipLaunchKernelGGL(inner128_kernel, dim3(a.npairs * (1 + a.prev_chunks)),
+                           dim3(kW128Threads), 0, s, a);
+        return hipGetLastError();
+    }
     const dim3 grid(a.npairs * (1 + a.prev_chunks));
     const bool hyp = a.n_plus < a.n;
     const dim3 blk(InnerCfg<32>::kThreads), blk64(InnerCfg<64>::kThreads);

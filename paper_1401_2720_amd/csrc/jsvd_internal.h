@@ -68,6 +68,13 @@ struct StepArgs {
     // D^-1 H D^-1 (D = diag(2^e_c)), the inner kernel works on R D^-1 and
     // writes the exponents of the transformed columns.  Null: not scaled.
     int *colexp;
+    // 2w = 128 (the third blocking level): per pivot pair a 128 x 128
+    // scratch for the Cholesky factor R, and the strategy tables of the
+    // block method inside the pair (every order up to 256, zero-based pairs)
+    double *rscratch;
+    const int *btbl_order;
+    const int64_t *btbl_off;
+    const unsigned char *btbls;
 };
 
 hipError_t launch_gram(int bw, const StepArgs &a, hipStream_t s);

@@ -23,10 +23,11 @@ __global__ __launch_bounds__(256) void update_kernel(StepArgs a) {
     const int64_t r0 = (int64_t)chunk * a.upd_rows;
     const int64_t r1 = min(rows, r0 + (int64_t)a.upd_rows);
     const double *vpr = a.vprime + (size_t)pair * BW * BW;
+    constexpr int JB = BW == 128 ? 4 : BW / 16;  // result tiles accumulated at a time
     if (isV)
-        update_rows<BW, 4, BW / 16, true>(a.V, a.ldv, r0, r1, a.pairs[pair], a.w, a.n, vpr, vs);
+        update_rows<BW, 4, JB, true>(a.V, a.ldv, r0, r1, a.pairs[pair], a.w, a.n, vpr, vs);
     else
-        update_rows<BW, 4, BW / 16>(a.G, a.ldg, r0, r1, a.pairs[pair], a.w, a.n, vpr, vs);
+        update_rows<BW, 4, JB>(a.G, a.ldg, r0, r1, a.pairs[pair], a.w, a.n, vpr, vs);
 }
 
 }  // namespace
@@ -36,8 +37,10 @@ hipError_t launch_update(int bw, const StepArgs &a, hipStream_t s) {
     if (grid.x == 0) return hipSuccess;
     if (bw == 32)
         hipLaunchKernelGGL(update_kernel<32>, grid, dim3(256), 0, s, a);
-    else
+    else if (bw == 64)
         hipLaunchKernelGGL(update_kernel<64>, grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(update_kernel<128>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -113,6 +113,13 @@ CASES = [
     ("round_robin_ragged300x200_w16", 300, 200, dict(block_w=16, strategy="rr"), "gauss"),
     ("round_robin_full_block_graded256_w32", 256, 256,
      dict(block_w=32, strategy="rr", max_inner_sweeps=30), "graded"),
+    # w = 64: the third blocking level (a block Jacobi with 16-column
+    # sub-blocks on the Cholesky factor of each 128-column pivot pair)
+    ("w64_ragged400x300", 400, 300, dict(block_w=64), "gauss"),
+    ("w64_graded512", 512, 512, dict(block_w=64), "graded"),
+    ("w64_full_block_ragged330x260_c", 330, 260,
+     dict(block_w=64, strategy="c", max_inner_sweeps=30), "gauss"),
+    ("w64_narrow200x90", 200, 90, dict(block_w=64), "gauss"),
 ]
 
 
@@ -266,6 +273,26 @@ def test_hsvd_matches_oracle(name, m, n, n_plus, shuffle, kw):
     assert np.max(np.abs(U.T @ U - np.eye(n))) <= 1e-13 * n
     assert np.all(np.diff(S[:npl]) <= 0) and np.all(np.diff(S[npl:]) >= 0)
     _say(f"  sweeps={info['sweeps']} clamps={info['hyp_clamps']}")
+
+
+def test_w64_falls_back_to_w32_for_hsvd_and_scaled_mode():
+    """The third blocking level runs the ordinary unscaled SVD; asked for
+    w = 64, the hyperbolic SVD and the scaled mode run with w = 32."""
+    g = inputs.rng(16)
+    G = inputs.gaussian(120, 100, g)
+    J = np.concatenate([np.ones(60), -np.ones(40)]).astype(np.int8)
+    U, S, V, Jout, info = _run_hsvd(G, J, block_w=64)
+    assert info["status"] == 0 and info["block_w"] == 32
+    ref = oracle.gesvj(G, n_plus=60)
+    assert np.all(np.abs(S - ref["S"]) <= 1e-12 * ref["S"] + 1e-13 * ref["S"].max())
+    A = inputs.gaussian(150, 130, g)
+    U, S, V, info = _run_gesvd(A, block_w=64, scaled="on")
+    assert info["status"] == 0 and info["block_w"] == 32 and info["scaled"] == 1
+    U, S, V, info = _run_gesvd(A, block_w=64)
+    assert info["status"] == 0 and info["block_w"] == 64 and info["scaled"] == 0
+    ref = oracle.gesvj(A)
+    _check_sigma(S, ref["S"], strict_rel=1e-12)
+    _check_svd(A, U, S, V, 130)
 
 
 def test_hsvd_identity_signature_equals_svd():
