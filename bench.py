@@ -40,8 +40,10 @@ def parse():
                     help="target length of the oracle sample (0 = skip)")
     ap.add_argument("--no-forms", action="store_true",
                     help="leave the batched and differentiable forms out of the svd4096 line")
-    ap.add_argument("--workload", default="svd4096", choices=["svd4096", "batched", "backward"],
-                    help="svd4096: the benchmark line; batched / backward: the other forms")
+    ap.add_argument("--workload", default="svd4096",
+                    choices=["svd4096", "tall", "batched", "backward"],
+                    help="svd4096: the benchmark line; tall: the 8192 x 2048 graded SVD (QR "
+                         "preprocessing); batched / backward: the other forms")
     return ap.parse_args()
 
 
@@ -307,12 +309,72 @@ def bench_backward(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_tall(args):
+    """The tall workload: 8192 x 2048, Q1 diag(sigma) Q2^T with sigma
+    log-spaced 1 .. 1e-10 (seed 3), through jsvd_gesvd (QR preprocessing of
+    eq. (2.1), the Jacobi method on R^T); one step = one SVD, the input
+    restored from a device copy first."""
+    import numpy as np
+    import torch
+
+    import paper_1401_2720_amd as jsvd
+    from paper_1401_2720_amd import _binding as B
+    from paper_1401_2720_amd import inputs
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    A_host = inputs.tall_graded()
+    m, n = A_host.shape
+    A0 = torch.from_numpy(A_host).to(dev).t().contiguous()  # column-major copy (n x m)
+    work = torch.empty_like(A0)
+    S = torch.empty(n, dtype=torch.float64, device=dev)
+    V = torch.empty((n, n), dtype=torch.float64, device=dev)
+    L = jsvd.lib()
+    h = B._handle(0, torch.cuda.current_stream(dev).cuda_stream)
+    opts = B.make_opts()
+    info = B.Info()
+
+    def step():
+        work.copy_(A0)
+        rc = L.jsvd_gesvd(h, m, n, ctypes.c_void_p(work.data_ptr()), m,
+                          ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(V.data_ptr()), n,
+                          ctypes.byref(opts), ctypes.byref(info))
+        if rc != 0:
+            raise B.JsvdError(rc, "jsvd_gesvd")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sweeps = []
+    for _ in range(args.steps):
+        step()
+        sweeps.append(info.sweeps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    sig = inputs.logspaced(n, -10.0)
+    s = S.cpu().numpy()
+    out = {"metric": "FP64 SVD time (s) at 8192x2048", "value": ms / 1e3, "unit": "s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "svd_tall_graded_8192x2048", "m": m, "n": n, "seed": 3,
+                      "block_w": info.block_w, "preprocessed": info.preprocessed,
+                      "sweeps": sweeps},
+           "accuracy": {"max_abs_sigma_err": float(np.max(np.abs(s - sig))),
+                        "max_rel_sigma_err_above_1e-3": float(np.max(
+                            np.abs(s - sig)[sig >= 1e-3] / sig[sig >= 1e-3]))},
+           "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU level is not part of "
               "it); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "tall":
+        return bench_tall(args)
     if args.workload == "batched":
         return bench_batched(args)
     if args.workload == "backward":
