@@ -105,8 +105,12 @@ typedef struct {
     int32_t block_w;           /* w actually used */
     int32_t n_blocks;          /* block-columns in the pivot strategy (with padding) */
     double seconds;            /* wall time of the call */
-    int32_t preprocessed;      /* 1 if the Jacobi method ran on R^T of a QR of G (eq. (2.1)) */
+    int32_t preprocessed;      /* 1 if the Jacobi method ran on R^T of a QR of G (eq. (2.1));
+                                  2 if G was rank deficient and it ran on the L_0 of the
+                                  LQ factorization (2.2) after a QR with column pivoting */
     int32_t scaled;            /* 1 if the scaled mode ran (opts.scaled) */
+    int32_t rank;              /* preprocessed == 2: the numerical rank k of G (the number
+                                  of singular values computed as positive); else n */
 } jsvd_info;
 
 /*
@@ -179,8 +183,15 @@ int jsvd_destroy(jsvd_handle_t h);
  * Householder reflections (eq. (2.1); column presorting in place of column
  * pivoting), the Jacobi method runs on R^T (n x n) giving R^T V_x = U_x Sigma,
  * and U = Q [V_x; 0], V = P U_x.  If R is numerically singular (some
- * |r_ii| <= n 2^-53 max |r_jj|) the call solves G directly instead, so that
- * V stays orthogonal and zero singular values stay exact.
+ * |r_ii| <= n 2^-53 max |r_jj|), G is rank deficient: R is factored again
+ * with column pivoting, R P_2 = Q_2 [R_0; ~0] (R_0 k x n, k the numerical
+ * rank: the pivoted norms fall to n 2^-53 of the first), R_0 by the LQ
+ * factorization R_0 = [L_0 0] Q_3^T (eq. (2.2)), the Jacobi method runs on
+ * L_0 (k x k) giving L_0 V_x = U_x Sigma_k, and U = Q [Q_2 [U_x; 0]; 0] (the
+ * other n - k columns zero), V = P P_2 Q_3 [V_x 0; 0 I], Sigma = (Sigma_k, 0)
+ * (info->preprocessed = 2, info->rank = k).  If a factorization's grid
+ * barrier cannot complete (other work on the device keeps some of its
+ * workgroups from starting), or k = 0, the call solves G directly instead.
  * The QR path needs m <= 32768.
  * Returns JSVD_OK, a negative argument index, JSVD_NOT_CONVERGED,
  * JSVD_NONFINITE, JSVD_HIP_ERROR or JSVD_NO_MEMORY.

@@ -32,7 +32,8 @@ class Info(ctypes.Structure):
     _fields_ = [("sweeps", _i32), ("converged", _i32), ("rotations", _i64),
                 ("proper_rotations", _i64), ("inner_sweeps", _i64), ("pair_updates", _i64),
                 ("chol_breakdowns", _i32), ("hyp_clamps", _i32), ("block_w", _i32),
-                ("n_blocks", _i32), ("seconds", _dbl), ("preprocessed", _i32), ("scaled", _i32)]
+                ("n_blocks", _i32), ("seconds", _dbl), ("preprocessed", _i32), ("scaled", _i32),
+                ("rank", _i32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -54,6 +54,8 @@ struct jsvd_handle_s {
     int64_t colexp_cap = 0;
     void *qr_ws = nullptr;          // QR preprocessing workspace (kept apart from ws,
     size_t qr_ws_bytes = 0;         // which the Jacobi solve of R^T may reallocate)
+    void *qr_ws2 = nullptr;         // rank-deficient G: the pivoted QR of R and the LQ step
+    size_t qr_ws2_bytes = 0;
     int qr_resident = 0;            // QR panel workgroups that can be resident at once
     void *noalloc_scratch = nullptr;  // device address of this device's fixed scratch
     // per-kernel timing (measurement aid): 4 events per p-step
@@ -386,6 +388,7 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     inf.block_w = w;
     inf.scaled = scaled ? 1 : 0;
     inf.n_blocks = order;
+    inf.rank = (int32_t)n;
     int status = JSVD_OK;
     bool converged = false;
     if (h->timing) {
@@ -660,6 +663,24 @@ int hh_apply_q(jsvd_handle_s *h, const QrWork &w, int64_t m, int64_t n, double *
     return JSVD_OK;
 }
 
+// T of each panel of reflectors that are already in w.W (m rows, ld m, n of
+// them, tau in w.tau), so that hh_apply_q can apply them: the part of
+// hh_factor that follows the panel factorization.
+int hh_build_t(jsvd_handle_s *h, const QrWork &w, int64_t m, int64_t n) {
+    hipStream_t st = h->stream;
+    constexpr int NB = kQrPanel;
+    const int64_t npan = (n + NB - 1) / NB;
+    for (int64_t p = 0; p < npan; ++p) {
+        const int64_t j = p * NB;
+        const int nb = (int)std::min<int64_t>(NB, n - j);
+        HIP_TRY(launch_qr_extract_v(w.W, m, m, j, nb, w.Vp, m, st));
+        int rc = gemm_splitk(w.Vp, m, w.Vp, m, NB, NB, m - j, w.parts, w.Y1, st);
+        if (rc) return rc;
+        HIP_TRY(launch_qr_t(w.Y1, w.tau + j, nb, w.T + p * NB * NB, st));
+    }
+    return JSVD_OK;
+}
+
 // Whether hh_factor completed and R (in w.W) is numerically nonsingular
 // (min |r_ii| > n 2^-53 max |r_jj|); one stream synchronisation, the values
 // read through the handle's pinned words.
@@ -675,6 +696,129 @@ int qr_check(jsvd_handle_s *h, const QrWork &w, int64_t m, int64_t n, bool *abor
     *aborted = *hab != 0;
     *singular = !(range[0] > (double)n * 0x1p-53 * range[1]);
     return JSVD_OK;
+}
+
+// Rank-deficient G after G P = Q_1 [R; 0] (eqs. (2.1)-(2.2)): the pivoted
+// QR of R, R P_2 = Q_2 [R_0; ~0] with R_0 k x n of full row rank k; the LQ
+// factorization of R_0 as the QR of R_0^T = Q_3 [L_0^T; 0]; the Jacobi method
+// on L_0 (k x k), L_0 V_x = U_x Sigma_k; then
+//   U = Q_1 [Q_2 [U_x; 0]; 0] (k columns; the other n - k zero),
+//   V = P P_2 Q_3 [V_x 0; 0 I_(n-k)],  Sigma = (Sigma_k, 0).
+// Sets *fallback (nothing written to A, S, V) when a factorization's grid
+// barrier did not complete or k = 0; the caller then solves G directly.
+int gesvd_rank_deficient(jsvd_handle_s *h, const QrWork &w1, int64_t m, int64_t n, double *A,
+                         int64_t lda, double *S, double *V, int64_t ldv, const jsvd_opts &o,
+                         jsvd_info *info, bool *fallback,
+                         std::chrono::steady_clock::time_point t0) {
+    hipStream_t st = h->stream;
+    constexpr int NB = kQrPanel;
+    *fallback = true;
+    const int64_t nn = n * n;
+    const int64_t npan = (n + NB - 1) / NB;
+    const int nwg = (int)std::max<int64_t>(
+        1, std::min<int64_t>({n, (int64_t)std::max(1, h->cu_count), (int64_t)qrcp_resident(h->cu_count)}));
+    // workspace: seven n x n matrices, the two reflector sets' T, tau, the
+    // pivoted QR's norms and candidates, and the GEMM scratch of hh_*
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off += align_up(bytes, 256); return at; };
+    const size_t oRn = take(nn * 8), oR2 = take(nn * 8), oX = take(nn * 8), oL0 = take(nn * 8),
+                 oVx = take(nn * 8), oB1 = take(nn * 8), oC = take(nn * 8),
+                 oT2 = take(npan * NB * NB * 8), oT3 = take(npan * NB * NB * 8),
+                 oTau2 = take(n * 8), oTau3 = take(n * 8), oVn1 = take(n * 8), oVn2 = take(n * 8),
+                 oCv = take(2 * (size_t)nwg * 8), oCi = take(2 * (size_t)nwg * 4),
+                 oJp = take(n * 4), oRow = take(n * 4), oVp = take((size_t)n * NB * 8),
+                 oParts = take((size_t)32 * NB * n * 8), oY1 = take((size_t)NB * n * 8),
+                 oY2 = take((size_t)NB * n * 8), oPart = take((size_t)2 * 64 * NB * 8),
+                 oProw = take((size_t)2 * NB * 8), oBar = take(128);
+    if (off > h->qr_ws2_bytes) {
+        if (h->qr_ws2) {
+            if (hipStreamSynchronize(st) != hipSuccess) return JSVD_HIP_ERROR;
+            (void)hipFree(h->qr_ws2);
+        }
+        h->qr_ws2 = nullptr;
+        h->qr_ws2_bytes = 0;
+        if (hipMalloc(&h->qr_ws2, off) != hipSuccess) {
+            h->qr_ws2 = nullptr;
+            return JSVD_NO_MEMORY;
+        }
+        h->qr_ws2_bytes = off;
+    }
+    char *ws = static_cast<char *>(h->qr_ws2);
+    auto d = [&](size_t o2) { return reinterpret_cast<double *>(ws + o2); };
+    double *Rn = d(oRn), *R2 = d(oR2), *X = d(oX), *L0 = d(oL0), *Vx = d(oVx), *B1 = d(oB1),
+           *C = d(oC);
+    int *jpvt = reinterpret_cast<int *>(ws + oJp), *rowof = reinterpret_cast<int *>(ws + oRow);
+    unsigned *bar = reinterpret_cast<unsigned *>(ws + oBar);
+    int *abort_flag = reinterpret_cast<int *>(ws + oBar + 8);
+    int *rank_d = reinterpret_cast<int *>(ws + oBar + 16);
+    // the reflector sets of the pivoted QR (in R2) and of the LQ step (in X)
+    QrWork w2{}, w3{};
+    for (QrWork *q : {&w2, &w3}) {
+        q->Vp = d(oVp); q->parts = d(oParts); q->Y1 = d(oY1); q->Y2 = d(oY2);
+        q->part = d(oPart); q->prow = d(oProw); q->bar = bar; q->abort_flag = abort_flag;
+        q->d_range = d(oBar + 64);
+    }
+    w2.W = R2; w2.T = d(oT2); w2.tau = d(oTau2);
+    w3.W = X; w3.T = d(oT3); w3.tau = d(oTau3);
+
+    // R P_2 = Q_2 R_2 with column pivoting, stopped at the numerical rank k
+    HIP_TRY(hipMemcpy2DAsync(Rn, (size_t)n * 8, w1.W, (size_t)m * 8, (size_t)n * 8, (size_t)n,
+                             hipMemcpyDeviceToDevice, st));
+    HIP_TRY(launch_zero_lower(Rn, n, n, st));
+    QrcpArgs qa;
+    qa.W = Rn; qa.ldw = n; qa.rows = n; qa.ncols = n; qa.tau = w2.tau; qa.jpvt = jpvt;
+    qa.vn1 = d(oVn1); qa.vn2 = d(oVn2); qa.cand_v = d(oCv);
+    qa.cand_i = reinterpret_cast<int *>(ws + oCi); qa.rank = rank_d; qa.bar = bar;
+    qa.abort_flag = abort_flag; qa.nwg = nwg; qa.tol = (double)n * 0x1p-53;
+    HIP_TRY(launch_qrcp(qa, st));
+    int *hk = reinterpret_cast<int *>(h->host_counters + kSlotFlag);
+    int *hab = reinterpret_cast<int *>(h->host_counters + kSlotFlag + 1);
+    HIP_TRY(hipMemcpyAsync(hk, rank_d, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hab, abort_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int64_t k = *hk;
+    if (*hab != 0 || k <= 0) return JSVD_OK;  // fall back
+    // R_2 in pivoted (logical) column order, then X = R_0^T (n x k)
+    HIP_TRY(launch_gather_cols(Rn, n, R2, n, n, n, jpvt, nullptr, nullptr, st));
+    HIP_TRY(launch_trap_transpose(R2, n, k, n, X, n, st));
+    // LQ of R_0: X = Q_3 [L_0^T; 0]
+    int rc = hh_factor(h, w3, n, k);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(hab, abort_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (*hab != 0) return JSVD_OK;  // fall back
+    *fallback = false;
+    HIP_TRY(launch_r_transpose(X, n, k, L0, k, st));
+    // the Jacobi method on L_0: L_0 V_x = U_x Sigma_k (L0 <- U_x)
+    jsvd_opts oj = o;
+    oj.want_v = 1;
+    oj.qr = 1;
+    oj.sort = 1;
+    jsvd_info inf{};
+    const int status = solve(h, k, k, L0, k, S, Vx, k, k, oj, &inf, false, nullptr);
+    if (status != JSVD_OK && status != JSVD_NOT_CONVERGED) return status;
+    HIP_TRY(launch_fill(S + k, n - k, 0.0, st));
+    // U = Q_1 [Q_2 [U_x; 0]; 0]
+    if ((rc = hh_build_t(h, w2, n, k))) return rc;
+    HIP_TRY(launch_embed(L0, k, k, B1, n, n, k, st));
+    if ((rc = hh_apply_q(h, w2, n, k, B1, n, k))) return rc;
+    HIP_TRY(launch_embed(B1, n, n, A, lda, m, k, st));
+    HIP_TRY(launch_fill2d(A + k * lda, lda, m, n - k, 0.0, st));
+    if ((rc = hh_apply_q(h, w1, m, n, A, lda, k))) return rc;
+    // V = P P_2 Q_3 [V_x 0; 0 I]
+    if (o.want_v) {
+        HIP_TRY(launch_embed(Vx, k, k, C, n, n, k, st));
+        HIP_TRY(launch_identity_cols(C + k * n, n, n, n - k, k, st));
+        if ((rc = hh_apply_q(h, w3, n, k, C, n, n))) return rc;
+        HIP_TRY(launch_compose(w1.perm, jpvt, n, rowof, st));
+        HIP_TRY(launch_scatter_rows(C, n, V, ldv, n, n, rowof, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    inf.preprocessed = 2;
+    inf.rank = (int32_t)k;
+    inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return status;
 }
 
 int gesvd_qr(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double *S,
@@ -697,6 +841,11 @@ int gesvd_qr(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, dou
     // untouched so far (the factorization works on the copy W).
     bool aborted = false, singular = false;
     if ((rc = qr_check(h, w, m, n, &aborted, &singular))) return rc;
+    if (!aborted && singular) {
+        bool fallback = false;
+        rc = gesvd_rank_deficient(h, w, m, n, A, lda, S, V, ldv, o, info, &fallback, t0);
+        if (!fallback) return rc;
+    }
     if (aborted || singular) {
         jsvd_opts od = o;
         od.qr = 1;
@@ -719,6 +868,7 @@ int gesvd_qr(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, dou
     if (o.want_v) HIP_TRY(launch_scatter_rows(w.X, n, V, ldv, n, n, w.perm, st));
     HIP_TRY(hipStreamSynchronize(st));
     inf.preprocessed = 1;
+    inf.rank = (int32_t)n;
     inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = inf;
     return status;
@@ -932,6 +1082,7 @@ int jsvd_destroy(jsvd_handle_t h) {
     if (h->batch_meta) (void)hipFree(h->batch_meta);
     if (h->host_counters) (void)hipHostFree(h->host_counters);
     if (h->qr_ws) (void)hipFree(h->qr_ws);
+    if (h->qr_ws2) (void)hipFree(h->qr_ws2);
     if (h->colexp) (void)hipFree(h->colexp);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     delete h;

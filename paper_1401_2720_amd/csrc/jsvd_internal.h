@@ -149,6 +149,31 @@ struct QrPanelArgs {
     int nwg;              // workgroups, <= 64 (all resident at once)
 };
 
+// QR with column pivoting of W (rows x ncols), in place, on nwg resident
+// workgroups (see jsvd_qr.hip).
+struct QrcpArgs {
+    double *W;
+    int64_t ldw, rows, ncols;
+    double *tau;           // [ncols] reflector scalars (the first rank used)
+    int *jpvt;             // [ncols] out: physical column at each position
+    double *vn1, *vn2;     // [ncols] partial norms, by physical column
+    double *cand_v;        // [2 nwg] per-workgroup pivot candidates
+    int *cand_i;           // [2 nwg]
+    int *rank;             // out: the numerical rank
+    unsigned *bar;         // grid barrier counter
+    int *abort_flag;       // set when a barrier does not complete
+    int nwg;
+    double tol;            // stop when the largest partial norm <= tol * the first pivot's
+};
+int qrcp_resident(int cu_count);
+hipError_t launch_qrcp(const QrcpArgs &a, hipStream_t s);
+hipError_t launch_trap_transpose(const double *W, int64_t ldw, int64_t k, int64_t ncols, double *X,
+                                 int64_t ldx, hipStream_t s);
+hipError_t launch_compose(const int *a, const int *b, int64_t n, int *out, hipStream_t s);
+hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill2d(double *B, int64_t ldb, int64_t rows, int64_t cols, double v,
+                         hipStream_t s);
+hipError_t launch_zero_lower(double *W, int64_t ldw, int64_t n, hipStream_t s);
 int qr_panel_groups(int64_t rows);
 int qr_panel_resident(int cu_count);  // panel workgroups that fit on the device at once
 hipError_t launch_qr_reset(unsigned *bar, int *abort_flag, hipStream_t s);

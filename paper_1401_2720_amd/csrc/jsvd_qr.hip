@@ -274,6 +274,225 @@ __global__ void diag_range_kernel(const double *W, int64_t ldw, int64_t n, doubl
     }
 }
 
+// ------------------------------------------------ QR with column pivoting
+// W (rows x ncols, ld ldw) in place by Householder reflections with column
+// pivoting (the P_c of eq. (2.1)), on a grid of nwg resident workgroups that
+// meet at grid barriers.  Physical column c belongs to workgroup c % nwg
+// and never moves; step j takes the free column of largest partial norm
+// (ties: smallest index) as pivot, its owner forms the reflector from rows
+// j .. rows-1 (LAPACK's convention: beta at row j, v below it with v(j) = 1
+// implicit), and every owner applies it to its free columns and downdates
+// their partial norms (recomputed when the downdate loses accuracy, as in
+// LAPACK's xLAQP2).  The factorization stops at the first step whose
+// largest partial norm is <= tol times the first pivot's, or at
+// min(rows, ncols): that step count is the numerical rank k.  jpvt[j] is
+// the physical column at position j (positions >= k: the remaining columns
+// in increasing order).  All reductions have a fixed order.
+struct QrcpShared {
+    double red[kQT];
+    int redi[kQT];
+};
+
+// Sum over the workgroup of v (one value per thread), fixed order; every
+// thread gets the result.
+__device__ __forceinline__ double wg_total(double v, QrcpShared &sh) {
+    const int t = threadIdx.x;
+    sh.red[t] = v;
+    __syncthreads();
+    for (int off = kQT / 2; off > 0; off >>= 1) {
+        if (t < off) sh.red[t] += sh.red[t + off];
+        __syncthreads();
+    }
+    const double r = sh.red[0];
+    __syncthreads();
+    return r;
+}
+
+// Largest (value, smallest index) over the workgroup; every thread gets it.
+__device__ __forceinline__ void wg_argmax(double v, int i, QrcpShared &sh, double &bv, int &bi) {
+    const int t = threadIdx.x;
+    sh.red[t] = v;
+    sh.redi[t] = i;
+    __syncthreads();
+    for (int off = kQT / 2; off > 0; off >>= 1) {
+        if (t < off) {
+            const double a = sh.red[t], b = sh.red[t + off];
+            const int ia = sh.redi[t], ib = sh.redi[t + off];
+            if (b > a || (b == a && ib < ia)) {
+                sh.red[t] = b;
+                sh.redi[t] = ib;
+            }
+        }
+        __syncthreads();
+    }
+    bv = sh.red[0];
+    bi = sh.redi[0];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kQT) void qrcp_kernel(QrcpArgs a) {
+    __shared__ QrcpShared sh;
+    const int wg = blockIdx.x, t = threadIdx.x;
+    const int64_t rows = a.rows;
+    const int nwg = a.nwg;
+    const int kmax = (int)min(rows, a.ncols);
+    unsigned epoch = 0;
+    // partial norms of the owned columns
+    for (int64_t c = wg; c < a.ncols; c += nwg) {
+        const double *col = a.W + c * a.ldw;
+        double s = 0.0;
+        for (int64_t i = t; i < rows; i += kQT) s = fma(col[i], col[i], s);
+        const double nrm = sqrt(wg_total(s, sh));
+        if (t == 0) {
+            a.vn1[c] = nrm;
+            a.vn2[c] = nrm;
+        }
+    }
+    __syncthreads();
+    double vmax0 = 0.0;
+    int k = kmax;
+    for (int j = 0; j < kmax; ++j) {
+        const int par = j & 1;
+        // the workgroup's candidate: largest partial norm of a free column
+        double bv = -1.0;
+        int bi = 0x7fffffff;
+        for (int64_t c = wg + (int64_t)t * nwg; c < a.ncols; c += (int64_t)kQT * nwg) {
+            const double v = a.vn1[c];
+            if (v > bv || (v == bv && c < bi)) {
+                bv = v;
+                bi = (int)c;
+            }
+        }
+        wg_argmax(bv, bi, sh, bv, bi);
+        if (t == 0) {
+            a.cand_v[par * nwg + wg] = bv;
+            a.cand_i[par * nwg + wg] = bi;
+        }
+        if (!grid_sync(a.bar, ++epoch * (unsigned)nwg, a.abort_flag)) return;
+        // the pivot: the same choice in every workgroup
+        double pv = -1.0;
+        int pc = 0x7fffffff;
+        if (t < nwg) {
+            pv = a.cand_v[par * nwg + t];
+            pc = a.cand_i[par * nwg + t];
+        }
+        wg_argmax(pv, pc, sh, pv, pc);
+        if (j == 0) vmax0 = pv;
+        if (!(pv > 0.0) || pv <= a.tol * vmax0) {
+            k = j;
+            break;
+        }
+        if (wg == 0 && t == 0) a.jpvt[j] = pc;
+        if (pc % nwg == wg) {
+            double *col = a.W + (int64_t)pc * a.ldw;
+            double s = 0.0;
+            for (int64_t i = j + 1 + t; i < rows; i += kQT) s = fma(col[i], col[i], s);
+            const double xn2 = wg_total(s, sh);
+            const double alpha = col[j];
+            double tau = 0.0, beta = alpha, scal = 0.0;
+            if (xn2 > 0.0) {
+                beta = -copysign(sqrt(fma(alpha, alpha, xn2)), alpha);
+                tau = (beta - alpha) / beta;
+                scal = 1.0 / (alpha - beta);
+            }
+            for (int64_t i = j + 1 + t; i < rows; i += kQT) col[i] *= scal;
+            if (t == 0) {
+                col[j] = beta;
+                a.tau[j] = tau;
+                a.vn1[pc] = -1.0;  // used
+            }
+        }
+        if (!grid_sync(a.bar, ++epoch * (unsigned)nwg, a.abort_flag)) return;
+        const double tauj = a.tau[j];
+        const double *v = a.W + (int64_t)pc * a.ldw;
+        for (int64_t c = wg; c < a.ncols; c += nwg) {
+            // used columns are skipped (vn1 < 0, written before the last
+            // grid barrier: the same value in every thread)
+            if (!(a.vn1[c] >= 0.0)) continue;
+            double *col = a.W + c * a.ldw;
+            if (tauj != 0.0) {
+                double s = (t == 0) ? col[j] : 0.0;
+                for (int64_t i = j + 1 + t; i < rows; i += kQT) s = fma(v[i], col[i], s);
+                const double z = tauj * wg_total(s, sh);
+                if (t == 0) col[j] -= z;
+                for (int64_t i = j + 1 + t; i < rows; i += kQT) col[i] = fma(-z, v[i], col[i]);
+            }
+            __syncthreads();
+            // partial norm of rows j+1 .. : downdate, or recompute when the
+            // downdate has cancelled most of it
+            const double n1 = a.vn1[c], n2 = a.vn2[c];
+            __syncthreads();  // every thread has read them before thread 0 writes
+            bool recompute = false;
+            double nn1 = n1;
+            if (n1 != 0.0) {
+                const double q = fabs(col[j]) / n1;
+                const double tmp = fmax(0.0, (1.0 - q) * (1.0 + q));
+                const double r = n1 / n2;
+                if (tmp * r * r <= 1.4901161193847656e-08)  // sqrt(2^-52)
+                    recompute = true;
+                else
+                    nn1 = n1 * sqrt(tmp);
+            }
+            if (recompute) {
+                double s = 0.0;
+                for (int64_t i = j + 1 + t; i < rows; i += kQT) s = fma(col[i], col[i], s);
+                nn1 = sqrt(wg_total(s, sh));
+            }
+            if (t == 0) {
+                a.vn1[c] = nn1;
+                if (recompute) a.vn2[c] = nn1;
+            }
+            __syncthreads();
+        }
+    }
+    if (wg == 0 && t == 0) {
+        // positions k .. ncols-1: the free columns, in increasing order
+        int pos = k;
+        for (int64_t c = 0; c < a.ncols; ++c)
+            if (a.vn1[c] >= 0.0) a.jpvt[pos++] = (int)c;
+        *a.rank = k;
+    }
+}
+
+// X (ncols x k, ld ldx) = the transpose of the first k rows of W's upper
+// trapezoid (zero below the diagonal): X(j, i) = (i <= j) ? W(i, j) : 0.
+__global__ void trap_transpose_kernel(const double *W, int64_t ldw, int64_t k, int64_t ncols,
+                                      double *X, int64_t ldx) {
+    const int64_t i = blockIdx.y;  // column of X = row of W
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ncols;
+         j += (int64_t)gridDim.x * blockDim.x)
+        X[j + i * ldx] = (i <= j) ? W[i + j * ldw] : 0.0;
+}
+
+// out[j] = a[b[j]]
+__global__ void compose_kernel(const int *a, const int *b, int64_t n, int *out) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x)
+        out[j] = a[b[j]];
+}
+
+__global__ void fill_kernel(double *x, int64_t n, double v) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x)
+        x[j] = v;
+}
+
+// B (rows x cols, ld ldb) = v
+__global__ void fill2d_kernel(double *B, int64_t ldb, int64_t rows, double v) {
+    const int64_t c = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * blockDim.x)
+        B[i + c * ldb] = v;
+}
+
+// the strictly lower triangle of the n x n W (ld ldw) := 0
+__global__ void zero_lower_kernel(double *W, int64_t ldw, int64_t n) {
+    const int64_t c = blockIdx.y;
+    for (int64_t i = c + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        W[i + c * ldw] = 0.0;
+}
+
 __global__ void qr_reset_kernel(unsigned *bar, int *abort_flag) {
     if (threadIdx.x == 0) {
         if (bar) *bar = 0u;
@@ -282,6 +501,61 @@ __global__ void qr_reset_kernel(unsigned *bar, int *abort_flag) {
 }
 
 }  // namespace
+
+int qrcp_resident(int cu_count) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(&qrcp_kernel), kQT, 0) != hipSuccess)
+        return 0;
+    return per_cu * cu_count;
+}
+
+// The abort flag is reset with the barrier; a barrier that cannot complete
+// (some of the nwg workgroups could not start beside other work on the
+// device) sets it after its spin bound and every workgroup leaves.
+hipError_t launch_qrcp(const QrcpArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(qr_reset_kernel, dim3(1), dim3(64), 0, s, a.bar, a.abort_flag);
+    hipLaunchKernelGGL(qrcp_kernel, dim3((unsigned)a.nwg), dim3(kQT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_trap_transpose(const double *W, int64_t ldw, int64_t k, int64_t ncols, double *X,
+                                 int64_t ldx, hipStream_t s) {
+    if (k <= 0) return hipSuccess;
+    const int64_t bx = std::max<int64_t>(1, std::min<int64_t>((ncols + 255) / 256, 16));
+    hipLaunchKernelGGL(trap_transpose_kernel, dim3((unsigned)bx, (unsigned)k), dim3(256), 0, s, W,
+                       ldw, k, ncols, X, ldx);
+    return hipGetLastError();
+}
+
+hipError_t launch_compose(const int *a, const int *b, int64_t n, int *out, hipStream_t s) {
+    hipLaunchKernelGGL(compose_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 64)),
+                       dim3(256), 0, s, a, b, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill2d(double *B, int64_t ldb, int64_t rows, int64_t cols, double v,
+                         hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    const int64_t bx = std::max<int64_t>(1, std::min<int64_t>((rows + 255) / 256, 16));
+    hipLaunchKernelGGL(fill2d_kernel, dim3((unsigned)bx, (unsigned)cols), dim3(256), 0, s, B, ldb,
+                       rows, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_lower(double *W, int64_t ldw, int64_t n, hipStream_t s) {
+    const int64_t bx = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16));
+    hipLaunchKernelGGL(zero_lower_kernel, dim3((unsigned)bx, (unsigned)n), dim3(256), 0, s, W, ldw,
+                       n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 64)),
+                       dim3(256), 0, s, x, n, v);
+    return hipGetLastError();
+}
 
 int qr_panel_groups(int64_t rows) {
     const int64_t per = (int64_t)kQT * kRpt;

@@ -84,13 +84,54 @@ def test_qr_chosen_for_tall_and_deterministic():
     assert r3[3]["preprocessed"] == 0   # m < 2n: direct
 
 
-def test_qr_singular_falls_back_to_direct():
-    _say("qr singular R -> direct")
-    A = inputs.gaussian(400, 40, inputs.rng(43))
-    A[:, 7] = 0.0
+def _rank_deficient(m, n, k, seed, zero_cols=0):
+    """m x n of rank k: k Gaussian columns, the others random combinations
+    of them (and zero_cols exactly zero columns among those)."""
+    g = inputs.rng(seed)
+    B = inputs.gaussian(m, k, g)
+    A = np.concatenate([B, B @ g.standard_normal((k, n - k))], axis=1)
+    if zero_cols:
+        A[:, k:k + zero_cols] = 0.0
+    return A[:, g.permutation(n)]
+
+
+RD = [("rank100_of_120", 1000, 120, 100, 0),
+      ("rank30_of_64_zero_columns", 500, 64, 30, 10),
+      ("rank1_of_50", 400, 50, 1, 0),
+      ("zero_column", 400, 40, 39, 1)]
+
+
+@pytest.mark.parametrize("name,m,n,k,zc", RD, ids=[c[0] for c in RD])
+def test_qr_rank_deficient_lq_path(name, m, n, k, zc):
+    """Rank-deficient tall G keeps the QR path (eqs. (2.1)-(2.2)): pivoted QR
+    of R, the LQ factorization of R_0, the Jacobi method on L_0; the k
+    positive sigma against the oracle, the others zero, U's first k columns
+    orthonormal and the others zero, V orthogonal, G = U Sigma V^T."""
+    _say(f"qr rank deficient {name}: {m} x {n}, rank {k}")
+    A = _rank_deficient(m, n, k, 43 + n, zc) if name != "zero_column" else None
+    if A is None:
+        A = inputs.gaussian(m, n, inputs.rng(43))
+        A[:, 7] = 0.0
     U, S, V, info = _run(A, qr="on")
-    assert info["preprocessed"] == 0 and info["status"] == 0
-    assert S[-1] == 0.0
-    assert np.max(np.abs(V.T @ V - np.eye(40))) <= 1e-13 * 40
-    ref = oracle.gesvj(A)
-    assert np.max(np.abs(S - ref["S"])) <= 1e-12 * ref["S"][0]
+    assert info["status"] == 0
+    assert info["preprocessed"] == 2 and info["rank"] == k, info
+    assert np.all(S[k:] == 0.0) and np.all(S[:k] > 0) and np.all(np.diff(S) <= 0)
+    assert np.all(U[:, k:] == 0.0)
+    assert np.max(np.abs(U[:, :k].T @ U[:, :k] - np.eye(k))) <= 1e-13 * n
+    assert np.max(np.abs(V.T @ V - np.eye(n))) <= 1e-13 * n
+    assert np.linalg.norm(A - (U * S) @ V.T) <= 1e-13 * n * np.linalg.norm(A)
+    ref = oracle.gesvj(A)["S"]
+    assert np.all(np.abs(S - ref) <= 1e-12 * ref + 1e-13 * ref[0]), \
+        float(np.max(np.abs(S - ref) / (1e-12 * ref + 1e-13 * ref[0])))
+    # A V_(k:) = 0: the last n - k columns of V span the null space
+    assert np.linalg.norm(A @ V[:, k:]) <= 1e-13 * n * np.linalg.norm(A)
+    _say(f"  sweeps={info['sweeps']}")
+
+
+def test_qr_zero_matrix_falls_back_to_direct():
+    _say("qr zero matrix -> direct")
+    A = np.zeros((300, 30))
+    U, S, V, info = _run(A, qr="on")
+    assert info["status"] == 0 and info["preprocessed"] == 0
+    assert np.all(S == 0.0) and np.all(U == 0.0)
+    assert np.max(np.abs(V.T @ V - np.eye(30))) <= 1e-13 * 30
