@@ -13,6 +13,9 @@ Contents
   * ``gesvj_many``   -- many independent small problems (OpenMP).
   * ``strategy``     -- the closest parallel strategies of Section 3.
   * ``adjoint``      -- the SVD adjoint (reverse-mode derivative).
+  * ``rdssq``        -- DRDSSQ, the overflow-safe sum of squares of
+                        Appendix A, and the one-sided Jacobi method with
+                        DDRJAC pairs (Section 4.3.1) built on it.
 
 Final ordering (the paper fixes none; reading used): ordinary SVD -- singular
 values non-increasing, ties kept in column order; hyperbolic SVD -- J stays

@@ -38,6 +38,9 @@
  * Define ORACLE_LONG_DOUBLE to get the same method in x87 extended
  * precision (symbols suffixed _ld), used as a brute-force reference.
  *
+ * The end of the file adds DRDSSQ (Appendix A) and the DDRJAC pairs of
+ * Section 4.3.1, in IEEE double only.
+ *
  * Parity pins (see tests/test_oracle_*.py): closed-form 2x2 SVD, prescribed
  * spectra, LAPACK normwise agreement, extended-precision agreement, exact
  * rational evaluation of rotation orthogonality, and the invariants of the
@@ -326,3 +329,297 @@ void NAME(orc_gesvj_many)(int64_t count, const int32_t *m, const int32_t *n,
 
 /* Threads the OpenMP entry points use (for reporting timings). */
 int NAME(orc_num_threads)(void) { return omp_get_max_threads(); }
+
+#ifndef ORACLE_LONG_DOUBLE
+/*
+ * ------------------------------------------------------------------------
+ * Appendix A: DRDSSQ, the scaled sum of squares, and the DDRJAC rotations of
+ * Section 4.3.1 (the one-sided Jacobi method whose pair parameters come
+ * from overflow- and underflow-safe column norms).  IEEE double only: the
+ * thresholds are those of the double format.
+ *
+ * A result is a pair (j, s) that stands for 2^j s = the sum of squares
+ * (the paper's (s^-2, sigma^2) with s^-2 = 2^j); the norm is 2^(j/2) sqrt(s).
+ * Every result is returned in the common form of Appendix A: j even and
+ * 0.5 <= s < 2 (s = 0, j = 0 for a zero vector).  Reading used: the paper
+ * puts only partial sums into that form before adding them; normalising the
+ * final pair as well is an exact rescaling that makes the representation
+ * unique, and leaves the norm's value unchanged.
+ *
+ * t_lo and t_hi are the safe bounds of Appendix A rounded inwards to
+ * doubles, t_lo = RU(sqrt(mu / gamma)) and t_hi = RZ(sqrt(nu / delta_n)),
+ * computed exactly by the Python side of the oracle and passed in; t_hi
+ * depends on the vector length through ceil(lg n), so the many-column entry
+ * points take a table indexed by it.
+ * ------------------------------------------------------------------------
+ */
+
+/* (j, s) -> the common form: s = 2^e y with 1 <= y < 2 becomes 2^e' y with
+ * e' = -(e mod 2) in {-1, 0}, and j grows by e - e' (even). */
+static void common_form(int *j, double *s)
+{
+    if (!(*s > 0))
+        return;
+    int f;
+    double y = frexp(*s, &f); /* s = y 2^f, 0.5 <= y < 1 */
+    int e = f - 1;            /* s = (2y) 2^e, 1 <= 2y < 2 */
+    int ep = -(((e % 2) + 2) % 2);
+    *j += e - ep;
+    *s = ldexp(2 * y, ep);
+}
+
+/* Sum of two pairs in common form: the smaller one (lexicographically on
+ * (j, s)) is rescaled to the scale of the larger and added to it. */
+static void add_pairs(int ja, double a, int jb, double b, int *j, double *s)
+{
+    if (ja > jb || (ja == jb && a > b)) {
+        int ti = ja;
+        ja = jb;
+        jb = ti;
+        double td = a;
+        a = b;
+        b = td;
+    }
+    *j = jb;
+    *s = ldexp(a, ja - jb) + b;
+}
+
+/* ceil(lg n) for n >= 1. */
+static int ceil_lg(int64_t n)
+{
+    int l = 0;
+    while (((int64_t)1 << l) < n)
+        ++l;
+    return l;
+}
+
+/* The largest l with 2^l f <= t (f, t positive; t normal). */
+static int scale_down_exp(double f, double t)
+{
+    int l = ilogb(t) - ilogb(f);
+    return (ldexp(f, l) > t) ? l - 1 : l;
+}
+
+/* The smallest k with 2^k f >= t (f, t positive; t normal). */
+static int scale_up_exp(double f, double t)
+{
+    int k = ilogb(t) - ilogb(f);
+    return (ldexp(f, k) < t) ? k + 1 : k;
+}
+
+/*
+ * DRDSSQ (Appendix A) of x[0], x[inc], ..., x[(n-1) inc], no special values.
+ * Steps: M = max |x_i| (zero vector: (0, 0)); m = the smallest non-zero
+ * |x_i|; the elements in [t_lo, t_hi] are summed unscaled, those above t_hi
+ * scaled by 2^l (the largest l with 2^l M <= t_hi), those below t_lo scaled
+ * by 2^k (the smallest k with 2^k m >= t_lo); each non-zero partial sum
+ * (2^-2l, .), (1, .), (2^-2k, .) is put into the common form and the
+ * partial sums are added smallest first.  *parts receives a mask of the
+ * partial sums formed (1: below t_lo, 2: unscaled, 4: above t_hi).  Partial
+ * sums are accumulated in index order with fma.
+ */
+void orc_rdssq(int64_t n, const double *x, int64_t inc, double t_lo, double t_hi, int *j_out,
+               double *s_out, int *parts)
+{
+    double M = 0, mn = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        double a = fabs(x[i * inc]);
+        if (a > M)
+            M = a;
+        if (a > 0 && (mn == 0 || a < mn))
+            mn = a;
+    }
+    *j_out = 0;
+    *s_out = 0;
+    if (parts)
+        *parts = 0;
+    if (M == 0)
+        return;
+    int js[3], cnt = 0, mask = 0;
+    double ss[3];
+    if (mn <= t_hi && M >= t_lo) { /* [m, M] meets [t_lo, t_hi] */
+        double s = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            double v = x[i * inc], a = fabs(v);
+            if (a >= t_lo && a <= t_hi)
+                s = fma(v, v, s);
+        }
+        js[cnt] = 0;
+        ss[cnt++] = s;
+        mask |= 2;
+    }
+    if (M > t_hi) {
+        int l = scale_down_exp(M, t_hi);
+        double s = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            double v = x[i * inc];
+            if (fabs(v) > t_hi) {
+                double y = ldexp(v, l);
+                s = fma(y, y, s);
+            }
+        }
+        js[cnt] = -2 * l;
+        ss[cnt++] = s;
+        mask |= 4;
+    }
+    if (mn < t_lo) {
+        int k = scale_up_exp(mn, t_lo);
+        double s = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            double v = x[i * inc];
+            if (v != 0 && fabs(v) < t_lo) {
+                double y = ldexp(v, k);
+                s = fma(y, y, s);
+            }
+        }
+        js[cnt] = -2 * k;
+        ss[cnt++] = s;
+        mask |= 1;
+    }
+    for (int i = 0; i < cnt; ++i)
+        common_form(&js[i], &ss[i]);
+    /* the two smallest first: sort the (at most three) pairs ascending */
+    for (int a = 0; a < cnt; ++a)
+        for (int b = a + 1; b < cnt; ++b)
+            if (js[b] < js[a] || (js[b] == js[a] && ss[b] < ss[a])) {
+                int ti = js[a];
+                js[a] = js[b];
+                js[b] = ti;
+                double td = ss[a];
+                ss[a] = ss[b];
+                ss[b] = td;
+            }
+    int j = js[0];
+    double s = ss[0];
+    for (int i = 1; i < cnt; ++i) {
+        add_pairs(j, s, js[i], ss[i], &j, &s);
+        common_form(&j, &s);
+    }
+    *j_out = j;
+    *s_out = s;
+    if (parts)
+        *parts = mask;
+}
+
+/* The norm 2^(j/2) sqrt(s) of a DRDSSQ result, as a double (may overflow
+ * to infinity or round to a subnormal). */
+static double rdssq_norm(int j, double s) { return ldexp(sqrt(s), j / 2); }
+
+/*
+ * One pivot pair by DDRJAC: the norms of g_p and g_q by DRDSSQ, the cosine
+ * of their angle xi = (g_p / ||g_p||)^T (g_q / ||g_q||) from the columns
+ * scaled by the powers of two of their norms, the relative orthogonality
+ * test |xi| <= tol (the test of Section 4.3, subphase 2, divided by the
+ * norms), and ct 2phi of (4.3) written in the ratio rho = ||g_q|| / ||g_p||:
+ * h_qq - t h_pp over 2 h_pq is (rho - t / rho) / (2 xi).  Then (4.4)-(4.6)
+ * and (4.1)/(4.2) as in the ordinary method.
+ */
+static int do_pair_ddrjac(int64_t m, int64_t n, double *G, int64_t ldg, double *V, int64_t ldv,
+                          int64_t n_plus, double tol, int64_t p, int64_t q, double t_lo,
+                          double t_hi)
+{
+    double *gp = G + p * ldg, *gq = G + q * ldg;
+    int ja, jb;
+    double sa, sb;
+    orc_rdssq(m, gp, 1, t_lo, t_hi, &ja, &sa, NULL);
+    orc_rdssq(m, gq, 1, t_lo, t_hi, &jb, &sb, NULL);
+    if (sa == 0 || sb == 0)
+        return 0;
+    double d = 0;
+    for (int64_t i = 0; i < m; ++i)
+        d = fma(ldexp(gp[i], -ja / 2), ldexp(gq[i], -jb / 2), d);
+    double na = sqrt(sa), nb = sqrt(sb);
+    double xi = d / (na * nb);
+    if (fabs(xi) <= tol)
+        return 0;
+    int t = (p < n_plus && q >= n_plus) ? -1 : 1;
+    double tt = (double)t;
+    double rho = ldexp(nb / na, (jb - ja) / 2);
+    double ct2 = tt * ((rho - tt / rho) / (2 * xi));
+    double tn, cs;
+    int fl = params_from_ct2(ct2, t, &tn, &cs);
+    apply_pair(m, gp, gq, tn, cs, t);
+    if (V)
+        apply_pair(n, V + p * ldv, V + q * ldv, tn, cs, t);
+    return 1 | ((cs != 1) ? 2 : 0) | ((fl & 1) ? 4 : 0);
+}
+
+/*
+ * The row-cyclic one-sided Jacobi (H)SVD of orc_gesvj with DDRJAC pairs;
+ * t_hi is the bound for vectors of length m.  Same arguments and result
+ * otherwise.
+ */
+int orc_gesvj_ddrjac(int64_t m, int64_t n, double *G, int64_t ldg, double *V, int64_t ldv,
+                     int64_t n_plus, int32_t max_sweeps, int64_t *stats, double t_lo,
+                     double t_hi)
+{
+    const double tol = unit_roundoff() * sqrt((double)m);
+    int64_t st[ST_N] = {0};
+    if (V)
+        init_identity(n, V, ldv);
+    for (int32_t sw = 0; sw < max_sweeps; ++sw) {
+        int64_t rot = 0;
+        for (int64_t p = 0; p + 1 < n; ++p)
+            for (int64_t q = p + 1; q < n; ++q) {
+                int r = do_pair_ddrjac(m, n, G, ldg, V, ldv, n_plus, tol, p, q, t_lo, t_hi);
+                if (r & 1) {
+                    ++rot;
+                    st[ST_PROPER] += (r >> 1) & 1;
+                    st[ST_CLAMP] += (r >> 2) & 1;
+                }
+            }
+        st[ST_SWEEPS] = sw + 1;
+        st[ST_ROT] += rot;
+        if (rot == 0) {
+            st[ST_CONV] = 1;
+            break;
+        }
+    }
+    if (stats)
+        memcpy(stats, st, sizeof st);
+    return st[ST_CONV] ? 0 : 1;
+}
+
+/*
+ * Singular values and U from the final columns by DRDSSQ: s_j = 2^(j/2)
+ * sqrt(s), u = (2^(-j/2) g) / sqrt(s) (zero for a zero column).  exps and
+ * ssq (may be NULL) receive the pairs.
+ */
+void orc_colnorms_rdssq(int64_t m, int64_t n, double *G, int64_t ldg, double *sig, int32_t *exps,
+                        double *ssq, double t_lo, double t_hi)
+{
+    for (int64_t c = 0; c < n; ++c) {
+        double *g = G + c * ldg;
+        int j;
+        double s;
+        orc_rdssq(m, g, 1, t_lo, t_hi, &j, &s, NULL);
+        sig[c] = (s > 0) ? rdssq_norm(j, s) : 0;
+        if (exps)
+            exps[c] = j;
+        if (ssq)
+            ssq[c] = s;
+        double r = sqrt(s);
+        for (int64_t i = 0; i < m; ++i)
+            g[i] = (s > 0) ? ldexp(g[i], -j / 2) / r : 0;
+    }
+}
+
+/* orc_gesvj_many with DDRJAC pairs and DRDSSQ norms; t_hi_by_lg[L] is the
+ * upper bound for vectors with ceil(lg length) = L. */
+void orc_gesvj_many_ddrjac(int64_t count, const int32_t *m, const int32_t *n,
+                           const int64_t *a_off, const int64_t *s_off, const int64_t *v_off,
+                           double *A, double *S, double *V, int32_t max_sweeps, int32_t *sweeps,
+                           int32_t *status, double t_lo, const double *t_hi_by_lg)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < count; ++i) {
+        int64_t st[ST_N];
+        double t_hi = t_hi_by_lg[ceil_lg(m[i])];
+        int rc = orc_gesvj_ddrjac(m[i], n[i], A + a_off[i], m[i], V ? V + v_off[i] : NULL, n[i],
+                                  n[i], max_sweeps, st, t_lo, t_hi);
+        orc_colnorms_rdssq(m[i], n[i], A + a_off[i], m[i], S + s_off[i], NULL, NULL, t_lo, t_hi);
+        sweeps[i] = (int32_t)st[ST_SWEEPS];
+        status[i] = rc;
+    }
+}
+#endif /* !ORACLE_LONG_DOUBLE */
