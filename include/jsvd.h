@@ -263,10 +263,25 @@ int jsvd_hsvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
  *                  n[i] x n[i], ldv = n[i].
  *   status       : device int32[batch] or NULL: 0 converged, JSVD_NOT_CONVERGED when
  *                  max_sweeps ended it, JSVD_NONFINITE when a blocked problem met a
- *                  NaN or infinite Cholesky pivot.
+ *                  NaN or infinite Cholesky pivot, or (opts->scaled = 2) a column
+ *                  held a NaN or an infinity.
  *   sweeps       : device int32[batch] or NULL: sweeps performed.
- * Only opts->max_sweeps and opts->want_v are used (block_w does not apply:
- * blocked problems use 16); the handle's tuned batch_g_groups, if any, sets
+ * Only opts->max_sweeps, opts->want_v and opts->scaled are used (block_w does
+ * not apply: blocked problems use 16).  opts->scaled = 2 is the mode for
+ * badly scaled problems: every problem runs the pointwise method with DDRJAC
+ * pairs (Section 4.3.1): the column norms by DRDSSQ (Appendix A, see
+ * jsvd_colnorms), the cosine of the pair's angle from the columns scaled by
+ * the powers of two of their norms, ct 2phi of (4.3) from the ratio of the
+ * norms, then (4.4)-(4.6); sigma and U from DRDSSQ of the final columns
+ * (sigma_i infinite if it overflows); a problem stops at a sweep with no
+ * rotation at all (the pointwise rule of Section 4.5: on graded columns a
+ * rotation with cos = 1 still moves the smaller column).  It covers
+ * entries anywhere in the
+ * double range (subnormals included) as long as, within a problem, the
+ * ratio of two column norms stays below about 2^1000.  0 and 1: the
+ * ordinary pairs, which need every column's squares and sums in the normal
+ * range (the default; the input is not inspected).  The handle's tuned
+ * batch_g_groups, if any, sets
  * how a workgroup of the pointwise kernel divides its half waves between G
  * and V, and its batch_block_min_n which problems are blocked.  The work is
  * enqueued on the handle's stream and the call returns without waiting; the
@@ -432,6 +447,42 @@ int jsvd_diag_fp64(jsvd_handle_t h, int64_t count, const double *a, const double
  */
 int jsvd_diag_refined(jsvd_handle_t h, int64_t count, const double *a, const double *b,
                       double *out);
+
+/*
+ * DRDSSQ, the sum of squares of Appendix A, of every column of A: safe from
+ * overflow and underflow over the whole double range, subnormals included.
+ * For column c (m elements) with M = max |a_ic| and mu_c the smallest
+ * non-zero |a_ic|: the elements in [t_lo, t_hi] are summed unscaled, those
+ * above t_hi scaled by 2^l (the largest l with 2^l M <= t_hi), those below
+ * t_lo scaled by 2^k (the smallest k with 2^k mu_c >= t_lo), each partial sum
+ * by a fixed reduction tree; each is put into the common form (2^j s, j
+ * even, 0.5 <= s < 2) and they are added smallest first.  The bounds are
+ * those of Appendix A rounded inwards (jsvd_rdssq_bounds).
+ *   A      : device, m x n column-major, leading dimension lda >= m.
+ *   exps   : device int32[n] or NULL: j of the result 2^j s (even).
+ *   ssq    : device double[n] or NULL: s, in [0.5, 2); 0 (with j = 0) for a
+ *            zero column; NaN for a column holding a NaN or an infinity.
+ *   norms  : device double[n] or NULL: ||a_c|| = 2^(j/2) sqrt(s) as a double
+ *            (infinite when it overflows, rounded when it is subnormal).
+ * One workgroup per column; enqueued on the handle's stream, returns without
+ * waiting.  Returns JSVD_OK, -1 if h is NULL, -2 for m < 1 or m > 2^40, -3
+ * for n < 0 or n >= 2^31, -4 for a NULL A (n > 0), -5 for lda < m, -6 if all
+ * three outputs are NULL, or JSVD_HIP_ERROR.
+ */
+int jsvd_colnorms(jsvd_handle_t h, int64_t m, int64_t n, const double *A, int64_t lda,
+                  int32_t *exps, double *ssq, double *norms);
+
+/*
+ * The safe bounds of DRDSSQ (Appendix A) for vectors of length n with
+ * ceil(lg n) = lg (0 <= lg <= 63), rounded inwards to doubles:
+ *   t_lo = RU(sqrt(mu / (1 - eps)))                       = 2^-511 (1 + 2^-52),
+ *   t_hi = RZ(sqrt(nu / (2^lg (1 + eps)^(1 + lg)))),
+ * mu the smallest positive normal double, nu the largest double, eps = 2^-53.
+ * No element in [t_lo, t_hi] has a square that underflows, and no sum of n
+ * such squares overflows.  Host only (no device call).  Returns JSVD_OK, -1
+ * for lg outside [0, 63], -2 for a NULL pointer.
+ */
+int jsvd_rdssq_bounds(int32_t lg, double *t_lo, double *t_hi);
 
 #ifdef __cplusplus
 }

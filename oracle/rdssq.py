@@ -164,12 +164,21 @@ def gesvj(A, n_plus=None, max_sweeps=100, want_v=True, sort=True):
 
 
 def _order_key(ex, ss):
-    """Values that order like the norms 2^(j/2) sqrt(s): log2 of them in
-    long double (ties of the norms stay ties)."""
-    ex = np.asarray(ex, dtype=np.longdouble)
-    ss = np.asarray(ss, dtype=np.longdouble)
-    with np.errstate(divide="ignore"):
-        return np.where(ss > 0, ex / 2 + np.log2(ss) / 2, -np.inf)
+    """Keys that order like the norms 2^(j/2) sqrt(s): the rank of (j, s) in
+    lexicographic order (the common form makes it the order of the norms),
+    a zero column lowest, equal pairs equal keys."""
+    ex = np.where(np.asarray(ss) > 0, np.asarray(ex, dtype=np.int64), np.iinfo(np.int64).min)
+    ss = np.asarray(ss, dtype=np.float64)
+    order = np.lexsort((ss, ex))
+    key = np.zeros(len(ss))
+    rank, prev = 0, None
+    for i in order:
+        cur = (int(ex[i]), float(ss[i]))
+        if prev is not None and cur != prev:
+            rank += 1
+        key[i] = rank
+        prev = cur
+    return key
 
 
 def gesvj_many(mats, max_sweeps=100, want_v=True):

@@ -60,7 +60,8 @@ EXPORTS = ["jsvd_default_opts", "jsvd_create", "jsvd_set_stream", "jsvd_destroy"
            "jsvd_diag_fp64", "jsvd_kernel_timing", "jsvd_kernel_times", "jsvd_gesvd_batched",
            "jsvd_svd_backward", "jsvd_set_tuning", "jsvd_batched_block_min_n",
            "jsvd_workspace_size", "jsvd_workspace_size_batched", "jsvd_reserve_batched",
-           "jsvd_diag_refined", "jsvd_gesvd_batched_noalloc", "jsvd_gesvd_full"]
+           "jsvd_diag_refined", "jsvd_gesvd_batched_noalloc", "jsvd_gesvd_full",
+           "jsvd_colnorms", "jsvd_rdssq_bounds"]
 
 
 def lib():
@@ -101,6 +102,9 @@ def lib():
                                               ctypes.POINTER(ctypes.c_size_t)]
     L.jsvd_reserve_batched.argtypes = [_vp, _i64, _i32, _i32, ctypes.POINTER(Opts)]
     L.jsvd_diag_refined.argtypes = [_vp, _i64, _vp, _vp, _vp]
+    L.jsvd_colnorms.argtypes = [_vp, _i64, _i64, _vp, _i64, _vp, _vp, _vp]
+    L.jsvd_rdssq_bounds.argtypes = [_i32, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]
     L.jsvd_kernel_timing.argtypes = [_vp, ctypes.c_int]
     L.jsvd_kernel_times.argtypes = [_vp, _vp, _vp]
     for f in ("jsvd_default_opts", "jsvd_create", "jsvd_set_stream", "jsvd_destroy",
@@ -108,7 +112,7 @@ def lib():
               "jsvd_kernel_timing", "jsvd_kernel_times", "jsvd_gesvd_batched",
               "jsvd_svd_backward", "jsvd_workspace_size", "jsvd_workspace_size_batched",
               "jsvd_reserve_batched", "jsvd_diag_refined", "jsvd_gesvd_batched_noalloc",
-              "jsvd_gesvd_full"):
+              "jsvd_gesvd_full", "jsvd_colnorms", "jsvd_rdssq_bounds"):
         getattr(L, f).restype = ctypes.c_int
     _LIB = L
     return L
@@ -349,6 +353,35 @@ def diag_fp64(a, b):
     return q, r
 
 
+def colnorms(A):
+    """DRDSSQ (Appendix A) of every column of a 2-D float64 CUDA tensor (any
+    strides are copied to column-major first): returns (exps, ssq, norms),
+    the sum of squares 2^exps ssq in the common form and the norm."""
+    import torch
+    m, n = A.shape
+    X = _colmajor_copy(A)
+    exps = torch.empty(n, dtype=torch.int32, device=A.device)
+    ssq = torch.empty(n, dtype=torch.float64, device=A.device)
+    norms = torch.empty(n, dtype=torch.float64, device=A.device)
+    dev = A.device
+    h = _handle(dev.index if dev.index is not None else torch.cuda.current_device(),
+                torch.cuda.current_stream(dev).cuda_stream)
+    rc = lib().jsvd_colnorms(h, m, n, _vp(X.data_ptr()), m, _vp(exps.data_ptr()),
+                             _vp(ssq.data_ptr()), _vp(norms.data_ptr()))
+    if rc:
+        raise JsvdError(rc, "jsvd_colnorms")
+    return exps, ssq, norms
+
+
+def rdssq_bounds(lg):
+    """(t_lo, t_hi) of DRDSSQ for vectors with ceil(lg n) = lg (host only)."""
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    rc = lib().jsvd_rdssq_bounds(int(lg), ctypes.byref(lo), ctypes.byref(hi))
+    if rc:
+        raise JsvdError(rc, "jsvd_rdssq_bounds")
+    return lo.value, hi.value
+
+
 def diag_refined(a, b):
     """The kernels' refined reciprocal, quotient and square roots on the
     device: returns (rcp(b), a/b, sqrt(a), 1/sqrt(a), sqrt(a)) as float64
@@ -515,11 +548,12 @@ class Batch:
         return U, S, V
 
 
-def gesvd_batched(batch, max_sweeps=30, restore=True, noalloc=False):
+def gesvd_batched(batch, max_sweeps=30, restore=True, noalloc=False, scaled="auto"):
     """Run jsvd_gesvd_batched (noalloc=True: jsvd_gesvd_batched_noalloc) on a
     Batch on the current stream (asynchronous).
 
     restore=True first copies the original inputs back into batch.A.
+    scaled="on": DDRJAC pairs and DRDSSQ norms for badly scaled problems.
     """
     import torch
     dev = batch.A.device
@@ -528,7 +562,7 @@ def gesvd_batched(batch, max_sweeps=30, restore=True, noalloc=False):
                 stream.cuda_stream)
     if restore:
         batch.A.copy_(batch.A0)
-    o = make_opts(max_sweeps=max_sweeps, want_v=batch.want_v)
+    o = make_opts(max_sweeps=max_sweeps, want_v=batch.want_v, scaled=scaled)
     name = "jsvd_gesvd_batched_noalloc" if noalloc else "jsvd_gesvd_batched"
     rc = getattr(lib(), name)(
         h, batch.count, batch.max_m, batch.max_n, _vp(batch.m.data_ptr()),

@@ -1,6 +1,6 @@
 // Small kernels around the sweeps: counter reset, V = I, column norms
 // (the singular values, Section 4), the final ordering and the gathers.
-#include "jsvd_device.h"
+#include "jsvd_rdssq.h"
 
 namespace jsvd {
 
@@ -36,53 +36,48 @@ __global__ __launch_bounds__(256) void colnorm_kernel(const double *G, int64_t l
     if (threadIdx.x == 0) s_out[j] = sqrt(part[0]);
 }
 
-// Column norms without overflow or underflow (the concern of Section 4.2
-// and Appendix A for badly scaled input): the largest magnitude m_j of the
-// column fixes a power of two 2^e0, the squares are summed of the column
-// scaled by 2^-e0 (exactly), and ||g_j|| = 2^e0 sqrt(sum).  Writes, when
-// asked, the norm and the exponent e_j of ||g_j|| (||g_j|| in [2^e_j,
-// 2^(e_j+1)); 0 for a zero column), and folds the exponents of the nonzero
-// columns into range[0] (min) and range[1] (max).
+// Column norms without overflow or underflow (the concern of Section 4.2),
+// by DRDSSQ (Appendix A; one workgroup per column): the pair (j, s) with
+// ||g_j||^2 = 2^j s.  Writes, when asked, the norm 2^(j/2) sqrt(s) and the
+// exponent e_j of ||g_j|| (||g_j|| in [2^e_j, 2^(e_j+1)): j/2, less one when
+// s < 1; 0 for a zero or non-finite column), and folds the exponents of the
+// nonzero finite columns into range[0] (min) and range[1] (max).
 __global__ __launch_bounds__(256) void colexp_kernel(const double *G, int64_t ldg, int64_t m,
-                                                     double *s_out, int *ex, int *range) {
-    __shared__ double part[256];
-    const int64_t j = blockIdx.x;
-    const double *g = G + j * ldg;
-    double mx = 0.0;
-    for (int64_t i = threadIdx.x; i < m; i += 256) mx = fmax(mx, fabs(g[i]));
-    part[threadIdx.x] = mx;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) part[threadIdx.x] = fmax(part[threadIdx.x], part[threadIdx.x + h]);
-        __syncthreads();
-    }
-    mx = part[0];
-    __syncthreads();
-    const bool nz = mx > 0.0 && mx <= 0x1.fffffffffffffp+1023;
-    const int e0 = nz ? ilogb(mx) : 0;
-    double sq = 0.0;
-    for (int64_t i = threadIdx.x; i < m; i += 256) {
-        const double v = ldexp(g[i], -e0);
-        sq = fma(v, v, sq);
-    }
-    part[threadIdx.x] = sq;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
-        __syncthreads();
-    }
+                                                     double t_hi, double *s_out, int *ex,
+                                                     int *range) {
+    __shared__ double red[3 * 256];
+    const int64_t c = blockIdx.x;
+    int j;
+    double s;
+    wg_rdssq<256>(G + c * ldg, m, t_hi, red, j, s);
     if (threadIdx.x == 0) {
-        const double r = sqrt(part[0]);  // in [1, sqrt(m)] for a finite nonzero column
-        const bool fin = nz && r <= 0x1.fffffffffffffp+1023;  // no NaN met
-        if (s_out) s_out[j] = nz ? ldexp(r, e0) : (mx == 0.0 ? 0.0 : mx * r);
+        const bool fin = s > 0.0 && s < 2.0;  // non-zero, no NaN met
+        if (s_out) s_out[c] = rdssq_norm(j, s);
         if (ex) {
-            const int e = fin ? e0 + ilogb(r) : 0;
-            ex[j] = e;
+            const int e = fin ? j / 2 - (s < 1.0 ? 1 : 0) : 0;
+            ex[c] = e;
             if (fin && range) {
                 atomicMin(&range[0], e);
                 atomicMax(&range[1], e);
             }
         }
+    }
+}
+
+// DRDSSQ of every column (the boundary's column-norm call): the pair
+// (j, s) and the norm, each output optional.
+__global__ __launch_bounds__(256) void rdssq_cols_kernel(const double *A, int64_t lda, int64_t m,
+                                                         double t_hi, int32_t *exps, double *ssq,
+                                                         double *norms) {
+    __shared__ double red[3 * 256];
+    const int64_t c = blockIdx.x;
+    int j;
+    double s;
+    wg_rdssq<256>(A + c * lda, m, t_hi, red, j, s);
+    if (threadIdx.x == 0) {
+        if (exps) exps[c] = j;
+        if (ssq) ssq[c] = s;
+        if (norms) norms[c] = rdssq_norm(j, s);
     }
 }
 
@@ -245,8 +240,17 @@ hipError_t launch_range_init(int *range, hipStream_t s) {
 
 hipError_t launch_colexp(const double *G, int64_t ldg, int64_t m, int64_t n, double *s_out,
                          int *ex, int *range, hipStream_t s) {
-    hipLaunchKernelGGL(colexp_kernel, dim3((unsigned)n), dim3(256), 0, s, G, ldg, m, s_out, ex,
-                       range);
+    const int lg = m <= 1 ? 0 : 64 - __builtin_clzll((unsigned long long)(m - 1));
+    hipLaunchKernelGGL(colexp_kernel, dim3((unsigned)n), dim3(256), 0, s, G, ldg, m,
+                       rdssq_t_hi(lg), s_out, ex, range);
+    return hipGetLastError();
+}
+
+hipError_t launch_rdssq_cols(const double *A, int64_t lda, int64_t m, int64_t n, int32_t *exps,
+                             double *ssq, double *norms, hipStream_t s) {
+    const int lg = m <= 1 ? 0 : 64 - __builtin_clzll((unsigned long long)(m - 1));
+    hipLaunchKernelGGL(rdssq_cols_kernel, dim3((unsigned)n), dim3(256), 0, s, A, lda, m,
+                       rdssq_t_hi(lg), exps, ssq, norms);
     return hipGetLastError();
 }
 

@@ -24,7 +24,15 @@
 // of a problem the column norms give sigma, the workgroup ranks them
 // (non-increasing, ties by index) and gathers U = G Sigma^{-1} and V in that
 // order (what is in global memory is permuted in place through LDS).
-#include "jsvd_blocked.h"
+//
+// Badly scaled problems (opts.scaled = 2): every pair is a DDRJAC pair
+// (Section 4.3.1): the column norms by DRDSSQ (Appendix A), the cosine of
+// the pair's angle from the columns scaled by the powers of two of their
+// norms, and ct 2phi from the norm ratio, so that no square or sum leaves
+// the normal range; sigma and U at the end come from DRDSSQ too.  Such
+// problems all take the pointwise kernel, and stop at a sweep with no
+// rotation (the pointwise rule of Section 4.5).
+#include "jsvd_rdssq.h"
 
 namespace jsvd {
 
@@ -44,11 +52,19 @@ constexpr int kGroups = kBatchThreads / 32;
 // double-buffered by p-step; cs = 0 marks a pair that did not rotate.
 // Returns the sweeps performed; sets *converged when a sweep performed no
 // proper rotation.
-template <int R, int K>
+// DD: DDRJAC pairs (t_hi: the DRDSSQ bound for columns of length m; a NaN
+// or infinite column sets *s_bad), and the stopping rule of the pointwise
+// method (Section 4.5): a sweep with no rotation at all.  Between columns
+// whose norms differ by many orders of magnitude a rotation with cs = 1
+// still moves the smaller column by tan phi times the larger one, so the
+// relaxed rule (no proper rotation) would stop too early on graded input.
+template <int R, int K, bool DD>
 __device__ int pointwise_sweeps(double *Gw, double *Vw, int m, int n, int N,
                                 const unsigned char *tbl, int max_sweeps, double tol, int g_groups,
                                 int *s_rot, double (*s_tn)[kBatchMaxN / 2],
-                                double (*s_cs)[kBatchMaxN / 2], bool *converged) {
+                                double (*s_cs)[kBatchMaxN / 2], bool *converged, double t_hi,
+                                int *s_bad) {
+    static_assert(!DD || K == 1, "DDRJAC pairs one at a time");
     const int tid = threadIdx.x, x = tid & 31, group = tid >> 5;
     const int half = N >> 1;
     const int ng = Vw ? g_groups : kGroups;      // half waves on G
@@ -82,6 +98,26 @@ __device__ int pointwise_sweeps(double *Gw, double *Vw, int m, int n, int N,
                                 b[k][r] = (use[k] && i < m) ? Gw[(size_t)qk[k] * m + i] : 0.0;
                             }
                         }
+                        double tn[K], cs[K];
+                        bool rk[K];
+                        if constexpr (DD) {
+                            int ja, jb;
+                            double sa, sb;
+                            hw_rdssq<R>(a[0], t_hi, ja, sa);
+                            hw_rdssq<R>(b[0], t_hi, jb, sb);
+                            double d = 0.0;
+#pragma unroll
+                            for (int r = 0; r < R; ++r)
+                                d = fma(ldexp(a[0][r], -ja / 2), ldexp(b[0][r], -jb / 2), d);
+                            d = hw_sum(d);
+                            bool clamped;
+                            tn[0] = 0.0;
+                            cs[0] = 0.0;
+                            rk[0] = use[0] && ddrjac_pair(ja, sa, jb, sb, d, tol, 1, tn[0], cs[0],
+                                                          clamped);
+                            if (!rk[0]) cs[0] = 0.0;
+                            if (use[0] && x == 0 && !(sa == sa && sb == sb)) *s_bad = 1;
+                        } else {
 #pragma unroll
                         for (int k = 0; k < K; ++k) {
                             hpp[k] = hqq[k] = hpq[k] = 0.0;
@@ -105,8 +141,6 @@ __device__ int pointwise_sweeps(double *Gw, double *Vw, int m, int n, int N,
                         for (int k = 0; k < K; ++k)
                             fast = fast && (!use[k] || (in_fast_range(hpp[k]) && in_fast_range(hqq[k]) &&
                                                         (hpq[k] == 0.0 || in_fast_range(fabs(hpq[k])))));
-                        double tn[K], cs[K];
-                        bool rk[K];
 #pragma unroll
                         for (int k = 0; k < K; ++k) {
                             if (K == 1) {  // one pair: skip the rotation when the test says so
@@ -126,10 +160,11 @@ __device__ int pointwise_sweeps(double *Gw, double *Vw, int m, int n, int N,
                             }
                             if (!rk[k]) cs[k] = 0.0;
                         }
+                        }  // DD
 #pragma unroll
                         for (int k = 0; k < K; ++k) {
                             if (rk[k]) {
-                                rot += cs[k] != 1.0 ? 1 : 0;
+                                rot += (DD || cs[k] != 1.0) ? 1 : 0;
                                 // (4.1); cs == 1 multiplies exactly
 #pragma unroll
                                 for (int r = 0; r < R; ++r) {
@@ -154,18 +189,35 @@ __device__ int pointwise_sweeps(double *Gw, double *Vw, int m, int n, int N,
                         const int p = ps[2 * slot], q = ps[2 * slot + 1];
                         if (q >= n) continue;  // padding index: uniform in the half wave
                         double *gp = Gw + (size_t)p * m, *gq = Gw + (size_t)q * m;
-                        double hpp = 0.0, hqq = 0.0, hpq = 0.0, tn = 0.0, cs = 0.0;
-                        for (int i = x; i < m; i += 32) {
-                            const double a0 = gp[i], b0 = gq[i];
-                            hpp = fma(a0, a0, hpp);
-                            hqq = fma(b0, b0, hqq);
-                            hpq = fma(a0, b0, hpq);
+                        double tn = 0.0, cs = 0.0;
+                        bool rot_pair;
+                        if constexpr (DD) {
+                            int ja, jb;
+                            double sa, sb;
+                            hw_rdssq_mem(gp, m, t_hi, ja, sa);
+                            hw_rdssq_mem(gq, m, t_hi, jb, sb);
+                            double d = 0.0;
+                            for (int i = x; i < m; i += 32)
+                                d = fma(ldexp(gp[i], -ja / 2), ldexp(gq[i], -jb / 2), d);
+                            d = hw_sum(d);
+                            bool clamped;
+                            rot_pair = ddrjac_pair(ja, sa, jb, sb, d, tol, 1, tn, cs, clamped);
+                            if (x == 0 && !(sa == sa && sb == sb)) *s_bad = 1;
+                        } else {
+                            double hpp = 0.0, hqq = 0.0, hpq = 0.0;
+                            for (int i = x; i < m; i += 32) {
+                                const double a0 = gp[i], b0 = gq[i];
+                                hpp = fma(a0, a0, hpp);
+                                hqq = fma(b0, b0, hqq);
+                                hpq = fma(a0, b0, hpq);
+                            }
+                            hpp = hw_sum(hpp);
+                            hqq = hw_sum(hqq);
+                            hpq = hw_sum(hpq);
+                            rot_pair = trig_pair(hpp, hqq, hpq, tol, tn, cs);
                         }
-                        hpp = hw_sum(hpp);
-                        hqq = hw_sum(hqq);
-                        hpq = hw_sum(hpq);
-                        if (trig_pair(hpp, hqq, hpq, tol, tn, cs)) {
-                            rot += cs != 1.0 ? 1 : 0;
+                        if (rot_pair) {
+                            rot += (DD || cs != 1.0) ? 1 : 0;
                             for (int i = x; i < m; i += 32) {
                                 const double a0 = gp[i], b0 = gq[i];
                                 gp[i] = cs * fma(-tn, b0, a0);
@@ -222,7 +274,8 @@ __device__ int pointwise_sweeps(double *Gw, double *Vw, int m, int n, int N,
 // columns at a time.
 template <int NT>
 __device__ __forceinline__ void permute_columns(double *X, int rows, int n, const int *perm,
-                                                const double *sig, double *lds, int64_t lds_cap) {
+                                                const double *sig, const int *ex,
+                                                double *lds, int64_t lds_cap) {
     const int tid = threadIdx.x;
     const int band = (int)min<int64_t>(rows, lds_cap / n);
     for (int i0 = 0; i0 < rows; i0 += band) {
@@ -235,7 +288,10 @@ __device__ __forceinline__ void permute_columns(double *X, int rows, int n, cons
         for (int e = tid; e < nr * n; e += NT) {
             const int k = e / nr, i = e % nr, c = perm[k];
             const double v = lds[(size_t)c * nr + i];
-            if (sig) {
+            if (sig && ex) {  // DRDSSQ pairs: sig holds sqrt(s), ex the j of 2^j s
+                const double sg = sig[c];
+                X[(size_t)k * rows + i0 + i] = sg > 0.0 ? ldexp(v, -ex[c] / 2) / sg : 0.0;
+            } else if (sig) {
                 const double sg = sig[c];
                 X[(size_t)k * rows + i0 + i] = sg > 0.0 ? v / sg : 0.0;
             } else {
@@ -246,27 +302,58 @@ __device__ __forceinline__ void permute_columns(double *X, int rows, int n, cons
     }
 }
 
+//
+// With DRDSSQ pairs (s_ex non-null, t_hi the bound for length m): the pair
+// (j, s) of each column gives sigma = 2^(j/2) sqrt(s) (infinite if it
+// overflows), the order compares the pairs (j, sqrt(s)) lexicographically
+// (a zero column last but NaN), and u = (2^(-j/2) g) / sqrt(s); s_rt
+// receives sqrt(s).
 template <int NT>
 __device__ __forceinline__ void finish_problem(const BatchArgs &b, int id, int m, int n, double *G,
                                                double *V, const double *Gw, const double *Vw,
                                                bool in_lds, bool v_lds, double *lds,
                                                int64_t lds_cap, int sweeps, int status,
-                                               double *s_sig, int *s_perm) {
+                                               double *s_sig, int *s_perm, int *s_ex = nullptr,
+                                               double *s_rt = nullptr, double t_hi = 0.0) {
     const int tid = threadIdx.x, x = tid & 31, group = tid >> 5;
     for (int j = group; j < n; j += NT / 32) {
         const double *g = Gw + (size_t)j * m;
-        double sacc = 0.0;
-        for (int i = x; i < m; i += 32) sacc = fma(g[i], g[i], sacc);
-        sacc = hw_sum(sacc);
-        if (x == 0) s_sig[j] = sqrt(sacc);
+        if (s_ex) {
+            int e;
+            double sq;
+            hw_rdssq_mem(g, m, t_hi, e, sq);
+            if (x == 0) {
+                s_ex[j] = sq > 0.0 ? e : -0x7fffffff;
+                s_rt[j] = sqrt(sq);
+                s_sig[j] = rdssq_norm(e, sq);
+            }
+        } else {
+            double sacc = 0.0;
+            for (int i = x; i < m; i += 32) sacc = fma(g[i], g[i], sacc);
+            sacc = hw_sum(sacc);
+            if (x == 0) s_sig[j] = sqrt(sacc);
+        }
     }
     __syncthreads();
     for (int j = tid; j < n; j += NT) {
-        const double kj = s_sig[j] != s_sig[j] ? -INFINITY : s_sig[j];
         int r = 0;
-        for (int i = 0; i < n; ++i) {
-            const double ki = s_sig[i] != s_sig[i] ? -INFINITY : s_sig[i];
-            r += (ki > kj || (ki == kj && i < j)) ? 1 : 0;
+        if (s_ex) {
+            const bool nj = s_rt[j] != s_rt[j];
+            for (int i = 0; i < n; ++i) {
+                const bool ni = s_rt[i] != s_rt[i];
+                const bool gt = ni || nj ? (!ni && nj)
+                                         : (s_ex[i] > s_ex[j] ||
+                                            (s_ex[i] == s_ex[j] && s_rt[i] > s_rt[j]));
+                const bool eq = ni || nj ? (ni && nj)
+                                         : (s_ex[i] == s_ex[j] && s_rt[i] == s_rt[j]);
+                r += (gt || (eq && i < j)) ? 1 : 0;
+            }
+        } else {
+            const double kj = s_sig[j] != s_sig[j] ? -INFINITY : s_sig[j];
+            for (int i = 0; i < n; ++i) {
+                const double ki = s_sig[i] != s_sig[i] ? -INFINITY : s_sig[i];
+                r += (ki > kj || (ki == kj && i < j)) ? 1 : 0;
+            }
         }
         s_perm[r] = j;
     }
@@ -275,8 +362,14 @@ __device__ __forceinline__ void finish_problem(const BatchArgs &b, int id, int m
     if (in_lds)
         for (int e = tid; e < m * n; e += NT) {
             const int k = e / m, i = e % m, c = s_perm[k];
-            const double sg = s_sig[c];
-            G[e] = sg > 0.0 ? Gw[(size_t)c * m + i] / sg : 0.0;
+            const double v = Gw[(size_t)c * m + i];
+            if (s_ex) {
+                const double rt = s_rt[c];
+                G[e] = rt > 0.0 ? ldexp(v, -s_ex[c] / 2) / rt : 0.0;
+            } else {
+                const double sg = s_sig[c];
+                G[e] = sg > 0.0 ? v / sg : 0.0;
+            }
         }
     if (V && v_lds)
         for (int e = tid; e < n * n; e += NT) {
@@ -284,8 +377,9 @@ __device__ __forceinline__ void finish_problem(const BatchArgs &b, int id, int m
             V[e] = Vw[(size_t)s_perm[k] * n + i];
         }
     __syncthreads();
-    if (!in_lds) permute_columns<NT>(G, m, n, s_perm, s_sig, lds, lds_cap);
-    if (V && !v_lds) permute_columns<NT>(V, n, n, s_perm, nullptr, lds, lds_cap);
+    if (!in_lds)
+        permute_columns<NT>(G, m, n, s_perm, s_ex ? s_rt : s_sig, s_ex, lds, lds_cap);
+    if (V && !v_lds) permute_columns<NT>(V, n, n, s_perm, nullptr, nullptr, lds, lds_cap);
     double *S = b.S + b.s_off[id];
     for (int k = tid; k < n; k += NT) S[k] = s_sig[s_perm[k]];
     if (tid == 0) {
@@ -296,15 +390,20 @@ __device__ __forceinline__ void finish_problem(const BatchArgs &b, int id, int m
 }
 
 // Problems at positions [queue[2], count) of the work order: the pointwise
-// method, G in LDS when it fits, V in what LDS is left.
+// method, G in LDS when it fits, V in what LDS is left.  DD: DDRJAC pairs
+// and DRDSSQ norms.
+template <bool DD>
 __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs b) {
     extern __shared__ double lds_g[];  // working copy of G when it fits
     __shared__ int s_item;
     __shared__ int s_rot;
+    __shared__ int s_bad;
     __shared__ double s_sig[kBatchMaxN];
     __shared__ int s_perm[kBatchMaxN];
     __shared__ double s_tn[2][kBatchMaxN / 2];  // published rotations, by p-step parity
     __shared__ double s_cs[2][kBatchMaxN / 2];
+    __shared__ int s_ex[DD ? kBatchMaxN : 1];       // DRDSSQ pairs of the final columns
+    __shared__ double s_rt[DD ? kBatchMaxN : 1];
     const int tid = threadIdx.x;
 
     for (;;) {
@@ -320,6 +419,7 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs b) {
         const int N = b.tbl_order[n];
         const unsigned char *tbl = b.tbls + b.tbl_off[N >> 1];
         const double tol = kEps * sqrt((double)m);  // c(eps) = eps sqrt(m)
+        const double t_hi = DD ? b.t_hi[ceil_lg(m)] : 0.0;
         const bool in_lds = (int64_t)m * n <= b.lds_doubles;
         const int64_t v_at = in_lds ? (int64_t)m * n : 0;
         const bool v_lds = V && v_at + (int64_t)n * n <= b.lds_doubles;
@@ -330,23 +430,26 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs b) {
             for (int e = tid; e < m * n; e += kBatchThreads) lds_g[e] = G[e];
         if (V)
             for (int e = tid; e < n * n; e += kBatchThreads) Vw[e] = (e % n == e / n) ? 1.0 : 0.0;
+        if (tid == 0) s_bad = 0;
         __syncthreads();
 
         bool converged = false;
         int sweeps;
         if (m <= 32)
-            sweeps = pointwise_sweeps<1, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged);
+            sweeps = pointwise_sweeps<1, 1, DD>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged, t_hi, &s_bad);
         else if (m <= 64)
-            sweeps = pointwise_sweeps<2, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged);
+            sweeps = pointwise_sweeps<2, 1, DD>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged, t_hi, &s_bad);
         else if (m <= 128)
-            sweeps = pointwise_sweeps<4, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged);
+            sweeps = pointwise_sweeps<4, 1, DD>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged, t_hi, &s_bad);
         else if (m <= 192)
-            sweeps = pointwise_sweeps<6, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged);
+            sweeps = pointwise_sweeps<6, 1, DD>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged, t_hi, &s_bad);
         else
-            sweeps = pointwise_sweeps<0, 1>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged);
+            sweeps = pointwise_sweeps<0, 1, DD>(Gw, Vw, m, n, N, tbl, b.max_sweeps, tol, b.g_groups, &s_rot, s_tn, s_cs, &converged, t_hi, &s_bad);
+        const int status = (DD && s_bad) ? JSVD_NONFINITE
+                           : converged ? 0 : JSVD_NOT_CONVERGED;
         finish_problem<kBatchThreads>(b, id, m, n, G, V, Gw, Vw, in_lds, v_lds, lds_g,
-                                      b.lds_doubles, sweeps, converged ? 0 : JSVD_NOT_CONVERGED,
-                                      s_sig, s_perm);
+                                      b.lds_doubles, sweeps, status, s_sig, s_perm,
+                                      DD ? s_ex : nullptr, DD ? s_rt : nullptr, t_hi);
     }
 }
 
@@ -420,8 +523,11 @@ __global__ void batch_zero_kernel(int *p, int count) {
 }  // namespace
 
 hipError_t batched_set_lds(int bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&batched_kernel),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&batched_kernel<false>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&batched_kernel<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess && bytes >= kBlkLdsDoubles * (int)sizeof(double))
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&batched_blocked_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -441,8 +547,12 @@ hipError_t launch_batched(const BatchArgs &b, int grid, int bgrid, int max_n, in
     if (b.blk_min_n > 0 && max_n >= b.blk_min_n)
         hipLaunchKernelGGL(batched_blocked_kernel, dim3(bgrid), dim3(kBlkThreads),
                            (unsigned)(kBlkLdsDoubles * sizeof(double)), s, b);
-    hipLaunchKernelGGL(batched_kernel, dim3(grid), dim3(kBatchThreads),
-                       (unsigned)(b.lds_doubles * sizeof(double)), s, b);
+    if (b.ddrjac)
+        hipLaunchKernelGGL(batched_kernel<true>, dim3(grid), dim3(kBatchThreads),
+                           (unsigned)(b.lds_doubles * sizeof(double)), s, b);
+    else
+        hipLaunchKernelGGL(batched_kernel<false>, dim3(grid), dim3(kBatchThreads),
+                           (unsigned)(b.lds_doubles * sizeof(double)), s, b);
     return hipGetLastError();
 }
 

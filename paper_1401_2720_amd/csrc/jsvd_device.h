@@ -178,14 +178,12 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 }
 
 // ----------------------------------------------------- rotations (4.3)-(4.6)
-// Trigonometric (t = +1) or hyperbolic (t = -1) rotation parameters from the
-// pivot Gram entries, cs_2 cosine, with the short cuts at sqrt(eps) and
-// sqrt(2/eps) and |coth 2phi| <= 1 replaced by 5/4.  IEEE operations.
-__device__ __forceinline__ void rotation(double hpp, double hqq, double hpq, int t, double &tn,
-                                         double &cs, bool &clamped) {
+// Trigonometric (t = +1) or hyperbolic (t = -1) rotation parameters from
+// ct 2phi, eqs. (4.4)-(4.6): cs_2 cosine, short cuts at sqrt(eps) and
+// sqrt(2/eps), |coth 2phi| <= 1 replaced by 5/4.  IEEE operations.
+__device__ __forceinline__ void rotation_from_ct2(double ct2, int t, double &tn, double &cs,
+                                                  bool &clamped) {
     const double tt = (double)t;
-    const double h = hqq - tt * hpp;
-    const double ct2 = tt * (h / (2.0 * hpq));
     const double sgn = ct2 < 0.0 ? -1.0 : 1.0;
     double a = fabs(ct2);
     clamped = false;
@@ -202,6 +200,14 @@ __device__ __forceinline__ void rotation(double hpp, double hqq, double hpq, int
         act = a + sqrt(fma(a, a, tt));
     tn = sgn * (1.0 / act);
     cs = (act >= kSqrt2OverEps) ? 1.0 : act / sqrt(fma(act, act, tt));
+}
+
+// The same from the pivot Gram entries: ct 2phi of eq. (4.3).
+__device__ __forceinline__ void rotation(double hpp, double hqq, double hpq, int t, double &tn,
+                                         double &cs, bool &clamped) {
+    const double tt = (double)t;
+    const double h = hqq - tt * hpp;
+    rotation_from_ct2(tt * (h / (2.0 * hpq)), t, tn, cs, clamped);
 }
 
 // The same formulas, branch-free, with the refined reciprocal and square

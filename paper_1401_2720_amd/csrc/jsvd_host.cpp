@@ -4,6 +4,7 @@
 // sweep performed no proper rotation (Section 4.5) or the sweep limit is
 // reached.  Everything else runs in the kernels of jsvd_gram.hip, jsvd_inner.hip,
 // jsvd_update.hip and jsvd_aux.hip.
+#include <cfloat>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -14,6 +15,30 @@
 #include "jsvd_internal.h"
 
 using namespace jsvd;
+
+// The upper safe bound of DRDSSQ (Appendix A), t_hi = RZ(sqrt(nu / delta_n))
+// with nu = (1 - 2^-53) 2^1024 and delta_n = 2^lg (1 + eps)^(1 + lg), eps =
+// 2^-53.  Written as 2^((1024 - lg) / 2) sqrt((1 - eps) / (1 + eps)^(1 + lg)),
+// the root's second factor is 1 - c eps + kappa eps^2 + O(lg^3 eps^3) with
+// c = (lg + 2) / 2 and kappa = lg / 4 + (lg + 2)^2 / 8 > 0.  Even lg: the
+// power of two is exact and c an integer, so the value lies just above the
+// double 2^(512 - lg/2) (1 - c eps), which is the result.  Odd lg: the
+// power carries a factor sqrt(2), and the value is computed in long double
+// (64-bit significand; powl, the division and sqrtl together stay within a
+// few units of 2^-64) and rounded toward zero to double.
+double jsvd::rdssq_t_hi(int lg) {
+    if (lg % 2 == 0) {
+        const double c = (double)((lg + 2) / 2);
+        return std::ldexp(1.0 - c * 0x1p-53, 512 - lg / 2);
+    }
+    const long double eps = 0x1p-53L;
+    const long double nu = (long double)DBL_MAX;
+    const long double dn = std::ldexp(std::pow(1.0L + eps, (long double)(lg + 1)), lg);
+    const long double x = std::sqrt(nu / dn);
+    double d = (double)x;
+    if ((long double)d > x) d = std::nextafter(d, 0.0);
+    return d;
+}
 
 namespace {
 
@@ -681,11 +706,13 @@ int hh_build_t(jsvd_handle_s *h, const QrWork &w, int64_t m, int64_t n) {
     return JSVD_OK;
 }
 
-// Whether hh_factor completed and R (in w.W) is numerically nonsingular
-// (min |r_ii| > n 2^-53 max |r_jj|); one stream synchronisation, the values
-// read through the handle's pinned words.
+// After hh_factor: whether a panel's grid barrier failed, whether R's
+// diagonal (in w.W) holds a NaN or an infinity (G was not finite), and
+// whether R is numerically singular (finite, min |r_ii| <= n 2^-53 max
+// |r_jj|); one stream synchronisation, the values read through the handle's
+// pinned words.
 int qr_check(jsvd_handle_s *h, const QrWork &w, int64_t m, int64_t n, bool *aborted,
-             bool *singular) {
+             bool *singular, bool *nonfinite = nullptr) {
     hipStream_t st = h->stream;
     HIP_TRY(launch_diag_range(w.W, m, n, w.d_range, st));
     int *hab = reinterpret_cast<int *>(h->host_counters + kSlotFlag);
@@ -694,7 +721,9 @@ int qr_check(jsvd_handle_s *h, const QrWork &w, int64_t m, int64_t n, bool *abor
     HIP_TRY(hipMemcpyAsync(range, w.d_range, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     *aborted = *hab != 0;
-    *singular = !(range[0] > (double)n * 0x1p-53 * range[1]);
+    const bool fin = std::isfinite(range[0]) && std::isfinite(range[1]);
+    if (nonfinite) *nonfinite = !fin;
+    *singular = fin && !(range[0] > (double)n * 0x1p-53 * range[1]);
     return JSVD_OK;
 }
 
@@ -725,6 +754,7 @@ int gesvd_rank_deficient(jsvd_handle_s *h, const QrWork &w1, int64_t m, int64_t 
                  oVx = take(nn * 8), oB1 = take(nn * 8), oC = take(nn * 8),
                  oT2 = take(npan * NB * NB * 8), oT3 = take(npan * NB * NB * 8),
                  oTau2 = take(n * 8), oTau3 = take(n * 8), oVn1 = take(n * 8), oVn2 = take(n * 8),
+                 oVn0 = take(n * 8), oCr = take(2 * (size_t)nwg * 8),
                  oCv = take(2 * (size_t)nwg * 8), oCi = take(2 * (size_t)nwg * 4),
                  oJp = take(n * 4), oRow = take(n * 4), oVp = take((size_t)n * NB * 8),
                  oParts = take((size_t)32 * NB * n * 8), oY1 = take((size_t)NB * n * 8),
@@ -767,7 +797,7 @@ int gesvd_rank_deficient(jsvd_handle_s *h, const QrWork &w1, int64_t m, int64_t 
     HIP_TRY(launch_zero_lower(Rn, n, n, st));
     QrcpArgs qa;
     qa.W = Rn; qa.ldw = n; qa.rows = n; qa.ncols = n; qa.tau = w2.tau; qa.jpvt = jpvt;
-    qa.vn1 = d(oVn1); qa.vn2 = d(oVn2); qa.cand_v = d(oCv);
+    qa.vn1 = d(oVn1); qa.vn2 = d(oVn2); qa.vn0 = d(oVn0); qa.cand_v = d(oCv); qa.cand_r = d(oCr);
     qa.cand_i = reinterpret_cast<int *>(ws + oCi); qa.rank = rank_d; qa.bar = bar;
     qa.abort_flag = abort_flag; qa.nwg = nwg; qa.tol = (double)n * 0x1p-53;
     HIP_TRY(launch_qrcp(qa, st));
@@ -777,7 +807,9 @@ int gesvd_rank_deficient(jsvd_handle_s *h, const QrWork &w1, int64_t m, int64_t 
     HIP_TRY(hipMemcpyAsync(hab, abort_flag, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const int64_t k = *hk;
-    if (*hab != 0 || k <= 0) return JSVD_OK;  // fall back
+    // fall back on a failed barrier, a zero R, or full numerical rank (R's
+    // small diagonal came from a graded, not a dependent, G)
+    if (*hab != 0 || k <= 0 || k >= n) return JSVD_OK;
     // R_2 in pivoted (logical) column order, then X = R_0^T (n x k)
     HIP_TRY(launch_gather_cols(Rn, n, R2, n, n, n, jpvt, nullptr, nullptr, st));
     HIP_TRY(launch_trap_transpose(R2, n, k, n, X, n, st));
@@ -840,13 +872,14 @@ int gesvd_qr(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, dou
     // stays orthogonal and zero singular values stay exact.  G itself is
     // untouched so far (the factorization works on the copy W).
     bool aborted = false, singular = false;
-    if ((rc = qr_check(h, w, m, n, &aborted, &singular))) return rc;
+    bool nonfinite = false;
+    if ((rc = qr_check(h, w, m, n, &aborted, &singular, &nonfinite))) return rc;
     if (!aborted && singular) {
         bool fallback = false;
         rc = gesvd_rank_deficient(h, w, m, n, A, lda, S, V, ldv, o, info, &fallback, t0);
         if (!fallback) return rc;
     }
-    if (aborted || singular) {
+    if (aborted || singular || nonfinite) {  // the direct method reports a NaN in G
         jsvd_opts od = o;
         od.qr = 1;
         return solve(h, m, n, A, lda, S, V, ldv, n, od, info, false, nullptr);
@@ -1242,7 +1275,7 @@ int check_batched_args(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t ma
     if (!A) return -10;
     if (!S) return -11;
     if (o.want_v && !V) return -12;
-    if (o.max_sweeps < 1) return -13;
+    if (o.max_sweeps < 1 || o.scaled < 0 || o.scaled > 2) return -13;
     return JSVD_OK;
 }
 
@@ -1284,6 +1317,10 @@ int launch_batched_solve(jsvd_handle_s *h, int64_t batch, int32_t max_n, const i
         const bool room = b.lds_doubles >= kBatchBlockLds;
         b.blk_min_n = (room && mn <= kBatchMaxN) ? mn : 0;
     }
+    // opts.scaled = 2: DDRJAC pairs and DRDSSQ norms, every problem pointwise
+    b.ddrjac = o.scaled == 2 ? 1 : 0;
+    if (b.ddrjac) b.blk_min_n = 0;
+    for (int lg = 0; lg < 32; ++lg) b.t_hi[lg] = b.ddrjac ? rdssq_t_hi(lg) : 0.0;
     HIP_TRY(launch_batched(b, bp.grid, bp.bgrid, max_n, reinterpret_cast<int *>(ws + bp.off_hist),
                            reinterpret_cast<int32_t *>(ws + bp.off_order), h->stream));
     return JSVD_OK;
@@ -1517,6 +1554,28 @@ int jsvd_reserve_batched(jsvd_handle_t h, int64_t batch, int32_t max_m, int32_t 
     if ((rc = ensure_batch_tables(h))) return rc;
     return ensure_batch_workspace(h, batch_plan(h, batch).total,
                                   stream_capturing(h->stream));
+}
+
+int jsvd_rdssq_bounds(int32_t lg, double *t_lo, double *t_hi) {
+    if (lg < 0 || lg > 63) return -1;
+    if (!t_lo || !t_hi) return -2;
+    *t_lo = 0x1.0000000000001p-511;
+    *t_hi = rdssq_t_hi(lg);
+    return JSVD_OK;
+}
+
+int jsvd_colnorms(jsvd_handle_t h, int64_t m, int64_t n, const double *A, int64_t lda,
+                  int32_t *exps, double *ssq, double *norms) {
+    if (!h) return -1;
+    if (m < 1 || m > ((int64_t)1 << 40)) return -2;
+    if (n < 0 || n > 0x7fffffff) return -3;
+    if (!A && n > 0) return -4;
+    if (lda < m) return -5;
+    if (!exps && !ssq && !norms) return -6;
+    if (n == 0) return JSVD_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
+    HIP_TRY(launch_rdssq_cols(A, lda, m, n, exps, ssq, norms, h->stream));
+    return JSVD_OK;
 }
 
 }  // extern "C"

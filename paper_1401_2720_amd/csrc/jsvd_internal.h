@@ -101,9 +101,16 @@ struct BatchArgs {
     int64_t lds_doubles;                        // problems with m n <= this work in LDS
     int g_groups;                               // half waves rotating G when V is wanted (of 32)
     int blk_min_n;                              // problems with n >= this are blocked (0: none)
+    int ddrjac;                                 // 1: DDRJAC pairs and DRDSSQ norms (no blocked problems)
+    double t_hi[32];                            // DRDSSQ upper bound by ceil(lg m)
 };
 
 hipError_t batched_set_lds(int bytes);
+
+// The upper safe bound of DRDSSQ (Appendix A) for vectors of length n with
+// ceil(lg n) = lg: RZ(sqrt(nu / delta_n)), nu the largest double,
+// delta_n = 2^lg (1 + 2^-53)^(1 + lg); 0 <= lg <= 63.
+double rdssq_t_hi(int lg);
 
 // grid: workgroups of the pointwise kernel; bgrid: of the blocked kernel
 // (two fit on a CU).
@@ -157,13 +164,15 @@ struct QrcpArgs {
     double *tau;           // [ncols] reflector scalars (the first rank used)
     int *jpvt;             // [ncols] out: physical column at each position
     double *vn1, *vn2;     // [ncols] partial norms, by physical column
+    double *vn0;           // [ncols] original column norms
     double *cand_v;        // [2 nwg] per-workgroup pivot candidates
+    double *cand_r;        // [2 nwg] per-workgroup largest kept fraction of a norm
     int *cand_i;           // [2 nwg]
     int *rank;             // out: the numerical rank
     unsigned *bar;         // grid barrier counter
     int *abort_flag;       // set when a barrier does not complete
     int nwg;
-    double tol;            // stop when the largest partial norm <= tol * the first pivot's
+    double tol;            // stop when every free column's partial norm <= tol * its norm
 };
 int qrcp_resident(int cu_count);
 hipError_t launch_qrcp(const QrcpArgs &a, hipStream_t s);
@@ -197,6 +206,8 @@ hipError_t launch_range_init(int *range, hipStream_t s);
 hipError_t launch_colexp(const double *G, int64_t ldg, int64_t m, int64_t n, double *s_out,
                          int *ex, int *range, hipStream_t s);
 hipError_t launch_rank(const double *s, int64_t n, int64_t n_plus, int *perm, hipStream_t st);
+hipError_t launch_rdssq_cols(const double *A, int64_t lda, int64_t m, int64_t n, int32_t *exps,
+                             double *ssq, double *norms, hipStream_t s);
 hipError_t launch_identity_cols(double *B, int64_t ldb, int64_t rows, int64_t cols, int64_t first,
                                 hipStream_t s);
 hipError_t launch_count_positive(const double *S, int64_t n, int *out, hipStream_t s);

@@ -283,9 +283,12 @@ __global__ void diag_range_kernel(const double *W, int64_t ldw, int64_t n, doubl
 // j .. rows-1 (LAPACK's convention: beta at row j, v below it with v(j) = 1
 // implicit), and every owner applies it to its free columns and downdates
 // their partial norms (recomputed when the downdate loses accuracy, as in
-// LAPACK's xLAQP2).  The factorization stops at the first step whose
-// largest partial norm is <= tol times the first pivot's, or at
-// min(rows, ncols): that step count is the numerical rank k.  jpvt[j] is
+// LAPACK's xLAQP2).  The factorization stops at the first step at which
+// every free column has kept at most tol of its original norm outside the
+// span of the pivots so far (partial norm <= tol times the column's norm;
+// a zero column counts as spent), or at min(rows, ncols): that step count is
+// the numerical rank k.  The test is invariant under column scaling, so a
+// column that is small but independent (a graded G) keeps its place.  jpvt[j] is
 // the physical column at position j (positions >= k: the remaining columns
 // in increasing order).  All reductions have a fixed order.
 struct QrcpShared {
@@ -337,7 +340,7 @@ __global__ __launch_bounds__(kQT) void qrcp_kernel(QrcpArgs a) {
     const int nwg = a.nwg;
     const int kmax = (int)min(rows, a.ncols);
     unsigned epoch = 0;
-    // partial norms of the owned columns
+    // partial norms of the owned columns, and their original norms
     for (int64_t c = wg; c < a.ncols; c += nwg) {
         const double *col = a.W + c * a.ldw;
         double s = 0.0;
@@ -346,39 +349,45 @@ __global__ __launch_bounds__(kQT) void qrcp_kernel(QrcpArgs a) {
         if (t == 0) {
             a.vn1[c] = nrm;
             a.vn2[c] = nrm;
+            a.vn0[c] = nrm;
         }
     }
     __syncthreads();
-    double vmax0 = 0.0;
     int k = kmax;
     for (int j = 0; j < kmax; ++j) {
         const int par = j & 1;
-        // the workgroup's candidate: largest partial norm of a free column
-        double bv = -1.0;
+        // the workgroup's candidate: largest partial norm of a free column,
+        // and the largest fraction of its norm that a free column has kept
+        double bv = -1.0, br = 0.0;
         int bi = 0x7fffffff;
         for (int64_t c = wg + (int64_t)t * nwg; c < a.ncols; c += (int64_t)kQT * nwg) {
-            const double v = a.vn1[c];
+            const double v = a.vn1[c], v0 = a.vn0[c];
             if (v > bv || (v == bv && c < bi)) {
                 bv = v;
                 bi = (int)c;
             }
+            if (v >= 0.0 && v0 > 0.0) br = fmax(br, v / v0);
         }
         wg_argmax(bv, bi, sh, bv, bi);
+        int unused;
+        wg_argmax(br, 0, sh, br, unused);
         if (t == 0) {
             a.cand_v[par * nwg + wg] = bv;
             a.cand_i[par * nwg + wg] = bi;
+            a.cand_r[par * nwg + wg] = br;
         }
         if (!grid_sync(a.bar, ++epoch * (unsigned)nwg, a.abort_flag)) return;
         // the pivot: the same choice in every workgroup
-        double pv = -1.0;
+        double pv = -1.0, pr = 0.0;
         int pc = 0x7fffffff;
         if (t < nwg) {
             pv = a.cand_v[par * nwg + t];
             pc = a.cand_i[par * nwg + t];
+            pr = a.cand_r[par * nwg + t];
         }
         wg_argmax(pv, pc, sh, pv, pc);
-        if (j == 0) vmax0 = pv;
-        if (!(pv > 0.0) || pv <= a.tol * vmax0) {
+        wg_argmax(pr, 0, sh, pr, unused);
+        if (!(pv > 0.0) || pr <= a.tol) {
             k = j;
             break;
         }

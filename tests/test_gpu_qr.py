@@ -128,6 +128,26 @@ def test_qr_rank_deficient_lq_path(name, m, n, k, zc):
     _say(f"  sweeps={info['sweeps']}")
 
 
+def test_qr_graded_full_rank_is_not_truncated():
+    """Column groups 2^450 B1 and 2^-450 P2 (P2 orthogonal to B1): R's
+    diagonal spans 2^900, but no column depends on the others, so the
+    pivoted QR's scale-invariant rank test finds full rank and every sigma
+    keeps its relative accuracy (the small group is not set to zero)."""
+    _say("qr graded full rank")
+    g = inputs.rng(45)
+    B1, B2 = inputs.gaussian(300, 40, g), inputs.gaussian(300, 30, g)
+    Q, _ = np.linalg.qr(B1)
+    P2 = B2 - Q @ (Q.T @ B2)
+    P2 = P2 - Q @ (Q.T @ P2)
+    A = np.hstack([np.ldexp(B1, 450), np.ldexp(B2, -450)])
+    s1 = np.ldexp(oracle.gesvj(B1)["S"], 450)
+    s2 = np.ldexp(oracle.gesvj(P2)["S"], -450)
+    U, S, V, info = _run(A, qr="on", scaled="off")
+    assert info["status"] == 0 and info["rank"] == 70, info
+    assert np.max(np.abs(S[:40] - s1) / s1) <= 1e-12
+    assert np.max(np.abs(S[40:] - s2) / s2) <= 1e-12
+
+
 def test_qr_zero_matrix_falls_back_to_direct():
     _say("qr zero matrix -> direct")
     A = np.zeros((300, 30))
@@ -135,3 +155,12 @@ def test_qr_zero_matrix_falls_back_to_direct():
     assert info["status"] == 0 and info["preprocessed"] == 0
     assert np.all(S == 0.0) and np.all(U == 0.0)
     assert np.max(np.abs(V.T @ V - np.eye(30))) <= 1e-13 * 30
+
+def test_qr_path_reports_nan_input():
+    """A NaN in a tall G on the QR path: R's diagonal is not finite, the call
+    goes to the direct method, which reports JSVD_NONFINITE (3)."""
+    _say("qr nan input")
+    A = inputs.gaussian(400, 40, inputs.rng(44))
+    A[11, 5] = np.nan
+    _, _, _, info = _run(A, qr="on", allow=(1, 2, 3))
+    assert info["status"] == 3
