@@ -90,6 +90,14 @@ typedef struct {
                                  block-pair, ratios of column norms up to about 2^1000
                                  (tested to 2^900).
                                  A badly scaled G skips the QR preprocessing. */
+    int32_t factorize;        /* how a pivot block-pair is shortened to its 2w x 2w triangular
+                                 factor R: 0 = Cholesky of the Gram matrix (Section 4.1,
+                                 default), 1 = the QR shortening of Section 4.2 (eq. (2.8)):
+                                 Householder QR of chunks of 2w rows, chunk factors folded
+                                 together by the peel-off Givens procedure, the Gram matrix
+                                 never formed (slower; R's accuracy does not depend on the
+                                 square of the pair's condition number).  With 1, block_w 64
+                                 is taken as 32. */
 } jsvd_opts;
 
 typedef struct {

@@ -25,7 +25,7 @@ STATUS = {0: "ok", 1: "not converged", 3: "non-finite value", 4: "HIP error",
 class Opts(ctypes.Structure):
     _fields_ = [("block_w", _i32), ("strategy", _i32), ("max_inner_sweeps", _i32),
                 ("max_sweeps", _i32), ("want_v", _i32), ("sort", _i32), ("qr", _i32),
-                ("scaled", _i32)]
+                ("scaled", _i32), ("factorize", _i32)]
 
 
 class Info(ctypes.Structure):
@@ -198,8 +198,11 @@ def set_tuning(device_index, table, handle=None):
 QR_MODES = {"auto": 0, "off": 1, "on": 2}  # also the scaled-mode choices
 
 
+FACTORIZE = {"cholesky": 0, "qr": 1}
+
+
 def make_opts(block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,
-              sort=True, qr="auto", scaled="auto"):
+              sort=True, qr="auto", scaled="auto", factorize="cholesky"):
     o = Opts()
     lib().jsvd_default_opts(ctypes.byref(o))
     o.block_w = int(block_w)
@@ -210,6 +213,7 @@ def make_opts(block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, wan
     o.sort = 1 if sort else 0
     o.qr = QR_MODES[qr] if isinstance(qr, str) else int(qr)
     o.scaled = QR_MODES[scaled] if isinstance(scaled, str) else int(scaled)
+    o.factorize = FACTORIZE[factorize] if isinstance(factorize, str) else int(factorize)
     return o
 
 
@@ -227,7 +231,7 @@ def _raise_on(rc, what, allow):
 
 
 def gesvd(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,
-          sort=True, allow=(1,), qr="auto", scaled="auto"):
+          sort=True, allow=(1,), qr="auto", scaled="auto", factorize="cholesky"):
     """SVD A = U diag(S) V^T of a float64 CUDA tensor (m >= n).
 
     Returns (U, S, V, info): U (m x n) and V (n x n) column-major views, S (n),
@@ -243,7 +247,8 @@ def gesvd(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want
     stream = torch.cuda.current_stream(dev)
     h = _handle(dev.index if dev.index is not None else torch.cuda.current_device(),
                 stream.cuda_stream)
-    o = make_opts(block_w, strategy, max_inner_sweeps, max_sweeps, want_v, sort, qr, scaled)
+    o = make_opts(block_w, strategy, max_inner_sweeps, max_sweeps, want_v, sort, qr, scaled,
+                  factorize)
     info = Info()
     rc = lib().jsvd_gesvd(h, m, n, _vp(work.data_ptr()), m, _vp(S.data_ptr()),
                           _vp(Vb.data_ptr()) if want_v else None, n, ctypes.byref(o),
@@ -255,7 +260,7 @@ def gesvd(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want
 
 
 def gesvd_full(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,
-               allow=(1,), qr="auto", scaled="auto"):
+               allow=(1,), qr="auto", scaled="auto", factorize="cholesky"):
     """Full SVD A = U [diag(S); 0] V^T of a float64 CUDA tensor (m >= n) with
     U of order m.  Returns (U, S, V, info): U (m x m) and V (n x n) views of
     column-major buffers."""
@@ -269,7 +274,8 @@ def gesvd_full(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30,
     stream = torch.cuda.current_stream(dev)
     h = _handle(dev.index if dev.index is not None else torch.cuda.current_device(),
                 stream.cuda_stream)
-    o = make_opts(block_w, strategy, max_inner_sweeps, max_sweeps, want_v, True, qr, scaled)
+    o = make_opts(block_w, strategy, max_inner_sweeps, max_sweeps, want_v, True, qr, scaled,
+                  factorize)
     info = Info()
     rc = lib().jsvd_gesvd_full(h, m, n, _vp(work.data_ptr()), m, _vp(Ub.data_ptr()), m,
                                _vp(S.data_ptr()), _vp(Vb.data_ptr()) if want_v else None, n,
@@ -281,7 +287,7 @@ def gesvd_full(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30,
 
 
 def hsvd(G, J, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,
-         sort=True, allow=(1,), scaled="auto"):
+         sort=True, allow=(1,), scaled="auto", factorize="cholesky"):
     """Hyperbolic SVD G V = U diag(S), V^T J V = diag(J_out).
 
     J: sequence of n values, each +1 or -1.  Returns (U, S, V, J_out, info)
@@ -301,7 +307,8 @@ def hsvd(G, J, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, wa
     stream = torch.cuda.current_stream(dev)
     h = _handle(dev.index if dev.index is not None else torch.cuda.current_device(),
                 stream.cuda_stream)
-    o = make_opts(block_w, strategy, max_inner_sweeps, max_sweeps, want_v, sort, scaled=scaled)
+    o = make_opts(block_w, strategy, max_inner_sweeps, max_sweeps, want_v, sort, scaled=scaled,
+                  factorize=factorize)
     info = Info()
     rc = lib().jsvd_hsvd(h, m, n, _vp(work.data_ptr()), m, _vp(Jh.ctypes.data),
                          _vp(Jout.ctypes.data), _vp(S.data_ptr()),

@@ -201,6 +201,7 @@ jsvd_opts defaults() {
     o.sort = 1;
     o.qr = 0;
     o.scaled = 0;
+    o.factorize = 0;
     return o;
 }
 
@@ -331,9 +332,11 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
         scaled = scaled || bad;
     }
     const Shapes shp = pick_shapes(h, o, m, n);
-    // w = 64 (the third blocking level) runs the ordinary, unscaled SVD; the
-    // hyperbolic SVD and the scaled mode take w = 32 instead
-    const int w = (shp.w == 64 && (n_plus < n || scaled)) ? 32 : shp.w;
+    // w = 64 (the third blocking level) runs the ordinary, unscaled SVD with
+    // the Cholesky factorization; the hyperbolic SVD, the scaled mode and the
+    // QR shortening take w = 32 instead
+    const bool qrf = o.factorize == 1;
+    const int w = (shp.w == 64 && (n_plus < n || scaled || qrf)) ? 32 : shp.w;
     const int bw = 2 * w;
     const int nb_real = (int)((n + w - 1) / w);
     const int order = strategy_order(nb_real);
@@ -390,6 +393,7 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     a.inner_tbl = inner;
     a.colexp = scaled ? h->colexp : nullptr;
     a.rscratch = bw == 128 ? reinterpret_cast<double *>(ws + L.rscratch) : nullptr;
+    a.qrf = qrf ? 1 : 0;
     a.btbl_order = static_cast<const int *>(h->batch_meta);
     a.btbl_off = reinterpret_cast<const int64_t *>(
         static_cast<char *>(h->batch_meta) + align_up((kBatchMaxN + 1) * sizeof(int), 256));
@@ -439,7 +443,7 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
             const bool timed = h->timing && s % h->timing_stride == 0;
             hipEvent_t *ev = timed ? &h->events[(size_t)4 * s] : nullptr;
             if (ev) HIP_TRY(hipEventRecord(ev[0], st));
-            HIP_TRY(launch_gram(bw, a, st));
+            HIP_TRY(qrf ? launch_qrfac(bw, a, st) : launch_gram(bw, a, st));
             if (ev) HIP_TRY(hipEventRecord(ev[1], st));
             HIP_TRY(launch_inner(bw, a, st));
             if (ev) HIP_TRY(hipEventRecord(ev[2], st));
@@ -1016,6 +1020,7 @@ int check_opts(const jsvd_opts &o) {
     if (o.max_sweeps < 1 || o.max_inner_sweeps < 0) return -1;
     if (o.qr < 0 || o.qr > 2) return -1;
     if (o.scaled < 0 || o.scaled > 2) return -1;
+    if (o.factorize < 0 || o.factorize > 1) return -1;
     return JSVD_OK;
 }
 

@@ -5,7 +5,7 @@
 // to V (eq. (2.9)): V lies off the path from one p-step's Gram matrices to
 // the next, and these workgroups stream it through HBM on the CUs that the
 // pivot pairs leave idle.
-#include "jsvd_blocked.h"
+#include "jsvd_qrpair.h"
 #include "jsvd_rows.h"
 
 namespace jsvd {
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
                                 ? hp[(size_t)(s0 + sp) * BW * BW + e] : 0.0;
             }
     };
-    load_batch(0);
+    if (!a.qrf) load_batch(0);
 
     // ---- strategy table and pair flags: 1 hyperbolic (kp < n+ <= kq),
     // 2 a padding column, 4 both columns in the + part, 8 both in the - part
@@ -143,7 +143,27 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
         }
     }
 
-    {
+    if (a.qrf) {
+        // QR shortening (Section 4.2): the splits' triangular factors folded
+        // into R by the peel-off procedure, V' (still free) holding the next
+        // factor; then V' = I
+        auto load_factor = [&](double *X, int sp) {
+            for (int e = tid; e < BW * BW; e += NT) {
+                const int i = e / BW, j = e % BW;
+                X[j * LD + i] = i <= j ? hp[(size_t)sp * BW * BW + e] : 0.0;
+            }
+        };
+        load_factor(R, 0);
+        for (int sp = 1; sp < a.splits; ++sp) {
+            load_factor(Vp, sp);
+            __syncthreads();
+            peel_off<BW, NT>(R, Vp, LD);
+        }
+        for (int e = tid; e < BW * BW; e += NT) {
+            const int i = e % BW, j = e / BW;
+            Vp[j * LD + i] = (i == j) ? 1.0 : 0.0;
+        }
+    } else {
         double s[EPT];
 #pragma unroll
         for (int u = 0; u < EPT; ++u) s[u] = 0.0;
@@ -175,12 +195,20 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
     __syncthreads();
 
 
+    // ---- QR shortening: R is there; a NaN or infinity on its diagonal
+    // stops the pair as a non-finite Cholesky pivot does
+    if (a.qrf) {
+        for (int c = tid; c < BW; c += NT)
+            if (!(fabs(R[c * LD + c]) <= 0x1.fffffffffffffp+1023)) flags[0] = 1;
+        __syncthreads();
+    }
+
     // ---- nothing to do: when every pair (i, j) of the block pair already
     // passes the relative orthogonality test on H itself, no rotation can
     // happen in the inner sweep (no column of R would change, so its dot
     // products stay those of H up to the rounding of the Cholesky factor),
     // and the pair is left alone as if the sweep had rotated nothing.
-    {
+    if (!a.qrf) {
         const double tol = kEps * sqrt((double)BW);
         bool need = false;
 #pragma unroll
@@ -202,6 +230,7 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
     // pivot that is NaN or infinite stops the pair.  The panel has no branch,
     // so the updates of one pivot overlap the square root of the next; row k
     // of R is H's row k times 1/sqrt(h_kk).
+    if (!a.qrf) {
 #pragma unroll
     for (int kb = 0; kb < BW / 16; ++kb) {
         if (wave == 0) {
@@ -267,6 +296,7 @@ __global__ __launch_bounds__(InnerCfg<BW>::kThreads) void inner_kernel(StepArgs 
             __syncthreads();
         }
     }
+    }  // !a.qrf
     if (flags[0]) {
         if (tid == 0) {
             a.pair_rot[pair] = 0;

@@ -72,12 +72,17 @@ struct StepArgs {
     // scratch for the Cholesky factor R, and the strategy tables of the
     // block method inside the pair (every order up to 256, zero-based pairs)
     double *rscratch;
+    // QR shortening (Section 4.2): hpart holds the splits' triangular
+    // factors of [G_p G_q] (qrfac kernel) instead of partial Gram matrices,
+    // and the inner kernel folds them together in place of the Cholesky
+    int qrf;
     const int *btbl_order;
     const int64_t *btbl_off;
     const unsigned char *btbls;
 };
 
 hipError_t launch_gram(int bw, const StepArgs &a, hipStream_t s);
+hipError_t launch_qrfac(int bw, const StepArgs &a, hipStream_t s);
 hipError_t launch_inner(int bw, const StepArgs &a, hipStream_t s);
 hipError_t launch_update(int bw, const StepArgs &a, hipStream_t s);
 
