@@ -134,6 +134,12 @@ def test_partitions():
     assert R.rdssq(np.array([th, tl, 0.0]))[2] == 2      # inclusive bounds
     assert R.rdssq(np.array([np.nextafter(th, np.inf), 1.0, 0.0]))[2] == 6
     assert R.rdssq(np.array([np.nextafter(tl, 0.0), 1.0, 0.0]))[2] == 3
+    # elements exactly on the bounds belong to the unscaled sum, and alone
+    # their norm is exact (sqrt(RN(v^2)) = |v|)
+    for v in (tl, float(R.t_hi_table()[0])):
+        j, s, parts = R.rdssq(np.array([v]))
+        assert parts == 2 and R.norm(np.array([v])) == v, v
+    assert R.rdssq(np.full(16, float(R.t_hi_table()[4])))[2] == 2
     # three partial sums: the value is exact here (each term is a power of
     # two far apart, and the sums are dominated by the largest)
     j, s, _ = R.rdssq(np.array([2.0 ** 600, 3.0, 2.0 ** -600]))
