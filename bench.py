@@ -41,9 +41,14 @@ def parse():
     ap.add_argument("--no-forms", action="store_true",
                     help="leave the batched and differentiable forms out of the svd4096 line")
     ap.add_argument("--workload", default="svd4096",
-                    choices=["svd4096", "tall", "batched", "backward"],
+                    choices=["svd4096", "tall", "batched", "backward", "svd4096_qrfactor"],
                     help="svd4096: the benchmark line; tall: the 8192 x 2048 graded SVD (QR "
-                         "preprocessing); batched / backward: the other forms")
+                         "preprocessing); batched / backward: the other forms; "
+                         "svd4096_qrfactor: the benchmark matrix with the QR shortening of "
+                         "the pivot pairs (opts.factorize = 1)")
+    ap.add_argument("--batched-scaled", default="auto", choices=["auto", "on"],
+                    help="batched workload: 'on' runs every problem with DDRJAC pairs and "
+                         "DRDSSQ norms (opts.scaled = 2)")
     return ap.parse_args()
 
 
@@ -138,7 +143,7 @@ def cpu_baseline(A, gpu_sweeps, target_s):
                        f"time x {sweeps} sweeps ({whose} sweep count on this matrix)")}
 
 
-def measure_batched(steps, warmup, cpu_seconds, plain_sample=200):
+def measure_batched(steps, warmup, cpu_seconds, plain_sample=200, scaled="auto"):
     """10,000 uneven problems (n ~ U{8..128}, m = n + U{0..64}, 20 % graded)
     in the two persistent launches, captured in a HIP graph and replayed;
     beside it the plain form (one jsvd_gesvd per problem, synchronising per
@@ -155,12 +160,12 @@ def measure_batched(steps, warmup, cpu_seconds, plain_sample=200):
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
         for _ in range(max(1, warmup)):
-            jsvd.gesvd_batched(b)
+            jsvd.gesvd_batched(b, scaled=scaled)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        jsvd.gesvd_batched(b)
+        jsvd.gesvd_batched(b, scaled=scaled)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -177,7 +182,7 @@ def measure_batched(steps, warmup, cpu_seconds, plain_sample=200):
     # pairs of 2w = 32 columns): per pair the Gram matrix 2w(2w+1)m, the
     # Cholesky (2w)^3/3, one inner sweep of 2w(2w-1)/2 pairs x (dots 6(2w)
     # + rotation of R and V' 6(4w)), and G and V times V' 2(m+n)(2w)^2
-    blk = n >= jsvd.batched_block_min_n()
+    blk = (n >= jsvd.batched_block_min_n()) & (scaled != "on")
     w2 = 32.0
     nb = np.ceil(n / 16.0)
     per_pair = (w2 * (w2 + 1) * m + w2 ** 3 / 3 + w2 * (w2 - 1) / 2 * (6 * w2 + 12 * w2)
@@ -210,10 +215,14 @@ def measure_batched(steps, warmup, cpu_seconds, plain_sample=200):
         # oracle on the problems in index order (one per OpenMP thread) until
         # the sample reaches the target time, scaled to problems per second
         done, t_cpu, k = 0, 0.0, 64
+        many = oracle.gesvj_many
+        if scaled == "on":
+            from oracle import rdssq
+            many = rdssq.gesvj_many
         while t_cpu < cpu_seconds and done < len(mats):
             chunk = mats[done:done + k]
             c0 = time.perf_counter()
-            oracle.gesvj_many(chunk)
+            many(chunk)
             t_cpu += time.perf_counter() - c0
             done += len(chunk)
             k *= 2
@@ -230,12 +239,13 @@ def measure_batched(steps, warmup, cpu_seconds, plain_sample=200):
 
 
 def bench_batched(args):
-    r = measure_batched(args.steps, args.warmup, args.cpu_seconds)
+    r = measure_batched(args.steps, args.warmup, args.cpu_seconds, scaled=args.batched_scaled)
     out = {"metric": "batched small SVDs/s", "value": r["svds_per_s"], "unit": "SVDs/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_batch"],
            "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": "batched_10000_ragged_n8-128", "seed": 5, "graph": True,
+                      "scaled": args.batched_scaled,
                       "sweeps_mean": r["sweeps_mean"], "sweeps_max": r["sweeps_max"],
                       "not_converged": r["not_converged"]},
            "roofline": r["roofline"], "plain_form": r["plain_form"],
@@ -367,6 +377,71 @@ def bench_tall(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_qrfactor(args):
+    """The benchmark matrix (4096 x 4096 N(0,1), seed 2) with the QR
+    shortening of the pivot block-pairs (Section 4.2) in place of the
+    Cholesky factor; one step = one SVD; sigma against the oracle's golden
+    values; per-kernel event times (the first kernel of a p-step is the QR
+    kernel here)."""
+    import numpy as np
+    import torch
+
+    import paper_1401_2720_amd as jsvd
+    from paper_1401_2720_amd import _binding as B
+    from paper_1401_2720_amd import inputs
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    n = args.n
+    A0 = torch.from_numpy(inputs.square_gaussian(seed=2, n=n)).to(dev).t().contiguous()
+    work = torch.empty_like(A0)
+    S = torch.empty(n, dtype=torch.float64, device=dev)
+    V = torch.empty((n, n), dtype=torch.float64, device=dev)
+    L = jsvd.lib()
+    h = B._handle(0, torch.cuda.current_stream(dev).cuda_stream)
+    opts = B.make_opts(block_w=args.block_w, strategy=args.strategy,
+                       max_inner_sweeps=args.max_inner_sweeps, factorize="qr")
+    info = B.Info()
+
+    def step():
+        work.copy_(A0)
+        rc = L.jsvd_gesvd(h, n, n, ctypes.c_void_p(work.data_ptr()), n,
+                          ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(V.data_ptr()), n,
+                          ctypes.byref(opts), ctypes.byref(info))
+        if rc != 0:
+            raise B.JsvdError(rc, "jsvd_gesvd")
+
+    for _ in range(args.warmup):
+        step()
+    B.kernel_timing(0, True, stride=TIMING_STRIDE)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sweeps = []
+    for _ in range(args.steps):
+        step()
+        sweeps.append(info.sweeps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    kt = B.kernel_times(0)
+    B.kernel_timing(0, False)
+    acc = None
+    gold = os.path.join(ROOT, "tests", "golden", "sigma_gaussian4096_seed2.txt")
+    if n == 4096 and os.path.exists(gold):
+        ref = np.loadtxt(gold)
+        s = S.cpu().numpy()
+        big = ref >= 1e-3 * ref[0]
+        acc = {"max_rel_sigma_err_above_1e-3": float(np.max(np.abs(s - ref)[big] / ref[big]))}
+    out = {"metric": f"FP64 SVD time (s) at n={n}, QR shortening", "value": ms / 1e3,
+           "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": False, "scaling": "strong",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"svd_gaussian_{n}x{n}_qrfactor", "m": n, "n": n, "seed": 2,
+                      "block_w": info.block_w, "factorize": "qr", "sweeps": sweeps},
+           "kernels_avg_us": {("qrfac" if k == "gram" else k): kt[k][0] / max(kt[k][1], 1) * 1e3
+                              for k in kt},
+           "accuracy": acc, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -379,6 +454,8 @@ def main():
         return bench_batched(args)
     if args.workload == "backward":
         return bench_backward(args)
+    if args.workload == "svd4096_qrfactor":
+        return bench_qrfactor(args)
     import numpy as np
     import torch
 
