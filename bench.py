@@ -319,7 +319,7 @@ def bench_backward(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_tall(args):
+def measure_tall(steps, warmup):
     """The tall workload: 8192 x 2048, Q1 diag(sigma) Q2^T with sigma
     log-spaced 1 .. 1e-10 (seed 3), through jsvd_gesvd (QR preprocessing of
     eq. (2.1), the Jacobi method on R^T); one step = one SVD, the input
@@ -351,29 +351,35 @@ def bench_tall(args):
         if rc != 0:
             raise B.JsvdError(rc, "jsvd_gesvd")
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sweeps = []
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
         sweeps.append(info.sweeps)
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    ms = (time.perf_counter() - t0) / steps * 1e3
     sig = inputs.logspaced(n, -10.0)
     s = S.cpu().numpy()
-    out = {"metric": "FP64 SVD time (s) at 8192x2048", "value": ms / 1e3, "unit": "s",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+    return {"s": ms / 1e3, "ms": ms, "m": m, "n": n, "block_w": info.block_w,
+            "preprocessed": info.preprocessed, "sweeps": sweeps,
+            "accuracy": {"max_abs_sigma_err": float(np.max(np.abs(s - sig))),
+                         "max_rel_sigma_err_above_1e-3": float(np.max(
+                             np.abs(s - sig)[sig >= 1e-3] / sig[sig >= 1e-3]))}}
+
+
+def bench_tall(args):
+    r = measure_tall(args.steps, args.warmup)
+    out = {"metric": "FP64 SVD time (s) at 8192x2048", "value": r["s"], "unit": "s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms"],
            "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
-           "config": {"workload": "svd_tall_graded_8192x2048", "m": m, "n": n, "seed": 3,
-                      "block_w": info.block_w, "preprocessed": info.preprocessed,
-                      "sweeps": sweeps},
-           "accuracy": {"max_abs_sigma_err": float(np.max(np.abs(s - sig))),
-                        "max_rel_sigma_err_above_1e-3": float(np.max(
-                            np.abs(s - sig)[sig >= 1e-3] / sig[sig >= 1e-3]))},
-           "cpu_baseline": None}
+           "config": {"workload": "svd_tall_graded_8192x2048", "m": r["m"], "n": r["n"],
+                      "seed": 3, "block_w": r["block_w"], "preprocessed": r["preprocessed"],
+                      "sweeps": r["sweeps"]},
+           "accuracy": r["accuracy"], "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
 
@@ -588,9 +594,11 @@ def main():
         torch.cuda.synchronize()
         bat = measure_batched(steps=5, warmup=1, cpu_seconds=0)
         bwd = measure_backward(steps=3, warmup=1)
+        tall = measure_tall(steps=3, warmup=1)
         forms = {"batched_svds_per_s": bat["svds_per_s"], "batched": bat,
                  "differentiable_forward_backward_s": bwd["forward_backward_s"],
-                 "differentiable": bwd["parts"]}
+                 "differentiable": bwd["parts"],
+                 "tall_8192x2048_s": tall["s"], "tall_8192x2048": tall}
 
     out = {
         "metric": "FP64 SVD time (s) at n=4096",

@@ -15,7 +15,7 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libjsvd.so")
 SOURCES = ["jsvd_gram.hip", "jsvd_qrfac.hip", "jsvd_inner.hip", "jsvd_update.hip", "jsvd_aux.hip", "jsvd_qr.hip",
            "jsvd_batched.hip",
-           "jsvd_backward.hip", "jsvd_host.cpp",
+           "jsvd_backward.hip", "jsvd_gemm.hip", "jsvd_host.cpp",
            "strategy.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
