@@ -89,7 +89,10 @@ typedef struct {
                                  norms over the whole normal range and, within one pivot
                                  block-pair, ratios of column norms up to about 2^1000
                                  (tested to 2^900).
-                                 A badly scaled G skips the QR preprocessing. */
+                                 A badly scaled tall G keeps the QR preprocessing: its
+                                 columns are scaled by the same powers of two before the
+                                 Householder QR, and the Jacobi method runs on
+                                 (R D)^T in the scaled mode. */
     int32_t factorize;        /* how a pivot block-pair is shortened to its 2w x 2w triangular
                                  factor R: 0 = Cholesky of the Gram matrix (Section 4.1,
                                  default), 1 = the QR shortening of Section 4.2 (eq. (2.8)):

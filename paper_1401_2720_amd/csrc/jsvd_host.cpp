@@ -568,7 +568,8 @@ int gemm_plain(bool ta, const double *A, int64_t lda, const double *B, int64_t l
 // ncols: the widest block Q is applied to (n for U = Q [V_x; 0], up to m for
 // the full U).
 struct QrLayout {
-    size_t oW, oX, oVx, oVp, oT, oTau, oParts, oY1, oY2, oPart, oProw, oNrm, oPerm, oBar, total;
+    size_t oW, oX, oVx, oVp, oT, oTau, oParts, oY1, oY2, oPart, oProw, oNrm, oScl, oPerm, oBar,
+        total;
 };
 
 QrLayout qr_plan(int64_t m, int64_t n, int64_t ncols = 0) {
@@ -590,6 +591,7 @@ QrLayout qr_plan(int64_t m, int64_t n, int64_t ncols = 0) {
     q.oPart = take((size_t)2 * 64 * NB * 8);
     q.oProw = take((size_t)2 * NB * 8);
     q.oNrm = take((size_t)n * 8);
+    q.oScl = take((size_t)2 * n * 8);
     q.oPerm = take((size_t)n * 4);
     q.oBar = take(128);
     q.total = off;
@@ -598,7 +600,7 @@ QrLayout qr_plan(int64_t m, int64_t n, int64_t ncols = 0) {
 
 // Pointers into the QR workspace of a layout.
 struct QrWork {
-    double *W, *X, *Vx, *Vp, *T, *tau, *parts, *Y1, *Y2, *part, *prow, *nrm, *d_range;
+    double *W, *X, *Vx, *Vp, *T, *tau, *parts, *Y1, *Y2, *part, *prow, *nrm, *scl, *d_range;
     int *perm, *abort_flag;
     unsigned *bar;
 };
@@ -621,7 +623,7 @@ int qr_workspace(jsvd_handle_s *h, const QrLayout &q, QrWork *w) {
     auto d = [&](size_t o) { return reinterpret_cast<double *>(ws + o); };
     w->W = d(q.oW); w->X = d(q.oX); w->Vx = d(q.oVx); w->Vp = d(q.oVp); w->T = d(q.oT);
     w->tau = d(q.oTau); w->parts = d(q.oParts); w->Y1 = d(q.oY1); w->Y2 = d(q.oY2);
-    w->part = d(q.oPart); w->prow = d(q.oProw); w->nrm = d(q.oNrm);
+    w->part = d(q.oPart); w->prow = d(q.oProw); w->nrm = d(q.oNrm); w->scl = d(q.oScl);
     w->perm = reinterpret_cast<int *>(ws + q.oPerm);
     w->bar = reinterpret_cast<unsigned *>(ws + q.oBar);
     w->abort_flag = reinterpret_cast<int *>(ws + q.oBar + 8);
@@ -857,8 +859,15 @@ int gesvd_rank_deficient(jsvd_handle_s *h, const QrWork &w1, int64_t m, int64_t 
     return status;
 }
 
+//
+// scaled (a badly scaled G, §4.2): the columns are scaled by the powers of
+// two of their norms before the factorization, W = G P D^-1 with D =
+// diag(2^e_c), ||g_c|| in [2^e_c, 2^(e_c+1)) (exact), so that no sum of the
+// Householder reflections leaves the normal range; then G P = Q (R~ D) and
+// the Jacobi method runs on X = (R~ D)^T (whose columns the scaled mode of
+// the Jacobi method handles).  A singular R~ sends G to the direct method.
 int gesvd_qr(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double *S,
-             double *V, int64_t ldv, const jsvd_opts &o, jsvd_info *info) {
+             double *V, int64_t ldv, const jsvd_opts &o, jsvd_info *info, bool scaled = false) {
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = h->stream;
     QrWork w;
@@ -866,9 +875,18 @@ int gesvd_qr(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, dou
     if (rc) return rc;
 
     // presort: W = G P, columns by non-increasing norm (ties by index)
-    HIP_TRY(launch_colnorms(A, lda, m, n, w.nrm, st));
+    double *dscale = w.scl + n;  // scaled: W's column k is G's perm[k] over dscale[k]
+    if (scaled) {
+        // norms and exponents by DRDSSQ (Appendix A); h->colexp was sized by
+        // the caller's scaling check
+        HIP_TRY(launch_colexp(A, lda, m, n, w.nrm, h->colexp, nullptr, st));
+        HIP_TRY(launch_pow2(h->colexp, n, w.scl, st));
+    } else {
+        HIP_TRY(launch_colnorms(A, lda, m, n, w.nrm, st));
+    }
     HIP_TRY(launch_rank(w.nrm, n, n, w.perm, st));
-    HIP_TRY(launch_gather_cols(A, lda, w.W, m, m, n, w.perm, nullptr, nullptr, st));
+    HIP_TRY(launch_gather_cols(A, lda, w.W, m, m, n, w.perm, scaled ? w.scl : nullptr,
+                               scaled ? dscale : nullptr, st));
     if ((rc = hh_factor(h, w, m, n))) return rc;
     // A grid barrier of the panel kernel that did not complete (some panel
     // workgroups could not start beside other work on the device), or R
@@ -878,7 +896,7 @@ int gesvd_qr(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, dou
     bool aborted = false, singular = false;
     bool nonfinite = false;
     if ((rc = qr_check(h, w, m, n, &aborted, &singular, &nonfinite))) return rc;
-    if (!aborted && singular) {
+    if (!aborted && singular && !scaled) {
         bool fallback = false;
         rc = gesvd_rank_deficient(h, w, m, n, A, lda, S, V, ldv, o, info, &fallback, t0);
         if (!fallback) return rc;
@@ -889,8 +907,8 @@ int gesvd_qr(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, dou
         return solve(h, m, n, A, lda, S, V, ldv, n, od, info, false, nullptr);
     }
 
-    // Jacobi on X = R^T: X V_x = U_x Sigma
-    HIP_TRY(launch_r_transpose(w.W, m, n, w.X, n, st));
+    // Jacobi on X = R^T (scaled: (R~ D)^T): X V_x = U_x Sigma
+    HIP_TRY(launch_r_transpose(w.W, m, n, w.X, n, st, scaled ? dscale : nullptr));
     jsvd_opts oj = o;
     oj.want_v = 1;
     oj.qr = 1;
@@ -1137,14 +1155,14 @@ int jsvd_gesvd(jsvd_handle_t h, int64_t m, int64_t n, double *A, int64_t lda, do
     if (o.want_v && ldv < n) return -8;
     if (hipSetDevice(h->device) != hipSuccess) return JSVD_HIP_ERROR;
     bool qr = wants_qr(h, o, m, n);
+    bool bad = false;
     if (qr && o.scaled != 1) {
-        // the Householder norms of the preprocessing are not scaled: a badly
-        // scaled G goes to the scaled Jacobi method directly
-        bool bad = o.scaled == 2;
-        if (!bad && (rc = column_exponents(h, m, n, A, lda, &bad))) return rc;
-        qr = !bad;
+        // a badly scaled G takes the QR with its columns scaled by powers of
+        // two (gesvd_qr)
+        if ((rc = column_exponents(h, m, n, A, lda, o.scaled == 0 ? &bad : nullptr))) return rc;
+        bad = bad || o.scaled == 2;
     }
-    if (qr) return gesvd_qr(h, m, n, A, lda, S, V, ldv, o, info);
+    if (qr) return gesvd_qr(h, m, n, A, lda, S, V, ldv, o, info, bad);
     return solve(h, m, n, A, lda, S, V, ldv, n, o, info, false, nullptr);
 }
 

@@ -196,8 +196,11 @@ hipError_t launch_qr_panel(const QrPanelArgs &a, hipStream_t s);
 hipError_t launch_qr_t(const double *Y, const double *tau, int nb, double *T, hipStream_t s);
 hipError_t launch_sum_parts(const double *parts, int np, int64_t count, double *out,
                             hipStream_t s);
+// X = the transpose of W's upper triangle; colscale (may be null): column i
+// of W multiplied by colscale[i] on the way (exact powers of two).
 hipError_t launch_r_transpose(const double *W, int64_t ldw, int64_t n, double *X, int64_t ldx,
-                              hipStream_t s);
+                              hipStream_t s, const double *colscale = nullptr);
+hipError_t launch_pow2(const int *ex, int64_t n, double *out, hipStream_t s);
 hipError_t launch_qr_extract_v(const double *W, int64_t ldw, int64_t m, int64_t j, int nb,
                                double *Vp, int64_t ldvp, hipStream_t s);
 hipError_t launch_embed(const double *X, int64_t ldx, int64_t n, double *B, int64_t ldb,

@@ -226,11 +226,20 @@ __global__ void sum_parts_kernel(const double *parts, int np, int64_t count, dou
 
 // X (n x n, ld ldx) = R^T, R the upper triangle of W's first n rows.
 __global__ void r_transpose_kernel(const double *W, int64_t ldw, int64_t n, double *X,
-                                   int64_t ldx) {
+                                   int64_t ldx, const double *colscale) {
     const int64_t c = blockIdx.y;  // column of X = row of R
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        X[i + c * ldx] = (i >= c) ? W[c + i * ldw] : 0.0;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = (i >= c) ? W[c + i * ldw] : 0.0;
+        X[i + c * ldx] = colscale ? v * colscale[i] : v;
+    }
+}
+
+// out[c] = 2^ex[c] (exact)
+__global__ void pow2_kernel(const int *ex, int64_t n, double *out) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (int64_t)gridDim.x * blockDim.x)
+        out[c] = ldexp(1.0, ex[c]);
 }
 
 // Explicit V of the panel at column j (rows j .. m-1 of W; unit diagonal).
@@ -615,10 +624,16 @@ hipError_t launch_sum_parts(const double *parts, int np, int64_t count, double *
 }
 
 hipError_t launch_r_transpose(const double *W, int64_t ldw, int64_t n, double *X, int64_t ldx,
-                              hipStream_t s) {
+                              hipStream_t s, const double *colscale) {
     const int64_t bx = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16));
     hipLaunchKernelGGL(r_transpose_kernel, dim3((unsigned)bx, (unsigned)n), dim3(256), 0, s, W,
-                       ldw, n, X, ldx);
+                       ldw, n, X, ldx, colscale);
+    return hipGetLastError();
+}
+
+hipError_t launch_pow2(const int *ex, int64_t n, double *out, hipStream_t s) {
+    const int64_t bx = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024));
+    hipLaunchKernelGGL(pow2_kernel, dim3((unsigned)bx), dim3(256), 0, s, ex, n, out);
     return hipGetLastError();
 }
 

@@ -154,15 +154,38 @@ def test_column_groups_far_apart(case, mode):
     assert np.max(col) <= 1e-13 * n
 
 
-def test_tall_badly_scaled_skips_qr():
-    """m >= 2n would take the QR preprocessing; badly scaled input goes to
-    the scaled Jacobi method instead."""
+@pytest.mark.parametrize("k", [-650, 700])
+def test_tall_badly_scaled_takes_scaled_qr(k):
+    """m >= 2n takes the QR preprocessing also when G is badly scaled: the
+    columns are scaled by the powers of two of their norms before the
+    Householder QR (the norms by DRDSSQ), and the Jacobi method runs on
+    (R~ D)^T in the scaled mode."""
+    _say(f"tall 2^{k} B through the scaled QR")
     B = inputs.gaussian(400, 96, inputs.rng(950))
-    U, S, V, info = _gesvd(np.ldexp(B, -650), block_w=16)
-    assert info["status"] == 0 and info["preprocessed"] == 0 and info["scaled"] == 1
+    U, S, V, info = _gesvd(np.ldexp(B, k), block_w=16)
+    assert info["status"] == 0 and info["preprocessed"] == 1 and info["scaled"] == 1, info
     ref = oracle.gesvj(B)
-    assert np.max(np.abs(np.ldexp(S, 650) - ref["S"]) / ref["S"]) <= 1e-12
+    assert np.max(np.abs(np.ldexp(S, -k) - ref["S"]) / ref["S"]) <= 1e-12
     assert _orth(U, 96) <= 1e-13 * 96 and _orth(V, 96) <= 1e-13 * 96
+    R = np.ldexp(B, k) - (U * S) @ V.T
+    assert np.max(_colnorms(R) / _colnorms(np.ldexp(B, k))) <= 1e-13 * 96
+
+
+def test_tall_column_groups_far_apart_through_qr():
+    """A tall G with column groups 2^500 B1 and 2^-400 B2 (ratio 2^900):
+    the scaled QR keeps both groups' sigma to relative accuracy, and so does
+    the scaled Jacobi method without the QR."""
+    _say("tall column groups through the scaled QR")
+    A, s1, s2 = _groups(600, 60, 50, 500, -400, 960)
+    n1 = 60
+    U, S, V, info = _gesvd(A, block_w=16)
+    assert info["status"] == 0 and info["preprocessed"] == 1, info
+    assert np.max(np.abs(S[:n1] - s1) / s1) <= 1e-12
+    assert np.max(np.abs(S[n1:] - s2) / s2) <= 1e-12
+    assert _orth(U, 110) <= 1e-13 * 110 and _orth(V, 110) <= 1e-13 * 110
+    U2, S2, V2, info2 = _gesvd(A, block_w=16, qr="off")
+    assert info2["preprocessed"] == 0 and info2["scaled"] == 1
+    assert np.max(np.abs(S2 - S) / S) <= 1e-12
 
 
 @pytest.mark.parametrize("k", [640, -640])
