@@ -34,7 +34,7 @@ import sys
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 COMMON = ["jsvd_device.h", "jsvd_internal.h"]
 KERNEL_SOURCES = {"gram": ["jsvd_gram.hip"],
-                  "inner": ["jsvd_inner.hip", "jsvd_rows.h", "jsvd_blocked.h"],
+                  "inner": ["jsvd_inner.hip", "jsvd_rows.h", "jsvd_blocked.h", "jsvd_qrpair.h"],
                   "update": ["jsvd_update.hip", "jsvd_rows.h"]}
 PSTEP = re.compile(r"\b(gram|inner|update)_kernel<(\d+)(?:, (?:true|false))*>")
 
