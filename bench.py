@@ -30,8 +30,8 @@ RIDGE = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--block-w", type=int, default=0)
     ap.add_argument("--strategy", default="rrev")
@@ -370,6 +370,50 @@ def measure_tall(steps, warmup):
                              np.abs(s - sig)[sig >= 1e-3] / sig[sig >= 1e-3]))}}
 
 
+def measure_small_and_hsvd(steps, warmup):
+    """Two more single-matrix workloads, seconds per solve through the
+    binding (input restored from a device copy each step, included):
+    small_256: 256 x 256, sigma log-spaced 1 .. 1e-6, Haar factors (seed 1),
+    w = 16, Rrev; hsvd_2048: the hyperbolic SVD of a 2048 x 2048 N(0,1)
+    matrix (seed 4) with J = diag(+1 x 1280, -1 x 768)."""
+    import numpy as np
+    import torch
+
+    import paper_1401_2720_amd as jsvd
+    from paper_1401_2720_amd import inputs
+    out = {}
+    A = torch.from_numpy(inputs.small_graded()).cuda()
+    sig = inputs.logspaced(256, -6.0)
+
+    def small():
+        return jsvd.gesvd(A, block_w=16, strategy="rrev")
+
+    G, J = inputs.hyperbolic_gaussian()
+    Gd = torch.from_numpy(G).cuda()
+
+    def hyp():
+        return jsvd.hsvd(Gd, J)
+
+    for name, fn in (("small_256", small), ("hsvd_2048", hyp)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = fn()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        info = r[-1]
+        rec = {"s": sec, "sweeps": info["sweeps"], "block_w": info["block_w"],
+               "status": info["status"]}
+        if name == "small_256":
+            s = r[1].cpu().numpy()
+            rec["max_abs_sigma_err"] = float(np.max(np.abs(s - sig)))
+        out[name] = rec
+    del np
+    return out
+
+
 def bench_tall(args):
     r = measure_tall(args.steps, args.warmup)
     out = {"metric": "FP64 SVD time (s) at 8192x2048", "value": r["s"], "unit": "s",
@@ -554,6 +598,10 @@ def main():
         r["avg_launch_us"] = avg[name] * 1e3
         r["launches"] = kt[name][1]
         r["traffic"] = measured_traffic(name, w)
+        # HBM rate from the counted bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+        # calibrated) over this run's average launch time
+        r["traffic_gbs"] = (r["traffic"] / (avg[name] * 1e-3) / 1e9
+                            if r["traffic"] is not None else None)
         r["algorithmic_per_launch"] = {k: v for k, v in per_launch.items() if k.startswith(name)}
         rooflines[name] = r
     dominant = max(kt, key=lambda k: kt[k][0])
@@ -595,10 +643,13 @@ def main():
         bat = measure_batched(steps=5, warmup=1, cpu_seconds=0)
         bwd = measure_backward(steps=3, warmup=1)
         tall = measure_tall(steps=3, warmup=1)
+        more = measure_small_and_hsvd(steps=5, warmup=2)
         forms = {"batched_svds_per_s": bat["svds_per_s"], "batched": bat,
                  "differentiable_forward_backward_s": bwd["forward_backward_s"],
                  "differentiable": bwd["parts"],
-                 "tall_8192x2048_s": tall["s"], "tall_8192x2048": tall}
+                 "tall_8192x2048_s": tall["s"], "tall_8192x2048": tall,
+                 "small_256_s": more["small_256"]["s"], "small_256": more["small_256"],
+                 "hsvd_2048_s": more["hsvd_2048"]["s"], "hsvd_2048": more["hsvd_2048"]}
 
     out = {
         "metric": "FP64 SVD time (s) at n=4096",
