@@ -11,9 +11,12 @@ namespace jsvd {
 namespace {
 
 // NW waves take 16-row slices of rows [r0, r1) and compute
-// (X V')^T = V'^T X^T tile by tile: V' (staged transposed in LDS, vs holds
-// at least BW * BW doubles) supplies the A operand, a slice of X the B
-// operand (lane l reads row l%16 of local column 4*ks + l/16), and each
+// (X V')^T = V'^T X^T tile by tile: V' (staged by rows in LDS, vs holds at
+// least BW * BW doubles: row i at vs + i BW, its column j at position
+// j ^ (i mod 16), so that the staging stores of 16 consecutive rows of one
+// column fall in 16 distinct banks, and the MFMA operand loads of 16
+// consecutive columns of one row too) supplies the A operand, a slice of X
+// the B operand (lane l reads row l%16 of local column 4*ks + l/16), and each
 // result column is written back as 16 consecutive rows.  All loads of a
 // slice precede its stores, so the update is in place.  The pair's columns
 // are w consecutive columns of block P, then w of block Q; local columns
@@ -30,7 +33,10 @@ __device__ __forceinline__ void update_rows(double *X, int64_t ldx, int64_t r0, 
     constexpr int KS = BW / 4, JT = BW / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i16 = lane & 15, grp = lane >> 4;
-    for (int e = threadIdx.x; e < BW * BW; e += 64 * NW) vs[(e % BW) * BW + e / BW] = vpr[e];
+    for (int e = threadIdx.x; e < BW * BW; e += 64 * NW) {
+        const int i = e % BW, j = e / BW;
+        vs[i * BW + (j ^ (i & 15))] = vpr[e];
+    }
     __syncthreads();
 
     // Column addresses are recomputed per slice rather than kept in
@@ -63,7 +69,8 @@ __device__ __forceinline__ void update_rows(double *X, int64_t ldx, int64_t r0, 
             for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
                 for (int jb = 0; jb < JB; ++jb)
-                    acc[jb] = mfma16(vs[(4 * ks + grp) * BW + (j0 + jb) * 16 + i16], b[ks], acc[jb]);
+                    acc[jb] = mfma16(vs[(4 * ks + grp) * BW + (j0 + jb) * 16 + (i16 ^ ((4 * ks + grp) & 15))],
+                                     b[ks], acc[jb]);
 #pragma unroll
             for (int jb = 0; jb < JB; ++jb)
 #pragma unroll

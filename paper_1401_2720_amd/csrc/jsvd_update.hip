@@ -13,7 +13,7 @@ namespace {
 // after the last p-step.
 template <int BW>
 __global__ __launch_bounds__(256) void update_kernel(StepArgs a) {
-    __shared__ double vs[BW * BW];  // V'_pq transposed: vs[k * BW + j] = V'(k, j)
+    __shared__ double vs[BW * BW];  // V'_pq by rows, in the layout update_rows uses
     const int pair = blockIdx.y;
     if (a.pair_rot[pair] == 0) return;
     int chunk = blockIdx.x;
