@@ -12,15 +12,17 @@ namespace {
 // tile t, loaded as 16-byte vectors.  The contraction index of the MFMA
 // runs over those rows, which is free to choose because both operands are
 // the same slice.  Only the tiles on and above the diagonal of the
-// symmetric H are formed.  Four rows per lane (not eight) keep the kernel
-// within 128 registers, four waves per SIMD; a pair whose columns all exist
-// loads without per-column selects (measured at n = 4096: 40.3 -> 35.8 us
-// per launch).
+// symmetric H are formed.  Four rows per lane (not eight); a pair whose
+// columns all exist loads without per-column selects (measured at n = 4096:
+// 40.3 -> 35.8 us per launch).  PF: the next slice is loaded while the
+// current one is multiplied (two register buffers, two waves per SIMD),
+// taken when the grid has at most two workgroups per CU (36.2 -> 35.0 us at
+// n = 4096); otherwise one buffer and four waves per SIMD.
 typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
 
 // SC: scaled mode, column c multiplied by 2^-e_c (exact) as it is loaded.
-template <int BW, bool SC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gram_kernel(StepArgs a) {
+template <int BW, bool SC, bool PF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PF ? 2 : 4))) void gram_kernel(StepArgs a) {
     constexpr int T = BW / 16;
     constexpr int NT = T * (T + 1) / 2;
     constexpr int S = 4;
@@ -61,8 +63,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
     const int64_t r1 = min(a.m, r0 + (int64_t)a.rows_per_split);
     // every column of the pair present: loads without selects
     const bool allv = (int64_t)(pq.y + 1) * a.w <= a.n;
-    for (int64_t base = r0 + wave * SLICE; base < r1; base += 4 * SLICE) {
-        double x[T][S];
+    auto load = [&](int64_t base, double (&x)[T][S]) {
         const int64_t rb = base + grp * S;
         if (allv && base + SLICE <= r1) {
 #pragma unroll
@@ -90,6 +91,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
                 for (int s = 0; s < S; ++s)
                     x[t][s] = (valid[t] && rb + s < r1) ? col[t][rb + s] : 0.0;
         }
+    };
+    auto product = [&](double (&x)[T][S]) {
         if constexpr (SC) {
 #pragma unroll
             for (int t = 0; t < T; ++t)
@@ -103,6 +106,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
             for (int tb = ta; tb < T; ++tb, ++k)
 #pragma unroll
                 for (int s = 0; s < S; ++s) acc[k] = mfma16(x[ta][s], x[tb][s], acc[k]);
+    };
+    if constexpr (PF) {
+        // software pipeline over the wave's slices: the loads of the next
+        // slice are issued before the products of the current one; the
+        // slices are multiplied in the same order as below, so the sums are
+        // the same
+        double xa[T][S], xb[T][S];
+        int64_t base = r0 + wave * SLICE;
+        if (base < r1) load(base, xa);
+        while (base < r1) {
+            int64_t nb = base + 4 * SLICE;
+            if (nb < r1) load(nb, xb);
+            product(xa);
+            base = nb;
+            if (base >= r1) break;
+            nb = base + 4 * SLICE;
+            if (nb < r1) load(nb, xa);
+            product(xb);
+            base = nb;
+        }
+    } else {
+        for (int64_t base = r0 + wave * SLICE; base < r1; base += 4 * SLICE) {
+            double x[T][S];
+            load(base, x);
+            product(x);
+        }
     }
 
     // Fixed-order sum over the four waves: ((w0 + w1) + w2) + w3.
@@ -255,14 +284,18 @@ hipError_t launch_gram(int bw, const StepArgs &a, hipStream_t s) {
     dim3 grid(a.splits, a.npairs);
     if (a.colexp) {
         if (bw == 32)
-            hipLaunchKernelGGL((gram_kernel<32, true>), grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL((gram_kernel<32, true, false>), grid, dim3(256), 0, s, a);
+        else if (a.gram_pf)
+            hipLaunchKernelGGL((gram_kernel<64, true, true>), grid, dim3(256), 0, s, a);
         else
-            hipLaunchKernelGGL((gram_kernel<64, true>), grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL((gram_kernel<64, true, false>), grid, dim3(256), 0, s, a);
     } else {
         if (bw == 32)
-            hipLaunchKernelGGL((gram_kernel<32, false>), grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL((gram_kernel<32, false, false>), grid, dim3(256), 0, s, a);
+        else if (a.gram_pf)
+            hipLaunchKernelGGL((gram_kernel<64, false, true>), grid, dim3(256), 0, s, a);
         else
-            hipLaunchKernelGGL((gram_kernel<64, false>), grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL((gram_kernel<64, false, false>), grid, dim3(256), 0, s, a);
     }
     return hipGetLastError();
 }

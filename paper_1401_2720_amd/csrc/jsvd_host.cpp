@@ -384,6 +384,7 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     a.npairs = npairs;
     a.splits = splits;
     a.rows_per_split = (int)rps;
+    a.gram_pf = (int64_t)splits * npairs <= 2 * (int64_t)h->cu_count ? 1 : 0;
     a.hpart = reinterpret_cast<double *>(ws + L.hpart);
     double *const vprime0 = reinterpret_cast<double *>(ws + L.vprime);
     int *const pair_rot0 = reinterpret_cast<int *>(ws + L.pair_rot);

@@ -76,6 +76,9 @@ struct StepArgs {
     // factors of [G_p G_q] (qrfac kernel) instead of partial Gram matrices,
     // and the inner kernel folds them together in place of the Cholesky
     int qrf;
+    // Gram kernel with the two-buffer software pipeline (the grid has at
+    // most two workgroups per CU)
+    int gram_pf;
     const int *btbl_order;
     const int64_t *btbl_off;
     const unsigned char *btbls;
