@@ -30,31 +30,35 @@ constexpr int kRpt = 2;            // panel rows per thread, at most
 
 // Grid-wide barrier among resident workgroups: monotonic arrival counter,
 // bounded spin (a barrier that does not complete within the bound sets the
-// abort flag and lets every workgroup leave).
+// abort flag and lets every workgroup leave).  The workgroup barrier first
+// completes the stores of all its threads; thread 0's release increment
+// then publishes them at device scope (one write-back of the XCD's L2), its
+// spin reads the counter without ordering, and one device-scope acquire
+// after the spin (one invalidation) makes the other workgroups' stores
+// visible to the whole workgroup past the second workgroup barrier.
 __device__ __forceinline__ bool grid_sync(unsigned *bar, unsigned target, int *abort_flag) {
-    __threadfence();
     __syncthreads();
     __shared__ int s_ok;
     if (threadIdx.x == 0) {
         __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         int ok = 1;
         unsigned spins = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                 ok = 0;
                 break;
             }
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_s_sleep(1);
             if (++spins > (1u << 24)) {
                 __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ok = 0;
                 break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         s_ok = ok;
     }
     __syncthreads();
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
     return s_ok != 0;
 }
 
@@ -91,6 +95,7 @@ __global__ __launch_bounds__(kQT, 1) void qr_panel_kernel(QrPanelArgs a) {
     __shared__ double wsum[kNb];
     __shared__ double gsum[kNb];
     __shared__ double s_prow[kNb];
+    __shared__ double s_w[kNb];   // v^T a_c of the current column's reflector
     const int wg = blockIdx.x, t = threadIdx.x;
     const int64_t rows = a.m - a.j;                       // panel rows j .. m-1
     const int64_t chunk = (rows + a.nwg - 1) / a.nwg;     // rows per workgroup
@@ -143,10 +148,21 @@ __global__ __launch_bounds__(kQT, 1) void qr_panel_kernel(QrPanelArgs a) {
         wg_sum(ps, nb, red, seg, wsum);
         if (t < nb) a.partials[((size_t)par * a.nwg + wg) * kNb + t] = wsum[t];
         if (!grid_sync(a.bar, (unsigned)(a.nwg * (k + 1)), a.abort_flag)) return;
-        // all workgroups: totals in workgroup order, the pivot row, the reflector
+        // all workgroups: totals in workgroup order (the loads of eight
+        // partials issued together, then added in order), the pivot row,
+        // the reflector
         if (t < nb) {
+            const double *pp = a.partials + (size_t)par * a.nwg * kNb + t;
             double sum = 0.0;
-            for (int w = 0; w < a.nwg; ++w) sum += a.partials[((size_t)par * a.nwg + w) * kNb + t];
+            int w = 0;
+            for (; w + 8 <= a.nwg; w += 8) {
+                double v8[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v8[u] = pp[(size_t)(w + u) * kNb];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) sum += v8[u];
+            }
+            for (; w < a.nwg; ++w) sum += pp[(size_t)w * kNb];
             gsum[t] = sum;
             s_prow[t] = a.prow[par * kNb + t];
         }
@@ -159,6 +175,8 @@ __global__ __launch_bounds__(kQT, 1) void qr_panel_kernel(QrPanelArgs a) {
             tau = (beta - alpha) / beta;
             scal = 1.0 / (alpha - beta);
         }
+        if (t < nb) s_w[t] = fma(scal, gsum[t], s_prow[t]);  // v^T a_c
+        __syncthreads();
         if (wg == 0 && t == 0) a.tau[a.j + k] = tau;
         // rows: v = e_pivot + scal * x(below); a_c -= tau v (v^T a_c), c > k
 #pragma unroll
@@ -168,15 +186,12 @@ __global__ __launch_bounds__(kQT, 1) void qr_panel_kernel(QrPanelArgs a) {
                 const double v = piv ? 1.0 : xk[q] * scal;
 #pragma unroll
                 for (int c = 0; c < kNb; ++c) {
-                    if (c > k && c < nb && tau != 0.0) {
-                        const double wc = fma(scal, gsum[c], s_prow[c]);  // v^T a_c
-                        x[q][c] = fma(-tau * v, wc, x[q][c]);
-                    }
+                    if (c > k && c < nb && tau != 0.0) x[q][c] = fma(-tau * v, s_w[c], x[q][c]);
                     if (c == k) x[q][c] = piv ? beta : v;
                 }
             }
         }
-        __syncthreads();  // gsum / s_prow are rewritten by the next column
+        __syncthreads();  // gsum, s_prow and s_w are rewritten by the next column
     }
     // write back: R above and on the diagonal, v below; explicit V of the panel
 #pragma unroll
