@@ -619,7 +619,7 @@ hipError_t launch_qr_reset(unsigned *bar, int *abort_flag, hipStream_t s) {
 // that the nwg <= 64 workgroups of 68 kB LDS can all be resident
 // (qr_panel_resident); work of other streams or processes on the device can
 // still keep some from starting, and then a barrier ends at its spin bound
-// (about 1 s) instead of hanging.
+// (2^24 polls of the counter) instead of hanging.
 hipError_t launch_qr_panel(const QrPanelArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(qr_reset_kernel, dim3(1), dim3(64), 0, s, a.bar, (int *)nullptr);
     hipLaunchKernelGGL(qr_panel_kernel, dim3((unsigned)a.nwg), dim3(kQT), 0, s, a);
