@@ -65,15 +65,19 @@ __device__ __forceinline__ bool grid_sync(unsigned *bar, unsigned target, int *a
 // Sums of the kNb values v[] over the workgroup's 256 threads, in a fixed
 // order: red[c][t] <- v[c] of thread t; 8 segments of 32 threads summed
 // sequentially, then the 8 segment sums.  Result in out[c] for c < nv.
-__device__ __forceinline__ void wg_sum(const double (&v)[kNb], int nv, double (*red)[kQT + 1], double (*seg)[8],
+// Thread t sums segment t / 32 of column t mod 32, so that the 16 lanes of
+// a wave that read LDS together read 16 columns (distinct banks), and seg
+// is padded to 9 for the same reason.
+__device__ __forceinline__ void wg_sum(const double (&v)[kNb], int nv, double (*red)[kQT + 1], double (*seg)[9],
                        double *out) {
+    static_assert(kNb == 32 && kQT == 256, "32 columns, 8 segments of 32 threads");
     const int t = threadIdx.x;
 #pragma unroll
     for (int c = 0; c < kNb; ++c)
         if (c < nv) red[c][t] = v[c];
     __syncthreads();
     {
-        const int c = t >> 3, sg = t & 7;
+        const int c = t & 31, sg = t >> 5;
         if (c < nv) {
             double s = 0.0;
             for (int i = 0; i < 32; ++i) s += red[c][sg * 32 + i];
@@ -91,7 +95,7 @@ __device__ __forceinline__ void wg_sum(const double (&v)[kNb], int nv, double (*
 
 __global__ __launch_bounds__(kQT, 1) void qr_panel_kernel(QrPanelArgs a) {
     __shared__ double red[kNb][kQT + 1];
-    __shared__ double seg[kNb][8];
+    __shared__ double seg[kNb][9];
     __shared__ double wsum[kNb];
     __shared__ double gsum[kNb];
     __shared__ double s_prow[kNb];
@@ -129,6 +133,7 @@ __global__ __launch_bounds__(kQT, 1) void qr_panel_kernel(QrPanelArgs a) {
             for (int c = 0; c < kNb; ++c) xk[q] = (c == k) ? x[q][c] : xk[q];
         }
         // partial sums over own rows below the pivot: column k with columns k .. nb-1
+        // (also formed, and not used, for the columns left of k)
         double ps[kNb];
 #pragma unroll
         for (int c = 0; c < kNb; ++c) ps[c] = 0.0;
@@ -136,8 +141,7 @@ __global__ __launch_bounds__(kQT, 1) void qr_panel_kernel(QrPanelArgs a) {
         for (int q = 0; q < kRpt; ++q) {
             if (rr[q] > pr && rr[q] < r_end) {
 #pragma unroll
-                for (int c = 0; c < kNb; ++c)
-                    if (c >= k) ps[c] = fma(xk[q], x[q][c], ps[c]);
+                for (int c = 0; c < kNb; ++c) ps[c] = fma(xk[q], x[q][c], ps[c]);
             }
             if (rr[q] == pr && rr[q] < r_end) {
 #pragma unroll
