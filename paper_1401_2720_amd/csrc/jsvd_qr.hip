@@ -152,23 +152,24 @@ __global__ __launch_bounds__(kQT, 1) void qr_panel_kernel(QrPanelArgs a) {
         wg_sum(ps, nb, red, seg, wsum);
         if (t < nb) a.partials[((size_t)par * a.nwg + wg) * kNb + t] = wsum[t];
         if (!grid_sync(a.bar, (unsigned)(a.nwg * (k + 1)), a.abort_flag)) return;
-        // all workgroups: totals in workgroup order (the loads of eight
-        // partials issued together, then added in order), the pivot row,
-        // the reflector
-        if (t < nb) {
-            const double *pp = a.partials + (size_t)par * a.nwg * kNb + t;
-            double sum = 0.0;
-            int w = 0;
-            for (; w + 8 <= a.nwg; w += 8) {
-                double v8[8];
+        // all workgroups: totals in workgroup order, the pivot row, the
+        // reflector.  The nwg x nb partial sums (nwg <= 64) and the pivot row
+        // are loaded by all threads at once into LDS (one memory round trip),
+        // then each column's partials are added in workgroup order.
+        {
+            const int c = t & 31;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v8[u] = pp[(size_t)(w + u) * kNb];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) sum += v8[u];
+            for (int i = 0; i < 8; ++i) {
+                const int w = (t >> 5) + 8 * i;
+                if (c < nb && w < a.nwg) red[c][w] = a.partials[((size_t)par * a.nwg + w) * kNb + c];
             }
-            for (; w < a.nwg; ++w) sum += pp[(size_t)w * kNb];
+            if (t < nb) s_prow[t] = a.prow[par * kNb + t];
+        }
+        __syncthreads();
+        if (t < nb) {
+            double sum = 0.0;
+            for (int w = 0; w < a.nwg; ++w) sum += red[t][w];
             gsum[t] = sum;
-            s_prow[t] = a.prow[par * kNb + t];
         }
         __syncthreads();
         const double alpha = s_prow[k];
@@ -179,18 +180,21 @@ __global__ __launch_bounds__(kQT, 1) void qr_panel_kernel(QrPanelArgs a) {
             tau = (beta - alpha) / beta;
             scal = 1.0 / (alpha - beta);
         }
-        if (t < nb) s_w[t] = fma(scal, gsum[t], s_prow[t]);  // v^T a_c
+        // v^T a_c for the columns the reflection changes, zero for the others
+        if (t < kNb) s_w[t] = (t > k && t < nb && tau != 0.0) ? fma(scal, gsum[t], s_prow[t]) : 0.0;
         __syncthreads();
         if (wg == 0 && t == 0) a.tau[a.j + k] = tau;
         // rows: v = e_pivot + scal * x(below); a_c -= tau v (v^T a_c), c > k
+        // (without a branch: the other columns get tau v times zero added)
 #pragma unroll
         for (int q = 0; q < kRpt; ++q) {
             if (rr[q] >= pr && rr[q] < r_end) {
                 const bool piv = rr[q] == pr;
                 const double v = piv ? 1.0 : xk[q] * scal;
+                const double mtv = -tau * v;
 #pragma unroll
                 for (int c = 0; c < kNb; ++c) {
-                    if (c > k && c < nb && tau != 0.0) x[q][c] = fma(-tau * v, s_w[c], x[q][c]);
+                    x[q][c] = fma(mtv, s_w[c], x[q][c]);
                     if (c == k) x[q][c] = piv ? beta : v;
                 }
             }
@@ -625,6 +629,9 @@ hipError_t launch_qr_reset(unsigned *bar, int *abort_flag, hipStream_t s) {
 // still keep some from starting, and then a barrier ends at its spin bound
 // (2^24 polls of the counter) instead of hanging.
 hipError_t launch_qr_panel(const QrPanelArgs &a, hipStream_t s) {
+    // the kernel gathers at most 64 workgroups' partial sums per column
+    // (m <= 32768 on every path that factors a panel)
+    if (a.nwg < 1 || a.nwg > 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL(qr_reset_kernel, dim3(1), dim3(64), 0, s, a.bar, (int *)nullptr);
     hipLaunchKernelGGL(qr_panel_kernel, dim3((unsigned)a.nwg), dim3(kQT), 0, s, a);
     return hipGetLastError();
