@@ -129,6 +129,30 @@ def test_square_gaussian_4096_sigma_against_oracle():
     print(f"  max rel sigma err {rel:.2e}", flush=True)
 
 
+def test_square_gaussian_4096_one_buffer_gram_against_oracle():
+    """The same with 16 Gram row splits (a tuning table with 1024 Gram
+    workgroups per launch): 1024 workgroups are more than two per CU, so the
+    Gram kernel takes its one-buffer loop instead of the two-buffer pipeline
+    of the default 8 splits, and the inner kernel sums 16 partials."""
+    torch = _torch()
+    import paper_1401_2720_amd as jsvd
+    from paper_1401_2720_amd import _binding as B
+    print("4096 x 4096 N(0,1), 16 Gram splits: sigma against the oracle", flush=True)
+    ref = _golden("sigma_gaussian4096_seed2.txt")
+    A = torch.from_numpy(inputs.square_gaussian()).cuda()
+    table = {"n_upper": [8192], "block_w": [32], "gram_wg": [1024], "update_wg": [1024],
+             "batch_g_groups": 0, "batch_block_min_n": 0}
+    B.set_tuning(0, table)
+    try:
+        _, S, _, info = jsvd.gesvd(A)
+        torch.cuda.synchronize()
+    finally:
+        B.set_tuning(0, B.load_tuning(0))
+    assert info["status"] == 0 and info["block_w"] == 32
+    rel = _sigma_gate(S.cpu().numpy(), ref)
+    print(f"  max rel sigma err {rel:.2e}", flush=True)
+
+
 def test_hyperbolic_2048_sigma_against_oracle():
     torch = _torch()
     import paper_1401_2720_amd as jsvd
