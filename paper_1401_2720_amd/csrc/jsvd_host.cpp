@@ -532,9 +532,15 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
 // G P = Q [R; 0] (eq. (2.1), column presorting by norm in place of column
 // pivoting), the Jacobi method on X = R^T, then U = Q [V_x; 0], V = P U_x.
 int gemm_splitk(const double *A, int64_t lda, const double *B, int64_t ldb, int M, int N,
-                int64_t K, double *parts, double *out, hipStream_t st) {
-    // out (M x N, ld M) = A^T B with A K x M and B K x N, K cut into slices
-    const int np = (int)std::max<int64_t>(1, std::min<int64_t>(32, K / 512));
+                int64_t K, double *parts, int64_t parts_cap, double *out, hipStream_t st) {
+    // out (M x N, ld M) = A^T B with A K x M and B K x N, K cut into slices:
+    // enough slices for about 1024 workgroups (four per CU) with 64 columns
+    // of B each, at least 16, slices of at least 64 rows, and as many as the
+    // partial buffer (parts_cap doubles) holds
+    const int64_t col_blocks = (N + 63) / 64;
+    int64_t np = std::max<int64_t>(16, (1024 + col_blocks - 1) / col_blocks);
+    np = std::min<int64_t>({np, 256, std::max<int64_t>(1, K / 64),
+                            std::max<int64_t>(1, parts_cap / ((int64_t)M * N))});
     const int64_t ks = align_up((size_t)((K + np - 1) / np), 16);
     const int used = (int)((K + ks - 1) / ks);
     GemmArgs g;
@@ -571,6 +577,7 @@ int gemm_plain(bool ta, const double *A, int64_t lda, const double *B, int64_t l
 struct QrLayout {
     size_t oW, oX, oVx, oVp, oT, oTau, oParts, oY1, oY2, oPart, oProw, oNrm, oScl, oPerm, oBar,
         total;
+    int64_t parts_cap;
 };
 
 QrLayout qr_plan(int64_t m, int64_t n, int64_t ncols = 0) {
@@ -586,7 +593,8 @@ QrLayout qr_plan(int64_t m, int64_t n, int64_t ncols = 0) {
     q.oVp = take((size_t)m * NB * 8);
     q.oT = take((size_t)npan * NB * NB * 8);
     q.oTau = take((size_t)n * 8);
-    q.oParts = take((size_t)32 * NB * nc * 8);
+    q.parts_cap = (int64_t)32 * NB * nc;
+    q.oParts = take((size_t)q.parts_cap * 8);
     q.oY1 = take((size_t)NB * nc * 8);
     q.oY2 = take((size_t)NB * nc * 8);
     q.oPart = take((size_t)2 * 64 * NB * 8);
@@ -604,6 +612,7 @@ struct QrWork {
     double *W, *X, *Vx, *Vp, *T, *tau, *parts, *Y1, *Y2, *part, *prow, *nrm, *scl, *d_range;
     int *perm, *abort_flag;
     unsigned *bar;
+    int64_t parts_cap;  // doubles in parts (split-K partial products)
 };
 
 int qr_workspace(jsvd_handle_s *h, const QrLayout &q, QrWork *w) {
@@ -624,6 +633,7 @@ int qr_workspace(jsvd_handle_s *h, const QrLayout &q, QrWork *w) {
     auto d = [&](size_t o) { return reinterpret_cast<double *>(ws + o); };
     w->W = d(q.oW); w->X = d(q.oX); w->Vx = d(q.oVx); w->Vp = d(q.oVp); w->T = d(q.oT);
     w->tau = d(q.oTau); w->parts = d(q.oParts); w->Y1 = d(q.oY1); w->Y2 = d(q.oY2);
+    w->parts_cap = q.parts_cap;
     w->part = d(q.oPart); w->prow = d(q.oProw); w->nrm = d(q.oNrm); w->scl = d(q.oScl);
     w->perm = reinterpret_cast<int *>(ws + q.oPerm);
     w->bar = reinterpret_cast<unsigned *>(ws + q.oBar);
@@ -652,14 +662,14 @@ int hh_factor(jsvd_handle_s *h, const QrWork &w, int64_t m, int64_t n) {
         qa.bar = w.bar; qa.abort_flag = w.abort_flag; qa.nwg = qr_panel_groups(rows);
         HIP_TRY(launch_qr_panel(qa, st));
         // T of the panel from V^T V
-        int rc = gemm_splitk(w.Vp, m, w.Vp, m, NB, NB, rows, w.parts, w.Y1, st);
+        int rc = gemm_splitk(w.Vp, m, w.Vp, m, NB, NB, rows, w.parts, w.parts_cap, w.Y1, st);
         if (rc) return rc;
         HIP_TRY(launch_qr_t(w.Y1, w.tau + j, nb, w.T + p * NB * NB, st));
         if (j + nb < n) {
             // trailing columns: C <- C - V T^T (V^T C)
             const int nc = (int)(n - j - nb);
             double *C = w.W + j + (j + nb) * m;
-            if ((rc = gemm_splitk(w.Vp, m, C, m, NB, nc, rows, w.parts, w.Y1, st))) return rc;
+            if ((rc = gemm_splitk(w.Vp, m, C, m, NB, nc, rows, w.parts, w.parts_cap, w.Y1, st))) return rc;
             if ((rc = gemm_plain(true, w.T + p * NB * NB, NB, w.Y1, NB, w.Y2, NB, NB, nc, NB, 1.0,
                                  0.0, st)))
                 return rc;
@@ -683,7 +693,7 @@ int hh_apply_q(jsvd_handle_s *h, const QrWork &w, int64_t m, int64_t n, double *
         const int64_t rows = m - j;
         HIP_TRY(launch_qr_extract_v(w.W, m, m, j, nb, w.Vp, m, st));
         double *Bj = B + j;
-        int rc = gemm_splitk(w.Vp, m, Bj, ldb, NB, (int)ncols, rows, w.parts, w.Y1, st);
+        int rc = gemm_splitk(w.Vp, m, Bj, ldb, NB, (int)ncols, rows, w.parts, w.parts_cap, w.Y1, st);
         if (rc) return rc;
         if ((rc = gemm_plain(false, w.T + p * NB * NB, NB, w.Y1, NB, w.Y2, NB, NB, (int)ncols, NB,
                              1.0, 0.0, st)))
@@ -706,7 +716,7 @@ int hh_build_t(jsvd_handle_s *h, const QrWork &w, int64_t m, int64_t n) {
         const int64_t j = p * NB;
         const int nb = (int)std::min<int64_t>(NB, n - j);
         HIP_TRY(launch_qr_extract_v(w.W, m, m, j, nb, w.Vp, m, st));
-        int rc = gemm_splitk(w.Vp, m, w.Vp, m, NB, NB, m - j, w.parts, w.Y1, st);
+        int rc = gemm_splitk(w.Vp, m, w.Vp, m, NB, NB, m - j, w.parts, w.parts_cap, w.Y1, st);
         if (rc) return rc;
         HIP_TRY(launch_qr_t(w.Y1, w.tau + j, nb, w.T + p * NB * NB, st));
     }
@@ -792,6 +802,7 @@ int gesvd_rank_deficient(jsvd_handle_s *h, const QrWork &w1, int64_t m, int64_t 
     QrWork w2{}, w3{};
     for (QrWork *q : {&w2, &w3}) {
         q->Vp = d(oVp); q->parts = d(oParts); q->Y1 = d(oY1); q->Y2 = d(oY2);
+        q->parts_cap = (int64_t)32 * NB * n;
         q->part = d(oPart); q->prow = d(oProw); q->bar = bar; q->abort_flag = abort_flag;
         q->d_range = d(oBar + 64);
     }

@@ -238,13 +238,28 @@ __global__ void qr_t_kernel(const double *Y, const double *tau, int nb, double *
     for (int e = t; e < kNb * kNb; e += blockDim.x) T[e] = Ts[e % kNb][e / kNb];
 }
 
-// out = sum of parts[0 .. np) (each count doubles, stride count), in order.
-__global__ void sum_parts_kernel(const double *parts, int np, int64_t count, double *out) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= count) return;
+// out = sum of parts[0 .. np) (each count doubles, stride count) in a fixed
+// order: the slices cut into 8 consecutive groups, each group summed in
+// order by its own thread, then the 8 group sums in order.  256 threads per
+// workgroup, 32 elements per workgroup.
+__global__ __launch_bounds__(256) void sum_parts_kernel(const double *parts, int np,
+                                                        int64_t count, double *out) {
+    __shared__ double gs[8][33];
+    const int t = threadIdx.x, l = t & 31, g = t >> 5;
+    const int64_t e = (int64_t)blockIdx.x * 32 + l;
+    const int per = (np + 7) / 8;
+    const int p0 = min(np, g * per), p1 = min(np, p0 + per);
     double s = 0.0;
-    for (int p = 0; p < np; ++p) s += parts[(size_t)p * count + e];
-    out[e] = s;
+    if (e < count)
+        for (int p = p0; p < p1; ++p) s += parts[(size_t)p * count + e];
+    gs[g][l] = s;
+    __syncthreads();
+    if (g == 0 && e < count) {
+        double r = gs[0][l];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) r += gs[k][l];
+        out[e] = r;
+    }
 }
 
 // X (n x n, ld ldx) = R^T, R the upper triangle of W's first n rows.
@@ -644,7 +659,7 @@ hipError_t launch_qr_t(const double *Y, const double *tau, int nb, double *T, hi
 
 hipError_t launch_sum_parts(const double *parts, int np, int64_t count, double *out,
                             hipStream_t s) {
-    hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((count + 31) / 32)), dim3(256), 0, s,
                        parts, np, count, out);
     return hipGetLastError();
 }
