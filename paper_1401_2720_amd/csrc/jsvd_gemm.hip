@@ -112,6 +112,9 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
 // consecutive rows of one column of A and of B: the same rows are the
 // contraction index of both MFMA operands), and their accumulators are
 // summed in a fixed order at the end.
+// two doubles loaded as one 16-byte access (8-byte alignment suffices)
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+
 template <int MT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gemm_tn_rows_kernel(const double *A, int64_t lda,
                                                            const double *B, int64_t ldb, int M,
@@ -145,17 +148,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
     for (int x = 0; x < MT; ++x)
 #pragma unroll
         for (int y = 0; y < NTL; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+    // every column of both operands present: the S = 2 consecutive rows of a
+    // lane as one 16-byte load, without selects
+    const bool allv = M == 16 * MT && j0 + 64 <= N;
     for (int64_t base = r0 + wave * 4 * S; base < r1; base += 16 * S) {
         const int64_t rb = base + grp * S;
         double xa[MT][S], xb[NTL][S];
+        if (allv && rb + S <= r1) {
+            static_assert(S == 2, "one 16-byte load per lane and column");
 #pragma unroll
-        for (int t = 0; t < MT; ++t)
+            for (int t = 0; t < MT; ++t) {
+                const d2u v = *reinterpret_cast<const d2u *>(ca[t] + rb);
+                xa[t][0] = v.x;
+                xa[t][1] = v.y;
+            }
 #pragma unroll
-            for (int s = 0; s < S; ++s) xa[t][s] = (va[t] && rb + s < r1) ? ca[t][rb + s] : 0.0;
+            for (int t = 0; t < NTL; ++t) {
+                const d2u v = *reinterpret_cast<const d2u *>(cb[t] + rb);
+                xb[t][0] = v.x;
+                xb[t][1] = v.y;
+            }
+        } else {
 #pragma unroll
-        for (int t = 0; t < NTL; ++t)
+            for (int t = 0; t < MT; ++t)
 #pragma unroll
-            for (int s = 0; s < S; ++s) xb[t][s] = (vb[t] && rb + s < r1) ? cb[t][rb + s] : 0.0;
+                for (int s = 0; s < S; ++s) xa[t][s] = (va[t] && rb + s < r1) ? ca[t][rb + s] : 0.0;
+#pragma unroll
+            for (int t = 0; t < NTL; ++t)
+#pragma unroll
+                for (int s = 0; s < S; ++s) xb[t][s] = (vb[t] && rb + s < r1) ? cb[t][rb + s] : 0.0;
+        }
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
