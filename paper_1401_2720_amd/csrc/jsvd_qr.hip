@@ -217,19 +217,24 @@ __global__ __launch_bounds__(kQT, 1) void qr_panel_kernel(QrPanelArgs a) {
 // T (nb x nb, upper triangular, column-major, ld kNb) with I - V T V^T =
 // H_1 ... H_nb from Y = V^T V (ld kNb) and tau: T(c, c) = tau_c,
 // T(0:c, c) = -tau_c T(0:c, 0:c) Y(0:c, c).
+// Y and tau are staged in LDS first, so that the nb steps of the recurrence
+// wait for no memory access.
 __global__ void qr_t_kernel(const double *Y, const double *tau, int nb, double *T) {
     __shared__ double Ts[kNb][kNb + 1];
-    __shared__ double z[kNb];
+    __shared__ double Ys[kNb][kNb + 1];
+    __shared__ double ts[kNb];
     const int t = threadIdx.x;
-    for (int e = t; e < kNb * kNb; e += blockDim.x) Ts[e % kNb][e / kNb] = 0.0;
+    for (int e = t; e < kNb * kNb; e += blockDim.x) {
+        Ts[e % kNb][e / kNb] = 0.0;
+        Ys[e % kNb][e / kNb] = Y[e];
+    }
+    if (t < nb) ts[t] = tau[t];
     __syncthreads();
     for (int c = 0; c < nb; ++c) {
-        const double tc = tau[c];
-        if (t < c) z[t] = Y[t + c * kNb];
-        __syncthreads();
+        const double tc = ts[c];
         if (t < c) {
             double s = 0.0;
-            for (int i = t; i < c; ++i) s = fma(Ts[t][i], z[i], s);
+            for (int i = t; i < c; ++i) s = fma(Ts[t][i], Ys[i][c], s);
             Ts[t][c] = -tc * s;
         }
         if (t == 0) Ts[c][c] = tc;
