@@ -108,6 +108,7 @@ __device__ __forceinline__ void blk_rows_update(double *X, int ldx, int rows, in
 constexpr int kBlkLdsDoubles = 2 * kBlkPairs * kBlkMat;  // R, V' (the Gram sums use V' space)
 static_assert(kBlkPairs * 3 * 4 * 64 <= kBlkPairs * kBlkMat, "Gram partial sums fit in V' space");
 static_assert(kBlkLdsDoubles == kBatchBlockLds, "host LDS bound of the blocked method");
+static_assert(kBlkBW == kBatchInnerOrder, "the host orders this table's pairs for the LDS banks");
 
 constexpr int kBlkConverged = 1 << 16, kBlkNonfinite = 1 << 17;
 

@@ -175,6 +175,7 @@ int get_inner_table(jsvd_handle_s *h, int bw, int kind, const unsigned char **ou
     if (it == h->inner_tables.end()) {
         Table t;
         if (!make_table(bw, kind, t)) return JSVD_HIP_ERROR;
+        if (bw <= 64) order_for_banks(t);  // inner_kernel's lane groups (not the 2w = 128 kernel)
         std::vector<unsigned char> flat;
         for (const auto &st : t)
             for (const auto &pr : st) {
@@ -953,6 +954,7 @@ int ensure_batch_tables(jsvd_handle_s *h) {
         if (strategy_order(N) != N) continue;
         Table t;
         if (!make_table(N, JSVD_STRAT_RREV, t)) return JSVD_HIP_ERROR;
+        if (N == kBatchInnerOrder) order_for_banks(t);  // the blocked method's inner sweeps
         tbl_off[N / 2] = (int64_t)flat.size();
         for (const auto &stp : t)
             for (const auto &pr : stp) {

@@ -19,6 +19,9 @@ using Table = std::vector<Step>;
 
 int strategy_order(int nb);
 bool make_table(int order, int kind, Table &out);
+// the pairs of each step reordered for conflict-free LDS access in the inner
+// kernels (a permutation within each step; the steps and pairs unchanged)
+void order_for_banks(Table &t);
 
 // ------------------------------------------------------------------ counters
 // Per-sweep device counters (unsigned 64-bit), reset at the start of a sweep.
@@ -93,6 +96,7 @@ hipError_t launch_update(int bw, const StepArgs &a, hipStream_t s);
 constexpr int kBatchMaxN = 256;  // largest n of a problem in the batched path
 constexpr int kBatchBlockMinN = 65;     // built-in: batched problems with n >= this are blocked
 constexpr int kBatchBlockLds = 8448;   // doubles of LDS the blocked method needs
+constexpr int kBatchInnerOrder = 32;   // 2w of the blocked method's inner sweeps
 
 struct BatchArgs {
     int64_t count;

@@ -235,4 +235,81 @@ bool make_table(int order, int kind, Table &out) {
     return true;
 }
 
+// The pairs of one parallel step are disjoint, so the slot a pair takes in
+// the inner kernels does not change any result.  There, slot s is lanes
+// 8s .. 8s + 7, lane x reading rows x + 8r of the pair's columns p and q
+// (column-major, leading dimension = 1 mod 32 doubles), so that its 8 lanes
+// hit 8 consecutive 8-byte banks starting at p mod 16 (32 four-byte banks,
+// read in 16-lane halves) or p mod 32 (64 banks, 32-lane halves).  Two slots
+// 2k, 2k + 1 are conflict-free under the first model when their p differ by
+// 8 mod 16 and their q too; four slots 4k .. 4k + 3 under the second when
+// their p mod 32 are c, c + 8, c + 16, c + 24 in that order, and their q mod
+// 32 likewise (within such a quadruple the slots are ordered so that its two
+// couples satisfy the first model too where they can).  Each step is
+// reordered greedily: such quadruples first, then such couples, then the
+// rest.
+void order_for_banks(Table &t) {
+    for (Step &st : t) {
+        const int np = (int)st.size();
+        std::vector<char> used(np, 0);
+        Step out;
+        out.reserve(np);
+        auto qpos = [](int v) { return (v % 32) / 8; };
+        // quadruples: the same p mod 8 and q mod 8, p mod 32 and q mod 32 in
+        // the four eighths of 32 (each once), slot order by p's eighth
+        for (int a = 0; a < np && np % 4 == 0; ++a) {
+            if (used[a]) continue;
+            int pick[4] = {-1, -1, -1, -1};
+            pick[qpos(st[a].first)] = a;
+            int qmask = 1 << qpos(st[a].second);
+            for (int b = 0; b < np; ++b) {
+                if (used[b] || b == a) continue;
+                if (st[b].first % 8 != st[a].first % 8 || st[b].second % 8 != st[a].second % 8)
+                    continue;
+                const int pp = qpos(st[b].first), qq = qpos(st[b].second);
+                if (pick[pp] >= 0 || (qmask >> qq & 1)) continue;
+                pick[pp] = b;
+                qmask |= 1 << qq;
+            }
+            if (pick[0] >= 0 && pick[1] >= 0 && pick[2] >= 0 && pick[3] >= 0) {
+                // an order whose two couples are also conflict-free in 16-lane
+                // halves (p and q each an odd number of eighths apart), if any
+                int ord[4] = {pick[0], pick[1], pick[2], pick[3]};
+                int perm[4] = {0, 1, 2, 3};
+                do {
+                    auto odd = [&](int u, int v) {
+                        const Pair &x = st[pick[perm[u]]], &y = st[pick[perm[v]]];
+                        return ((qpos(x.first) - qpos(y.first)) & 1) && ((qpos(x.second) - qpos(y.second)) & 1);
+                    };
+                    if (odd(0, 1) && odd(2, 3)) {
+                        for (int k = 0; k < 4; ++k) ord[k] = pick[perm[k]];
+                        break;
+                    }
+                } while (std::next_permutation(perm, perm + 4));
+                for (int k = 0; k < 4; ++k) {
+                    used[ord[k]] = 1;
+                    out.push_back(st[ord[k]]);
+                }
+            }
+        }
+        // couples: p and q both 8 apart mod 16
+        for (int a = 0; a < np; ++a) {
+            if (used[a]) continue;
+            for (int b = a + 1; b < np; ++b) {
+                if (used[b]) continue;
+                if ((st[a].first - st[b].first + 16) % 16 == 8 &&
+                    (st[a].second - st[b].second + 16) % 16 == 8) {
+                    used[a] = used[b] = 1;
+                    out.push_back(st[a]);
+                    out.push_back(st[b]);
+                    break;
+                }
+            }
+        }
+        for (int a = 0; a < np; ++a)
+            if (!used[a]) out.push_back(st[a]);
+        st.swap(out);
+    }
+}
+
 }  // namespace jsvd
