@@ -27,7 +27,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PF ? 2 : 4)
     constexpr int NT = T * (T + 1) / 2;
     constexpr int S = 4;
     constexpr int SLICE = 4 * S;  // rows per wave and iteration
-    __shared__ d4 red[NT * 64];
+    // wave partial sums, element v of tile k's accumulator of lane l at
+    // red[(4 k + v) 64 + l]: 64 consecutive doubles per access, no bank conflict
+    __shared__ double red[NT * 4 * 64];
 
     // Workgroups go to the 8 XCDs round robin by linear index.  When the
     // pairs divide evenly, all splits of pair k run on XCD k mod 8, where
@@ -139,7 +141,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PF ? 2 : 4)
         if (wave == wv) {
 #pragma unroll
             for (int k = 0; k < NT; ++k)
-                red[k * 64 + lane] = (wv == 0) ? acc[k] : red[k * 64 + lane] + acc[k];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    double &r = red[(4 * k + v) * 64 + lane];
+                    r = (wv == 0) ? acc[k][v] : r + acc[k][v];
+                }
         }
         __syncthreads();
     }
@@ -155,7 +161,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PF ? 2 : 4)
                     tb = y0;
                 }
         const int row = ta * 16 + (l >> 4) + 4 * v, colh = tb * 16 + (l & 15);
-        out[row * BW + colh] = red[k * 64 + l][v];
+        out[row * BW + colh] = red[(4 * k + v) * 64 + l];
     }
 }
 
