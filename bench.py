@@ -585,8 +585,11 @@ def main():
         "update_bytes": upd_per_launch * m * bw * 8.0 * 2,
         "inner_flops": (isw_per_launch * (bw - 1) * (bw // 2) * 6.0 * bw
                         + rot_per_launch * 12.0 * bw + npairs * bw ** 3 / 3.0),
-        # the survey's model of the inner Jacobi: 36 w n^2 s_in flops per
-        # block sweep (s_in inner sweeps per pivot pair), nb - 1 launches
+        # the algorithmic model of the inner Jacobi: per block sweep about
+        # n^2 / (2 w^2) pivot block-pairs, each inner sweep (2w - 1) w pivot
+        # pairs at 6 (2w) flops for the dot products and 12 (2w) for rotating
+        # R and V', i.e. 36 w n^2 s_in flops (s_in inner sweeps per pivot
+        # block-pair), over the nb - 1 launches of a sweep
         "inner_flops_model": 36.0 * w * n * n * (isw_per_launch / npairs) / steps_per_sweep,
         "inner_v_flops": upd_per_launch * 2.0 * n * bw * bw,
         "inner_v_bytes": upd_per_launch * n * bw * 8.0 * 2,
