@@ -404,6 +404,17 @@ int jsvd_svd_backward(jsvd_handle_t h, int64_t batch, int64_t m, int64_t n, cons
  */
 int jsvd_strategy_table(int32_t order, int32_t kind, int32_t *pairs);
 
+/*
+ * The table the inner kernels use for a pivot block-pair of 2w = order
+ * columns (order 32 or 64): jsvd_strategy_table's with the pairs of each
+ * p-step reordered for conflict-free LDS access.  The pairs of a parallel
+ * step are disjoint (Section 3), so their order within the step changes no
+ * result; the steps and the set of pairs in each are those of
+ * jsvd_strategy_table.  Same layout, arguments and return codes, and -1
+ * also for an order other than 32 or 64.
+ */
+int jsvd_inner_table(int32_t order, int32_t kind, int32_t *pairs);
+
 /* Smallest supported strategy order >= max(nb, 2) (even, 2^k * o, o <= 11). */
 int32_t jsvd_strategy_order(int32_t nb);
 

@@ -56,7 +56,8 @@ class JsvdError(RuntimeError):
 
 _LIB = None
 EXPORTS = ["jsvd_default_opts", "jsvd_create", "jsvd_set_stream", "jsvd_destroy", "jsvd_gesvd",
-           "jsvd_hsvd", "jsvd_strategy_table", "jsvd_strategy_order", "jsvd_error_string",
+           "jsvd_hsvd", "jsvd_strategy_table", "jsvd_inner_table", "jsvd_strategy_order",
+           "jsvd_error_string",
            "jsvd_diag_fp64", "jsvd_kernel_timing", "jsvd_kernel_times", "jsvd_gesvd_batched",
            "jsvd_svd_backward", "jsvd_set_tuning", "jsvd_batched_block_min_n",
            "jsvd_workspace_size", "jsvd_workspace_size_batched", "jsvd_reserve_batched",
@@ -84,6 +85,7 @@ def lib():
     L.jsvd_hsvd.argtypes = [_vp, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _i64,
                             ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     L.jsvd_strategy_table.argtypes = [_i32, _i32, _vp]
+    L.jsvd_inner_table.argtypes = [_i32, _i32, _vp]
     L.jsvd_strategy_order.argtypes = [_i32]
     L.jsvd_strategy_order.restype = _i32
     L.jsvd_batched_block_min_n.argtypes = [_vp]
@@ -328,6 +330,18 @@ def strategy_table(order, kind="rrev"):
     rc = lib().jsvd_strategy_table(int(order), k, _vp(out.ctypes.data))
     if rc:
         raise JsvdError(rc, "jsvd_strategy_table")
+    return out.reshape(order - 1, order // 2, 2)
+
+
+def inner_table(order, kind="rrev"):
+    """The inner kernels' table for 2w = order (32 or 64): strategy_table's
+    with each step's pairs reordered for the LDS banks (host only)."""
+    import numpy as np
+    out = np.zeros((order - 1) * (order // 2) * 2, dtype=np.int32)
+    k = STRATEGIES[kind] if isinstance(kind, str) else int(kind)
+    rc = lib().jsvd_inner_table(int(order), k, _vp(out.ctypes.data))
+    if rc:
+        raise JsvdError(rc, "jsvd_inner_table")
     return out.reshape(order - 1, order // 2, 2)
 
 

@@ -1286,6 +1286,22 @@ int jsvd_strategy_table(int32_t order, int32_t kind, int32_t *pairs) {
     return JSVD_OK;
 }
 
+int jsvd_inner_table(int32_t order, int32_t kind, int32_t *pairs) {
+    if (kind < JSVD_STRAT_RREV || kind > JSVD_STRAT_RR) return -2;
+    if (!pairs) return -3;
+    if (order != 32 && order != 64) return -1;
+    Table t;
+    if (!make_table(order, kind, t)) return -1;
+    order_for_banks(t);
+    size_t k = 0;
+    for (const auto &st : t)
+        for (const auto &pr : st) {
+            pairs[k++] = pr.first + 1;
+            pairs[k++] = pr.second + 1;
+        }
+    return JSVD_OK;
+}
+
 int32_t jsvd_strategy_order(int32_t nb) { return strategy_order(nb); }
 
 int32_t jsvd_batched_block_min_n(jsvd_handle_t h) {
