@@ -52,6 +52,9 @@ QR_CASES = [
     ("tall2500x33_gauss", 2500, 33, "gauss"),      # a panel of 1 column, 5 workgroups
     ("square96_graded", 96, 96, "graded"),         # forced QR on a square matrix
     ("narrow700x5_gauss", 700, 5, "gauss"),
+    # the largest m of the QR path: 64 panel workgroups, whose 64 partial sums
+    # per column are gathered in one round trip
+    ("tall32768x40_graded", 32768, 40, "graded"),
 ]
 
 
