@@ -257,6 +257,31 @@ int gram_splits(int64_t m, int npairs, int gram_wg, int64_t *rows_per_split) {
     return (int)((m + rps - 1) / rps);
 }
 
+// The workgroups a p-step's first launch aims at: the tuned Gram figure, or,
+// for the QR shortening, the row splits whose chains are shortest.  A QR
+// workgroup's chain is about 2 bw barrier stages per bw-row chunk (bw - 1
+// reflections, then bw peel-off stages to fold it in) and the inner kernel's
+// fold of the splits' factors bw stages per split after the first, so s
+// splits of c chunks cost about 2 ceil(c / s) + s - 1 chains of bw stages;
+// s is kept to grids that stay resident (two bw x (bw + 1) matrices of LDS
+// per workgroup: two per CU at bw = 64, four at bw = 32).
+int split_target(const jsvd_handle_s *h, const jsvd_opts &o, const Shapes &shp, int64_t m,
+                 int npairs, int bw) {
+    if (o.factorize != 1) return shp.gram_wg;
+    const int64_t chunks = (m + bw - 1) / bw;
+    const int64_t resident = (int64_t)(bw >= 64 ? 2 : 4) * h->cu_count;
+    int best = 1;
+    int64_t best_cost = 2 * chunks;
+    for (int sp = 2; sp <= 16 && (int64_t)sp * npairs <= resident; ++sp) {
+        const int64_t cost = 2 * ((chunks + sp - 1) / sp) + sp - 1;
+        if (cost < best_cost) {
+            best = sp;
+            best_cost = cost;
+        }
+    }
+    return best * npairs;
+}
+
 // Workspace carve-up for one solve.
 struct Layout {
     size_t hpart, vprime, pair_rot, counters, perm, s_tmp, tmp, perm_in, rscratch, total;
@@ -351,7 +376,7 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     // pairs leave free (a workgroup there has 16 * 2w threads).
     const int target_wg = shp.update_wg;
     int64_t rps = 0;
-    const int splits = gram_splits(m, npairs, shp.gram_wg, &rps);
+    const int splits = gram_splits(m, npairs, split_target(h, o, shp, m, npairs, bw), &rps);
     const int per_pair = std::max(1, target_wg / npairs);
     const int64_t upd_rows_g = align_up((size_t)((m + per_pair - 1) / per_pair), 64);
     const int64_t upd_rows_v = align_up((size_t)((n + per_pair - 1) / per_pair), 64);
@@ -1572,7 +1597,8 @@ int jsvd_workspace_size(jsvd_handle_t h, int64_t m, int64_t n, const jsvd_opts *
         auto bytes_at = [&](int w) {
             const int order = strategy_order((int)((nn + w - 1) / w));
             int64_t rps = 0;
-            const int splits = gram_splits(mm, order / 2, shp.gram_wg, &rps);
+            const int tgt = split_target(h, o, shp, mm, order / 2, 2 * w);
+            const int splits = gram_splits(mm, order / 2, tgt, &rps);
             return plan(mm, nn, 2 * w, order / 2, splits, hsvd).total;
         };
         // w = 64 falls back to 32 for the hyperbolic SVD and the scaled mode

@@ -133,7 +133,7 @@ def test_square_gaussian_4096_one_buffer_gram_against_oracle():
     """The same with 16 Gram row splits (a tuning table with 1024 Gram
     workgroups per launch): 1024 workgroups are more than two per CU, so the
     Gram kernel takes its one-buffer loop instead of the two-buffer pipeline
-    of the default 8 splits, and the inner kernel sums 16 partials."""
+    of the default 4 splits, and the inner kernel sums 16 partials."""
     torch = _torch()
     import paper_1401_2720_amd as jsvd
     from paper_1401_2720_amd import _binding as B
