@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--block-w", type=int, default=0)
     ap.add_argument("--strategy", default="rrev")
     ap.add_argument("--max-inner-sweeps", type=int, default=0, help="0 = library's choice")
+    ap.add_argument("--fuse", action="store_true",
+                    help="the update fused into the next p-step's Gram launch (opts.fuse)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the oracle sample (0 = skip)")
     ap.add_argument("--no-forms", action="store_true",
@@ -486,8 +488,8 @@ def bench_qrfactor(args):
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"svd_gaussian_{n}x{n}_qrfactor", "m": n, "n": n, "seed": 2,
                       "block_w": info.block_w, "factorize": "qr", "sweeps": sweeps},
-           "kernels_avg_us": {("qrfac" if k == "gram" else k): kt[k][0] / max(kt[k][1], 1) * 1e3
-                              for k in kt},
+           "kernels_avg_us": {("qrfac" if k == "gram" else k): kt[k][0] / kt[k][1] * 1e3
+                              for k in kt if kt[k][1] > 0},
            "accuracy": acc, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
@@ -525,7 +527,7 @@ def main():
     L = jsvd.lib()
     h = B._handle(0, stream.cuda_stream)
     opts = B.make_opts(block_w=args.block_w, strategy=args.strategy,
-                       max_inner_sweeps=args.max_inner_sweeps)
+                       max_inner_sweeps=args.max_inner_sweeps, fuse=args.fuse)
     info = B.Info()
 
     def step():
@@ -573,7 +575,10 @@ def main():
     #           products (6 bw) and per rotation the update of two columns of
     #           R and of V' (12 bw), FP64 vector work; the same launch also
     #           streams the previous p-step's V update (2 n bw^2 flops, n x bw
-    #           columns read and written per transformed pair).
+    #           columns read and written per transformed pair);
+    #   fused   the update of a p-step and the next p-step's Gram matrices in
+    #           one launch: both kernels' flops, G read once and the
+    #           transformed pairs' columns written.
     launches = sum(sweeps) * steps_per_sweep
     upd_per_launch = sum(updates) / max(launches, 1)
     rot_per_launch = sum(rotations) / max(launches, 1)
@@ -594,9 +599,17 @@ def main():
         "inner_v_flops": upd_per_launch * 2.0 * n * bw * bw,
         "inner_v_bytes": upd_per_launch * n * bw * 8.0 * 2,
     }
-    avg = {k: (kt[k][0] / max(kt[k][1], 1)) for k in kt}
+    per_launch["fused_flops"] = per_launch["update_flops"] + per_launch["gram_flops"]
+    per_launch["fused_bytes"] = per_launch["gram_bytes"] + upd_per_launch * m * bw * 8.0
+    # kernels that ran in the timed p-steps (with the update fused into the
+    # next Gram launch, the plain Gram and update kernels run only at the
+    # first and last p-step of a sweep, which the sampled steps may miss)
+    kt = {k: v for k, v in kt.items() if v[1] > 0}
+    avg = {k: (kt[k][0] / kt[k][1]) for k in kt}
     rooflines = {}
-    for name in ("gram", "inner", "update"):
+    for name in ("gram", "inner", "update", "fused"):
+        if name not in kt:
+            continue
         r = kernel_roofline(name, avg[name], per_launch)
         r["avg_launch_us"] = avg[name] * 1e3
         r["launches"] = kt[name][1]
@@ -616,7 +629,10 @@ def main():
     tiles = bw // 16
     gram_exec = npairs * 2.0 * m * bw * bw * (tiles * (tiles + 1) / 2) / (tiles * tiles)
     mfma = {"peak_tflops": PEAK_FP64_TFLOPS}
-    for name, fl in (("gram", gram_exec), ("update", per_launch["update_flops"])):
+    for name, fl in (("gram", gram_exec), ("update", per_launch["update_flops"]),
+                     ("fused", gram_exec + per_launch["update_flops"])):
+        if name not in kt:
+            continue
         tf = fl / (avg[name] * 1e-3) / 1e12
         mfma[name] = {"executed_flops_per_launch": fl, "tflops": tf,
                       "frac": tf / PEAK_FP64_TFLOPS, "avg_launch_us": avg[name] * 1e3}
@@ -668,14 +684,16 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"svd_gaussian_{m}x{n}", "m": m, "n": n, "seed": 2,
-                   "block_w": w, "strategy": args.strategy,
+                   "block_w": w, "strategy": args.strategy, "fused": "fused" in kt,
                    "max_inner_sweeps": args.max_inner_sweeps, "sweeps": sweeps,
                    "rotations": rotations[-1]},
         "roofline": roof,
         "rooflines": rooflines,
         "mfma": mfma,
+        # the FP64 MFMA rate of a p-step's Gram and update work
         "gram_update_mfma_frac": (gram_exec + per_launch["update_flops"])
-        / ((avg["gram"] + avg["update"]) * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+        / ((avg["fused"] if "fused" in avg else avg["gram"] + avg["update"]) * 1e-3) / 1e12
+        / PEAK_FP64_TFLOPS,
         "forms": forms,
         "kernels_avg_us": {k: avg[k] * 1e3 for k in avg},
         "kernels_share": {k: kt[k][0] / max(sum(v[0] for v in kt.values()), 1e-9) for k in kt},

@@ -101,6 +101,20 @@ typedef struct {
                                  never formed (slower; R's accuracy does not depend on the
                                  square of the pair's condition number).  With 1, block_w 64
                                  is taken as 32. */
+    int32_t fuse;             /* 1: where the ordering exchanges partners inside
+                                 groups of two pivot pairs from one p-step to the next
+                                 (the Mantharam-Eberlein orderings for a power-of-two
+                                 number of blocks, jsvd_quad_table), 2w = 64, no padding
+                                 columns, m a multiple of 64 (and lda <= 2^25), the
+                                 unscaled Cholesky path: the update of a
+                                 p-step (eq. (2.9)) and the next p-step's Gram matrices
+                                 (eq. (2.7)) in one launch, G read once per p-step;
+                                 elsewhere, and with 0 (default), three launches per
+                                 p-step.  The Gram partial sums are formed in another
+                                 order, so the results agree with the three-launch path
+                                 to rounding.  On the MI355X the fused launch takes
+                                 longer than the two it replaces (its MFMA issue, not
+                                 HBM, bounds both), hence the default. */
 } jsvd_opts;
 
 typedef struct {
@@ -415,6 +429,22 @@ int jsvd_strategy_table(int32_t order, int32_t kind, int32_t *pairs);
  */
 int jsvd_inner_table(int32_t order, int32_t kind, int32_t *pairs);
 
+/*
+ * The step-to-step groups that the fused update-and-Gram launch works on
+ * (opts.fuse): for a table of jsvd_strategy_table whose consecutive p-steps
+ * exchange partners inside groups of two pairs -- (a0, a1) and (b0, b1) in
+ * p-step s, and in p-step s + 1 one pair of {a0, a1} x {b0, b1} and the
+ * other -- per p-step s < order - 2 and group, 8 int32: the two pairs'
+ * zero-based indices ia, ib within p-step s, the two new pairs' indices jx,
+ * jy within p-step s + 1, the block a0 of pair ia and b0 of pair ib that
+ * pair jx holds (zero-based block indices), and two zeros.
+ *   quads : host, (order - 2) * (order / 4) * 8 int32.
+ * Returns JSVD_OK, 1 when the table has no such structure (quads is not
+ * written; the p-steps then take three launches), -1 for an unsupported
+ * order, -2 for an unknown kind, -3 for quads == NULL.
+ */
+int jsvd_quad_table(int32_t order, int32_t kind, int32_t *quads);
+
 /* Smallest supported strategy order >= max(nb, 2) (even, 2^k * o, o <= 11). */
 int32_t jsvd_strategy_order(int32_t nb);
 
@@ -425,13 +455,13 @@ int32_t jsvd_batched_block_min_n(jsvd_handle_t h);
 
 /*
  * Measurement aid: per-kernel GPU time of the block sweeps, taken with HIP
- * events recorded on the handle's stream around every launch of the three
+ * events recorded on the handle's stream around every launch of the
  * p-step kernels (index 0 = Gram, 1 = inner Cholesky and Jacobi, 2 =
- * update).  jsvd_kernel_timing(h, k) with k > 0 turns it on for every k-th
+ * update, 3 = the update fused with the next p-step's Gram kernel).  jsvd_kernel_timing(h, k) with k > 0 turns it on for every k-th
  * p-step of each sweep (k = 1: all; a larger k keeps the events' own cost
  * out of the run) and zeroes the totals; (h, 0) turns it off.
- * jsvd_kernel_times writes the totals since the last reset: ms[3] (host) in
- * milliseconds and launches[3] (host), the number of timed launches.
+ * jsvd_kernel_times writes the totals since the last reset: ms[4] (host) in
+ * milliseconds and launches[4] (host), the number of timed launches.
  * Both return JSVD_OK, -i for a NULL argument i, or -2 for k < 0.
  */
 int jsvd_kernel_timing(jsvd_handle_t h, int enable);

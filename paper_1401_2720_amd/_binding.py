@@ -25,7 +25,7 @@ STATUS = {0: "ok", 1: "not converged", 3: "non-finite value", 4: "HIP error",
 class Opts(ctypes.Structure):
     _fields_ = [("block_w", _i32), ("strategy", _i32), ("max_inner_sweeps", _i32),
                 ("max_sweeps", _i32), ("want_v", _i32), ("sort", _i32), ("qr", _i32),
-                ("scaled", _i32), ("factorize", _i32)]
+                ("scaled", _i32), ("factorize", _i32), ("fuse", _i32)]
 
 
 class Info(ctypes.Structure):
@@ -56,7 +56,8 @@ class JsvdError(RuntimeError):
 
 _LIB = None
 EXPORTS = ["jsvd_default_opts", "jsvd_create", "jsvd_set_stream", "jsvd_destroy", "jsvd_gesvd",
-           "jsvd_hsvd", "jsvd_strategy_table", "jsvd_inner_table", "jsvd_strategy_order",
+           "jsvd_hsvd", "jsvd_strategy_table", "jsvd_inner_table", "jsvd_quad_table",
+           "jsvd_strategy_order",
            "jsvd_error_string",
            "jsvd_diag_fp64", "jsvd_kernel_timing", "jsvd_kernel_times", "jsvd_gesvd_batched",
            "jsvd_svd_backward", "jsvd_set_tuning", "jsvd_batched_block_min_n",
@@ -86,6 +87,7 @@ def lib():
                             ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     L.jsvd_strategy_table.argtypes = [_i32, _i32, _vp]
     L.jsvd_inner_table.argtypes = [_i32, _i32, _vp]
+    L.jsvd_quad_table.argtypes = [_i32, _i32, _vp]
     L.jsvd_strategy_order.argtypes = [_i32]
     L.jsvd_strategy_order.restype = _i32
     L.jsvd_batched_block_min_n.argtypes = [_vp]
@@ -204,7 +206,7 @@ FACTORIZE = {"cholesky": 0, "qr": 1}
 
 
 def make_opts(block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,
-              sort=True, qr="auto", scaled="auto", factorize="cholesky"):
+              sort=True, qr="auto", scaled="auto", factorize="cholesky", fuse=False):
     o = Opts()
     lib().jsvd_default_opts(ctypes.byref(o))
     o.block_w = int(block_w)
@@ -216,6 +218,7 @@ def make_opts(block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, wan
     o.qr = QR_MODES[qr] if isinstance(qr, str) else int(qr)
     o.scaled = QR_MODES[scaled] if isinstance(scaled, str) else int(scaled)
     o.factorize = FACTORIZE[factorize] if isinstance(factorize, str) else int(factorize)
+    o.fuse = 1 if fuse else 0
     return o
 
 
@@ -233,7 +236,7 @@ def _raise_on(rc, what, allow):
 
 
 def gesvd(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,
-          sort=True, allow=(1,), qr="auto", scaled="auto", factorize="cholesky"):
+          sort=True, allow=(1,), qr="auto", scaled="auto", factorize="cholesky", fuse=False):
     """SVD A = U diag(S) V^T of a float64 CUDA tensor (m >= n).
 
     Returns (U, S, V, info): U (m x n) and V (n x n) column-major views, S (n),
@@ -250,7 +253,7 @@ def gesvd(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want
     h = _handle(dev.index if dev.index is not None else torch.cuda.current_device(),
                 stream.cuda_stream)
     o = make_opts(block_w, strategy, max_inner_sweeps, max_sweeps, want_v, sort, qr, scaled,
-                  factorize)
+                  factorize, fuse)
     info = Info()
     rc = lib().jsvd_gesvd(h, m, n, _vp(work.data_ptr()), m, _vp(S.data_ptr()),
                           _vp(Vb.data_ptr()) if want_v else None, n, ctypes.byref(o),
@@ -262,7 +265,7 @@ def gesvd(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want
 
 
 def gesvd_full(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,
-               allow=(1,), qr="auto", scaled="auto", factorize="cholesky"):
+               allow=(1,), qr="auto", scaled="auto", factorize="cholesky", fuse=False):
     """Full SVD A = U [diag(S); 0] V^T of a float64 CUDA tensor (m >= n) with
     U of order m.  Returns (U, S, V, info): U (m x m) and V (n x n) views of
     column-major buffers."""
@@ -277,7 +280,7 @@ def gesvd_full(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30,
     h = _handle(dev.index if dev.index is not None else torch.cuda.current_device(),
                 stream.cuda_stream)
     o = make_opts(block_w, strategy, max_inner_sweeps, max_sweeps, want_v, True, qr, scaled,
-                  factorize)
+                  factorize, fuse)
     info = Info()
     rc = lib().jsvd_gesvd_full(h, m, n, _vp(work.data_ptr()), m, _vp(Ub.data_ptr()), m,
                                _vp(S.data_ptr()), _vp(Vb.data_ptr()) if want_v else None, n,
@@ -289,7 +292,7 @@ def gesvd_full(A, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30,
 
 
 def hsvd(G, J, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, want_v=True,
-         sort=True, allow=(1,), scaled="auto", factorize="cholesky"):
+         sort=True, allow=(1,), scaled="auto", factorize="cholesky", fuse=False):
     """Hyperbolic SVD G V = U diag(S), V^T J V = diag(J_out).
 
     J: sequence of n values, each +1 or -1.  Returns (U, S, V, J_out, info)
@@ -310,7 +313,7 @@ def hsvd(G, J, block_w=0, strategy="rrev", max_inner_sweeps=0, max_sweeps=30, wa
     h = _handle(dev.index if dev.index is not None else torch.cuda.current_device(),
                 stream.cuda_stream)
     o = make_opts(block_w, strategy, max_inner_sweeps, max_sweeps, want_v, sort, scaled=scaled,
-                  factorize=factorize)
+                  factorize=factorize, fuse=fuse)
     info = Info()
     rc = lib().jsvd_hsvd(h, m, n, _vp(work.data_ptr()), m, _vp(Jh.ctypes.data),
                          _vp(Jout.ctypes.data), _vp(S.data_ptr()),
@@ -343,6 +346,21 @@ def inner_table(order, kind="rrev"):
     if rc:
         raise JsvdError(rc, "jsvd_inner_table")
     return out.reshape(order - 1, order // 2, 2)
+
+
+def quad_table(order, kind="rrev"):
+    """(order - 2, order / 4, 8) int32 array of the step-to-step groups of
+    the fused update-and-Gram launch, or None when the ordering has none
+    (host only)."""
+    import numpy as np
+    out = np.zeros(max(order - 2, 0) * (order // 4) * 8, dtype=np.int32)
+    k = STRATEGIES[kind] if isinstance(kind, str) else int(kind)
+    rc = lib().jsvd_quad_table(int(order), k, _vp(out.ctypes.data))
+    if rc == 1:
+        return None
+    if rc:
+        raise JsvdError(rc, "jsvd_quad_table")
+    return out.reshape(order - 2, order // 4, 8)
 
 
 def strategy_order(nb):
@@ -472,16 +490,18 @@ def kernel_timing(device_index, enable=True, stride=1):
 
 
 def kernel_times(device_index):
-    """{'gram'|'inner'|'update': (total_ms, launches)} since the last reset."""
+    """{'gram'|'inner'|'update'|'fused': (total_ms, launches)} since the last
+    reset ('fused': the update fused with the next p-step's Gram kernel)."""
     import numpy as np
     import torch
     h = _handle(device_index, torch.cuda.current_stream(device_index).cuda_stream)
-    ms = np.zeros(3, np.float64)
-    cnt = np.zeros(3, np.int64)
+    ms = np.zeros(4, np.float64)
+    cnt = np.zeros(4, np.int64)
     rc = lib().jsvd_kernel_times(h, _vp(ms.ctypes.data), _vp(cnt.ctypes.data))
     if rc:
         raise JsvdError(rc, "jsvd_kernel_times")
-    return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(("gram", "inner", "update"))}
+    return {k: (float(ms[i]), int(cnt[i]))
+            for i, k in enumerate(("gram", "inner", "update", "fused"))}
 
 
 class Batch:

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libjsvd.so")
-SOURCES = ["jsvd_gram.hip", "jsvd_qrfac.hip", "jsvd_inner.hip", "jsvd_update.hip", "jsvd_aux.hip", "jsvd_qr.hip",
+SOURCES = ["jsvd_gram.hip", "jsvd_fused.hip", "jsvd_qrfac.hip", "jsvd_inner.hip", "jsvd_update.hip", "jsvd_aux.hip", "jsvd_qr.hip",
            "jsvd_batched.hip",
            "jsvd_backward.hip", "jsvd_gemm.hip", "jsvd_host.cpp",
            "strategy.cpp"]

@@ -69,6 +69,7 @@ struct jsvd_handle_s {
     unsigned long long *host_counters = nullptr;  // pinned, kHostSlots words
     std::map<std::pair<int, int>, DeviceTable> block_tables;  // (order, kind) -> int2[]
     std::map<std::pair<int, int>, DeviceTable> inner_tables;  // (bw, kind) -> uchar[]
+    std::map<std::pair<int, int>, DeviceTable> quad_tables;   // (order, kind) -> int[8][]
     // batched path: strategy tables of every order up to kBatchMaxN
     void *batch_tables = nullptr;   // uchar pairs
     void *batch_meta = nullptr;     // int tbl_order[kBatchMaxN+1], int64 tbl_off[kBatchMaxN/2+1]
@@ -87,8 +88,8 @@ struct jsvd_handle_s {
     bool timing = false;
     int timing_stride = 1;          // time every timing_stride-th p-step
     std::vector<hipEvent_t> events;
-    double kernel_ms[3] = {0, 0, 0};
-    int64_t launches[3] = {0, 0, 0};
+    double kernel_ms[4] = {0, 0, 0, 0};  // Gram, inner, update, fused update and Gram
+    int64_t launches[4] = {0, 0, 0, 0};
 };
 
 namespace {
@@ -169,6 +170,27 @@ int get_block_table(jsvd_handle_s *h, int order, int kind, const int2 **out) {
     return JSVD_OK;
 }
 
+// The step-to-step quads of a block table (make_quads), or null when the
+// ordering has none (the p-step then takes three launches).
+int get_quad_table(jsvd_handle_s *h, int order, int kind, const int **out) {
+    auto key = std::make_pair(order, kind);
+    auto it = h->quad_tables.find(key);
+    if (it == h->quad_tables.end()) {
+        Table t;
+        if (!make_table(order, kind, t)) return JSVD_HIP_ERROR;
+        std::vector<int> flat;
+        DeviceTable d;
+        if (make_quads(t, flat)) {
+            d.bytes = flat.size() * sizeof(int);
+            HIP_TRY(hipMalloc(&d.ptr, d.bytes));
+            HIP_TRY(hipMemcpy(d.ptr, flat.data(), d.bytes, hipMemcpyHostToDevice));
+        }
+        it = h->quad_tables.emplace(key, d).first;
+    }
+    *out = static_cast<const int *>(it->second.ptr);
+    return JSVD_OK;
+}
+
 int get_inner_table(jsvd_handle_s *h, int bw, int kind, const unsigned char **out) {
     auto key = std::make_pair(bw, kind);
     auto it = h->inner_tables.find(key);
@@ -203,6 +225,7 @@ jsvd_opts defaults() {
     o.qr = 0;
     o.scaled = 0;
     o.factorize = 0;
+    o.fuse = 0;
     return o;
 }
 
@@ -264,9 +287,12 @@ int gram_splits(int64_t m, int npairs, int gram_wg, int64_t *rows_per_split) {
 // fold of the splits' factors bw stages per split after the first, so s
 // splits of c chunks cost about 2 ceil(c / s) + s - 1 chains of bw stages;
 // s is kept to grids that stay resident (two bw x (bw + 1) matrices of LDS
-// per workgroup: two per CU at bw = 64, four at bw = 32).
+// per workgroup: two per CU at bw = 64, four at bw = 32).  With the update
+// fused into the next p-step's Gram launch, one fused workgroup per CU
+// (each owns two pairs' columns: 2 cu_count pair-splits).
 int split_target(const jsvd_handle_s *h, const jsvd_opts &o, const Shapes &shp, int64_t m,
-                 int npairs, int bw) {
+                 int npairs, int bw, bool fused) {
+    if (fused) return 2 * h->cu_count;
     if (o.factorize != 1) return shp.gram_wg;
     const int64_t chunks = (m + bw - 1) / bw;
     const int64_t resident = (int64_t)(bw >= 64 ? 2 : 4) * h->cu_count;
@@ -369,6 +395,18 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     const int npairs = order / 2;
     const int nsteps = order - 1;
     const bool want_v = o.want_v != 0;
+    // the update fused with the next p-step's Gram kernel where the ordering
+    // has step-to-step quads (make_quads): 2w = 64, no padding columns, rows
+    // a multiple of 64 (whole 16-row slices for the four waves of a role),
+    // lane byte offsets of up to 16 columns below 2^32, unscaled, the
+    // Cholesky factorization
+    const int *quads = nullptr;
+    if (o.fuse && bw == 64 && !scaled && !qrf && (int64_t)order * w == n && m % 64 == 0 &&
+        lda <= ((int64_t)1 << 25) &&
+        (rc = get_quad_table(h, order, o.strategy, &quads)))
+        return rc;
+    const bool fused = quads != nullptr;
+    const int nquads = npairs / 2;
 
     // Gram row splits (at most 16) and update row chunks: aim at a few
     // workgroups per CU.  The V update of a p-step is done by the next
@@ -376,7 +414,7 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     // pairs leave free (a workgroup there has 16 * 2w threads).
     const int target_wg = shp.update_wg;
     int64_t rps = 0;
-    const int splits = gram_splits(m, npairs, split_target(h, o, shp, m, npairs, bw), &rps);
+    const int splits = gram_splits(m, npairs, split_target(h, o, shp, m, npairs, bw, fused), &rps);
     const int per_pair = std::max(1, target_wg / npairs);
     const int64_t upd_rows_g = align_up((size_t)((m + per_pair - 1) / per_pair), 64);
     const int64_t upd_rows_v = align_up((size_t)((n + per_pair - 1) / per_pair), 64);
@@ -425,6 +463,8 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
     a.btbl_off = reinterpret_cast<const int64_t *>(
         static_cast<char *>(h->batch_meta) + align_up((kBatchMaxN + 1) * sizeof(int), 256));
     a.btbls = static_cast<const unsigned char *>(h->batch_tables);
+    a.quads = nullptr;
+    a.next_pairs = nullptr;
     if (bw == 128 && !h->batch_tables) return JSVD_HIP_ERROR;
     a.max_inner_sweeps = o.max_inner_sweeps > 0 ? o.max_inner_sweeps : choose_inner_sweeps(m, n);
     a.upd_rows = (int)upd_rows_g;
@@ -470,11 +510,20 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
             const bool timed = h->timing && s % h->timing_stride == 0;
             hipEvent_t *ev = timed ? &h->events[(size_t)4 * s] : nullptr;
             if (ev) HIP_TRY(hipEventRecord(ev[0], st));
-            HIP_TRY(qrf ? launch_qrfac(bw, a, st) : launch_gram(bw, a, st));
+            // fused: the previous p-step's launch formed this one's Gram
+            // partials, except at the first p-step of a sweep
+            if (!fused || s == 0) HIP_TRY(qrf ? launch_qrfac(bw, a, st) : launch_gram(bw, a, st));
             if (ev) HIP_TRY(hipEventRecord(ev[1], st));
             HIP_TRY(launch_inner(bw, a, st));
             if (ev) HIP_TRY(hipEventRecord(ev[2], st));
-            HIP_TRY(launch_update(bw, a, st));
+            if (fused && s + 1 < nsteps) {
+                StepArgs f = a;
+                f.quads = quads + (size_t)s * nquads * 8;
+                f.next_pairs = blk + (size_t)(s + 1) * npairs;
+                HIP_TRY(launch_fused(nquads, f, st));
+            } else {
+                HIP_TRY(launch_update(bw, a, st));
+            }
             if (ev) HIP_TRY(hipEventRecord(ev[3], st));
         }
         HIP_TRY(hipMemcpyAsync(h->host_counters, a.counters, C_COUNT * sizeof(unsigned long long),
@@ -483,11 +532,17 @@ int solve(jsvd_handle_s *h, int64_t m, int64_t n, double *A, int64_t lda, double
         if (h->timing) {
             for (int s = 0; s < nsteps; s += h->timing_stride) {
                 hipEvent_t *ev = &h->events[(size_t)4 * s];
+                // interval k of a p-step and the kernel it timed: 0 Gram
+                // (none when fused, past the first p-step), 1 inner, 2 update
+                // or the fused update and Gram (3)
+                const bool fz = fused && s + 1 < nsteps;
+                const int kind[3] = {(fused && s > 0) ? -1 : 0, 1, fz ? 3 : 2};
                 for (int k = 0; k < 3; ++k) {
+                    if (kind[k] < 0) continue;
                     float ms = 0.f;
                     HIP_TRY(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
-                    h->kernel_ms[k] += ms;
-                    h->launches[k] += 1;
+                    h->kernel_ms[kind[k]] += ms;
+                    h->launches[kind[k]] += 1;
                 }
             }
         }
@@ -1078,6 +1133,7 @@ int check_opts(const jsvd_opts &o) {
     if (o.qr < 0 || o.qr > 2) return -1;
     if (o.scaled < 0 || o.scaled > 2) return -1;
     if (o.factorize < 0 || o.factorize > 1) return -1;
+    if (o.fuse < 0 || o.fuse > 1) return -1;
     return JSVD_OK;
 }
 
@@ -1173,6 +1229,8 @@ int jsvd_destroy(jsvd_handle_t h) {
     for (void *p : h->bws_retired) (void)hipFree(p);
     for (auto &kv : h->block_tables) (void)hipFree(kv.second.ptr);
     for (auto &kv : h->inner_tables) (void)hipFree(kv.second.ptr);
+    for (auto &kv : h->quad_tables)
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     if (h->batch_tables) (void)hipFree(h->batch_tables);
     if (h->batch_meta) (void)hipFree(h->batch_meta);
     if (h->host_counters) (void)hipHostFree(h->host_counters);
@@ -1324,6 +1382,17 @@ int jsvd_inner_table(int32_t order, int32_t kind, int32_t *pairs) {
             pairs[k++] = pr.first + 1;
             pairs[k++] = pr.second + 1;
         }
+    return JSVD_OK;
+}
+
+int jsvd_quad_table(int32_t order, int32_t kind, int32_t *quads) {
+    if (kind < JSVD_STRAT_RREV || kind > JSVD_STRAT_RR) return -2;
+    if (!quads) return -3;
+    Table t;
+    if (!make_table(order, kind, t)) return -1;
+    std::vector<int> flat;
+    if (!make_quads(t, flat)) return 1;
+    std::copy(flat.begin(), flat.end(), quads);
     return JSVD_OK;
 }
 
@@ -1527,7 +1596,7 @@ int jsvd_kernel_timing(jsvd_handle_t h, int enable) {
     if (enable < 0) return -2;
     h->timing = enable != 0;
     h->timing_stride = enable > 0 ? enable : 1;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         h->kernel_ms[k] = 0.0;
         h->launches[k] = 0;
     }
@@ -1538,7 +1607,7 @@ int jsvd_kernel_times(jsvd_handle_t h, double *ms, int64_t *launches) {
     if (!h) return -1;
     if (!ms) return -2;
     if (!launches) return -3;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         ms[k] = h->kernel_ms[k];
         launches[k] = h->launches[k];
     }
@@ -1597,9 +1666,13 @@ int jsvd_workspace_size(jsvd_handle_t h, int64_t m, int64_t n, const jsvd_opts *
         auto bytes_at = [&](int w) {
             const int order = strategy_order((int)((nn + w - 1) / w));
             int64_t rps = 0;
-            const int tgt = split_target(h, o, shp, mm, order / 2, 2 * w);
-            const int splits = gram_splits(mm, order / 2, tgt, &rps);
-            return plan(mm, nn, 2 * w, order / 2, splits, hsvd).total;
+            size_t bytes = 0;
+            for (int fused = 0; fused < 2; ++fused) {  // the fused path may split more
+                const int tgt = split_target(h, o, shp, mm, order / 2, 2 * w, fused != 0);
+                const int splits = gram_splits(mm, order / 2, tgt, &rps);
+                bytes = std::max(bytes, plan(mm, nn, 2 * w, order / 2, splits, hsvd).total);
+            }
+            return bytes;
         };
         // w = 64 falls back to 32 for the hyperbolic SVD and the scaled mode
         if (shp.w == 64) return hsvd ? bytes_at(32) : std::max(bytes_at(64), bytes_at(32));

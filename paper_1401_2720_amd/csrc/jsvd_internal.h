@@ -22,6 +22,13 @@ bool make_table(int order, int kind, Table &out);
 // the pairs of each step reordered for conflict-free LDS access in the inner
 // kernels (a permutation within each step; the steps and pairs unchanged)
 void order_for_banks(Table &t);
+// The step-to-step groups of a strategy table whose consecutive steps
+// exchange partners inside groups of two pairs, (a0 a1), (b0 b1) -> pairs of
+// {a0, a1} x {b0, b1}: per step s < order - 2 and group, 8 ints {ia, ib, jx,
+// jy, a0, b0, 0, 0} (old pairs' indices in step s, new pairs' in step s + 1,
+// the blocks of ia and ib that pair jx holds).  False when some step has no
+// such structure.
+bool make_quads(const Table &t, std::vector<int> &out);
 
 // ------------------------------------------------------------------ counters
 // Per-sweep device counters (unsigned 64-bit), reset at the start of a sweep.
@@ -85,12 +92,18 @@ struct StepArgs {
     const int *btbl_order;
     const int64_t *btbl_off;
     const unsigned char *btbls;
+    // the update fused with the next p-step's Gram kernel: the quads of this
+    // p-step (8 ints each: old pairs ia, ib, new pairs jx, jy, blocks a0 of
+    // ia and b0 of ib that go to jx, two unused) and the next p-step's pairs
+    const int *quads;
+    const int2 *next_pairs;
 };
 
 hipError_t launch_gram(int bw, const StepArgs &a, hipStream_t s);
 hipError_t launch_qrfac(int bw, const StepArgs &a, hipStream_t s);
 hipError_t launch_inner(int bw, const StepArgs &a, hipStream_t s);
 hipError_t launch_update(int bw, const StepArgs &a, hipStream_t s);
+hipError_t launch_fused(int nquads, const StepArgs &a, hipStream_t s);
 
 // ------------------------------------------------------ batched small SVDs
 constexpr int kBatchMaxN = 256;  // largest n of a problem in the batched path

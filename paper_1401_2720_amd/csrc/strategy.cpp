@@ -312,4 +312,36 @@ void order_for_banks(Table &t) {
     }
 }
 
+bool make_quads(const Table &t, std::vector<int> &out) {
+    out.clear();
+    if (t.size() < 2) return false;
+    const int np = (int)t[0].size();
+    std::vector<int> owner(2 * np, -1);
+    for (size_t s = 0; s + 1 < t.size(); ++s) {
+        const Step &cur = t[s], &nxt = t[s + 1];
+        if ((int)cur.size() != np || (int)nxt.size() != np) return false;
+        for (int i = 0; i < np; ++i) owner[cur[i].first] = owner[cur[i].second] = i;
+        std::vector<char> done(np, 0);
+        for (int j = 0; j < np; ++j) {
+            const int ia = owner[nxt[j].first], ib = owner[nxt[j].second];
+            if (ia == ib || ia < 0 || ib < 0) return false;
+            if (done[j]) continue;
+            // the other new pair of the group must take the other two blocks
+            const int a0 = nxt[j].first, b0 = nxt[j].second;
+            const int a1 = cur[ia].first == a0 ? cur[ia].second : cur[ia].first;
+            const int b1 = cur[ib].first == b0 ? cur[ib].second : cur[ib].first;
+            int jy = -1;
+            for (int k = 0; k < np; ++k)
+                if ((nxt[k].first == a1 && nxt[k].second == b1) ||
+                    (nxt[k].first == b1 && nxt[k].second == a1))
+                    jy = k;
+            if (jy < 0 || jy == j) return false;
+            done[j] = done[jy] = 1;
+            const int q[8] = {ia, ib, j, jy, a0, b0, 0, 0};
+            out.insert(out.end(), q, q + 8);
+        }
+    }
+    return true;
+}
+
 }  // namespace jsvd

@@ -6,7 +6,7 @@
 
 ``traffic`` reads two ``rocprofv3 --pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
 counter collections of the same program, averages the counters (KiB per
-dispatch) of the Gram, inner and update kernels, and converts them to HBM
+dispatch) of the Gram, inner, update and fused update-and-Gram kernels, and converts them to HBM
 bytes with the factors that the same counters give for a device copy of
 known size inside the program (torch's copy of the input matrix,
 ``__amd_rocclr_copyBufferRectAligned``, ``--calib-bytes`` read and written).
@@ -35,12 +35,14 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 COMMON = ["jsvd_device.h", "jsvd_internal.h"]
 KERNEL_SOURCES = {"gram": ["jsvd_gram.hip"],
                   "inner": ["jsvd_inner.hip", "jsvd_rows.h", "jsvd_blocked.h", "jsvd_qrpair.h"],
-                  "update": ["jsvd_update.hip", "jsvd_rows.h"]}
-PSTEP = re.compile(r"\b(gram|inner|update)_kernel<(\d+)(?:, (?:true|false))*>")
+                  "update": ["jsvd_update.hip", "jsvd_rows.h"],
+                  "fused": ["jsvd_fused.hip"]}
+PSTEP = re.compile(r"\b(gram|inner|update|fused)_kernel<(\d+)(?:, (?:true|false))*>")
 
 
 def kernel_sources_sha256(kernel):
-    """SHA-256 over the sources of one p-step kernel ('gram', 'inner', 'update')."""
+    """SHA-256 over the sources of one p-step kernel ('gram', 'inner', 'update',
+    'fused')."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES[kernel] + COMMON:
         with open(os.path.join(CSRC, name), "rb") as f:

@@ -143,6 +143,65 @@ def test_inner_table_is_the_strategy_reordered_within_steps(order, kind):
     assert L.jsvd_inner_table(32, 0, None) == -3
 
 
+@pytest.mark.parametrize("kind", ["rrev", "r", "crev", "c", "rr"])
+@pytest.mark.parametrize("order", [4, 8, 16, 32, 64, 128, 256, 12, 24, 96])
+def test_quad_table_groups_follow_the_strategy_table(order, kind):
+    """The groups of the fused update-and-Gram launch, checked against the
+    strategy table by brute force: in every p-step s < order - 2 each pair of
+    step s and each pair of step s + 1 lies in exactly one group; a group's
+    old pairs ia, ib of step s hold the blocks a0, a1 and b0, b1; its new
+    pairs jx, jy of step s + 1 are {a0, b0} and {a1, b1} in either order.
+    The Mantharam-Eberlein orderings have such groups for a power-of-two
+    number of blocks; round robin (from order 8) and the orders made by
+    expansion from 3, 5, ... 2^k do not, and the table says so."""
+    t = jsvd._binding.strategy_table(order, kind) - 1
+    got = jsvd._binding.quad_table(order, kind)
+
+    def has_groups():
+        for s in range(order - 2):
+            where = {}
+            for i, (p, q) in enumerate(t[s]):
+                where[p] = where[q] = i
+            for p, q in t[s + 1]:
+                if where[p] == where[q]:
+                    return False
+            # the two new pairs fed by an old pair must be fed by the same two
+            feeds = {}
+            for j, (p, q) in enumerate(t[s + 1]):
+                key = frozenset((where[p], where[q]))
+                feeds.setdefault(key, []).append(j)
+            if any(len(v) != 2 for v in feeds.values()):
+                return False
+        return True
+
+    expect = has_groups()
+    assert (got is not None) == expect
+    pow2 = order & (order - 1) == 0
+    if kind != "rr" and pow2:
+        assert expect
+    if not pow2:
+        assert not expect
+    if got is None:
+        return
+    assert got.shape == (order - 2, order // 4, 8)
+    for s in range(order - 2):
+        old_seen, new_seen = set(), set()
+        for ia, ib, jx, jy, a0, b0, z0, z1 in got[s]:
+            assert z0 == 0 and z1 == 0
+            pa, pb = set(t[s][ia]), set(t[s][ib])
+            assert a0 in pa and b0 in pb
+            (a1,), (b1,) = pa - {a0}, pb - {b0}
+            assert set(t[s + 1][jx]) == {a0, b0} and set(t[s + 1][jy]) == {a1, b1}
+            old_seen |= {ia, ib}
+            new_seen |= {jx, jy}
+        assert old_seen == set(range(order // 2)) and new_seen == set(range(order // 2))
+    L = jsvd.lib()
+    buf = np.zeros(8, np.int32)
+    assert L.jsvd_quad_table(order, 9, buf.ctypes.data) == -2
+    assert L.jsvd_quad_table(order, 0, None) == -3
+    assert L.jsvd_quad_table(26, 0, buf.ctypes.data) == -1
+
+
 def test_workspace_and_diagnostic_calls_validate_arguments():
     """The workspace queries, the reservation and the refined-arithmetic
     diagnostic reject a NULL handle before touching a device, and the status
