@@ -1667,7 +1667,9 @@ int jsvd_workspace_size(jsvd_handle_t h, int64_t m, int64_t n, const jsvd_opts *
             const int order = strategy_order((int)((nn + w - 1) / w));
             int64_t rps = 0;
             size_t bytes = 0;
-            for (int fused = 0; fused < 2; ++fused) {  // the fused path may split more
+            // the fused update-and-Gram path (opts.fuse, 2w = 64) may split more
+            const int fuse_max = (o.fuse && w == 32) ? 1 : 0;
+            for (int fused = 0; fused <= fuse_max; ++fused) {
                 const int tgt = split_target(h, o, shp, mm, order / 2, 2 * w, fused != 0);
                 const int splits = gram_splits(mm, order / 2, tgt, &rps);
                 bytes = std::max(bytes, plan(mm, nn, 2 * w, order / 2, splits, hsvd).total);
