@@ -17,8 +17,9 @@ namespace jsvd {
 
 namespace {
 
-// 16-row slices of rows [r0, r1), one quad, 2w = 64.  RA / RB: old pair A /
-// B rotated (else its columns pass through unchanged and are not stored).
+// 16-row slices of rows [r0, r1), one quad, 2w = 64, the waves of phase
+// 0..3 taking rows r0 + 16 phase + 64 i.  RA / RB: old pair A / B rotated
+// (else its columns pass through unchanged and are not stored).
 // The wave's role is one of the two canonical new pairs, X' = [a0 b0] (role
 // 0) or Y' = [a1 b1] (role 1); its four register tiles d[0..3] are the two
 // 16-column tiles of its block of A, then the two of its block of B, and it
@@ -45,7 +46,8 @@ __device__ __forceinline__ void fused_slices(const StepArgs &a, int64_t r0, int6
     // row i16 of pair column 4k + grp, k < 8 in the first block); a pair
     // passing through as this role's two tiles (x[4u + v] = row grp + 4v of
     // column 16u + i16 of its block).  Every slice is whole: the host takes
-    // this path only when the splits' row counts are multiples of 32.
+    // this path only when m, and so every split's row count, is a multiple
+    // of 64, and lda <= 2^25 (the byte offsets stay below 2^32).
     const uint32_t off_op = (uint32_t)((grp * a.ldg + i16) * 8);   // operand layout
     const uint32_t off_t = (uint32_t)((i16 * a.ldg + grp) * 8);    // tile layout
     auto at = [](const double *sb, uint32_t off) {
