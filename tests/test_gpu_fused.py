@@ -177,3 +177,27 @@ def test_fused_not_taken_where_it_does_not_apply():
         U, S, V, info, la = _run(A, fuse=True, **kw)
         assert info["status"] == 0, (m, n, kw)
         assert la["fused"] == 0 and la["gram"] > info["sweeps"], (m, n, kw, la)
+
+
+def test_fused_4096_against_golden_sigma():
+    """The benchmark matrix (4096 x 4096 N(0,1), seed 2) in the configuration
+    that bench.py --fuse times (w = 32, Rrev, 8 row splits): every sigma
+    against the oracle's golden values (tests/golden/, written by the
+    oracle), at the bars of the full-size tests, and the fused launch at all
+    p-steps but the first and last of each sweep."""
+    import os
+    _say("fused 4096 x 4096 N(0,1) against the golden sigma")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "sigma_gaussian4096_seed2.txt")
+    ref = np.loadtxt(path, comments="#")
+    A = inputs.square_gaussian()
+    U, S, V, info, la = _run(A, fuse=True)
+    assert info["status"] == 0 and info["converged"] == 1 and info["block_w"] == 32, info
+    _fused_ran(la, info, 127)
+    err = np.abs(S - ref)
+    assert np.all(err <= 1e-12 * ref + 1e-13 * ref.max()), float(np.max(err / ref))
+    big = ref >= 1e-3 * ref.max()
+    rel = float(np.max(err[big] / ref[big]))
+    assert rel <= 1e-12, rel
+    assert np.max(np.abs(V.T @ V - np.eye(4096))) <= 1e-13 * 4096
+    _say(f"  max rel sigma err {rel:.2e}, sweeps {info['sweeps']}")
